@@ -1,0 +1,189 @@
+/*
+ * sem.h -- C ABI of libsem: the spectral-element pressure-solve hot path on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The method (paper, section 3.1 "Neko"): the domain is split into E
+ * non-overlapping hexahedral elements carrying order-N polynomials on the
+ * Gauss-Lobatto-Legendre (GLL) points; operators are applied element by
+ * element without assembling a matrix; the elements are coupled only by a
+ * unit-depth gather-scatter; each time step solves A x = b with a
+ * preconditioned Krylov method.  The spectral-element definitions are the
+ * textbook ones the paper cites (Deville, Fischer & Mund 2002).
+ *
+ * Conventions shared by every entry point
+ *  - Meshes are structured boxes of nelx*nely*nelz hexahedra given by their
+ *    vertex lattice.  Element e = ex + nelx*(ey + nely*ez).
+ *  - A "local" field is a contiguous device array [E][N+1][N+1][N+1] with the
+ *    last index (i, the r direction) fastest: one value per element node.
+ *    Shared nodes appear once per element that holds them.
+ *  - Device pointers are plain HIP device addresses (e.g. torch tensors'
+ *    data_ptr()); host pointers are marked HOST.  The library never frees or
+ *    reallocates caller memory.  Streams are hipStream_t passed as void*
+ *    (NULL = the null stream).  Calls marked "async" only enqueue work.
+ *  - Every function returns a sem_status and never throws; on failure
+ *    sem_last_error() describes the problem (thread-local string, valid until
+ *    the next call on the same thread).
+ *  - The library allocates device memory only in sem_mesh_create and
+ *    sem_smoother_create; hot calls allocate nothing.  Concurrent calls on one
+ *    mesh are safe when their output buffers are distinct.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SEM_OK = 0,
+    SEM_ERR_INVALID_ARG = 1,   /* null pointer, bad size/dtype/order, inverted element */
+    SEM_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
+    SEM_ERR_HIP = 3,           /* a HIP runtime call failed */
+    SEM_ERR_NOT_CONVERGED = 4, /* max_iter reached; x holds the last iterate */
+    SEM_ERR_BREAKDOWN = 5,     /* non-finite value or (p, S p) <= 0 in CG */
+    SEM_ERR_UNSUPPORTED = 6    /* valid request this build does not provide */
+} sem_status;
+
+typedef enum { SEM_F64 = 0, SEM_F32 = 1, SEM_BF16 = 2 } sem_dtype;
+
+typedef struct sem_mesh sem_mesh;           /* opaque, immutable after create */
+typedef struct sem_smoother sem_smoother;   /* opaque learned smoother */
+
+/* Low-precision copies of the geometric factors built at mesh creation. */
+#define SEM_PREP_F32 1u
+#define SEM_PREP_BF16 2u
+
+typedef struct {
+    int32_t nelx, nely, nelz;   /* elements per direction, each >= 1 */
+    int32_t order;              /* polynomial order N, 1..15 */
+    const double *vertices;     /* HOST [(nelz+1)][(nely+1)][(nelx+1)][3]; copied */
+    uint8_t periodic[3];        /* x, y, z: the last vertex plane is the periodic
+                                   image of the first (nodes identified) */
+    uint8_t dirichlet_faces;    /* bits 0..5 = x-,x+,y-,y+,z-,z+: homogeneous
+                                   Dirichlet (ignored in periodic directions) */
+    uint8_t prepare;            /* SEM_PREP_* bits */
+} sem_mesh_desc;
+
+typedef struct {
+    int64_t nelem;              /* E */
+    int64_t n_local;            /* E (N+1)^3 */
+    int64_t n_global;           /* unique nodes */
+    int64_t n_shared_global;    /* unique nodes with more than one copy */
+    int64_t n_shared_local;     /* local copies of those nodes */
+    int64_t n_masked_global;    /* unique nodes on Dirichlet faces */
+    int32_t order;
+    int32_t npts_elem;          /* (N+1)^3 */
+    size_t device_bytes;        /* device memory held by the mesh */
+} sem_mesh_info;
+
+/* Fields for sem_mesh_export (host copies, canonical layouts). */
+enum {
+    SEM_FIELD_GLO_NUM = 0,  /* int64  [E][p]    global node id, lexicographic (z, y, x) */
+    SEM_FIELD_MULT = 1,     /* int32  [E][p]    number of copies of the node */
+    SEM_FIELD_MASK = 2,     /* uint8  [E][p]    1 on Dirichlet nodes */
+    SEM_FIELD_G = 3,        /* double [6][E][p] G11 G12 G13 G22 G23 G33 (with W detJ) */
+    SEM_FIELD_B = 4,        /* double [E][p]    mass W detJ */
+    SEM_FIELD_XYZ = 5,      /* double [3][E][p] node coordinates */
+    SEM_FIELD_GLL = 6,      /* double [2][N+1]  GLL nodes, then weights */
+    SEM_FIELD_DERIV = 7     /* double [N+1][N+1] D[i][j] = l_j'(xi_i) */
+};
+
+/* Host setup (GLL rule, trilinear geometry, geometric factors, numbering,
+ * gather-scatter lists) and upload to the current HIP device.  Fails with
+ * SEM_ERR_INVALID_ARG if any element has detJ <= 0 at a GLL node. */
+sem_status sem_mesh_create(const sem_mesh_desc *desc, sem_mesh **out);
+sem_status sem_mesh_destroy(sem_mesh *mesh);
+sem_status sem_mesh_query(const sem_mesh *mesh, sem_mesh_info *out);
+/* Copy one field to HOST memory; `bytes` must equal the field's size. */
+sem_status sem_mesh_export(const sem_mesh *mesh, int field, void *host_dst, size_t bytes);
+
+/* Local operator (async), element by element, unassembled:
+ *   w_e = h1 * sum_{a,b} D_a^T (G_ab o D_b u_e) + h2 * B o u_e
+ * with D_r, D_s, D_t the GLL derivative along r, s, t (Deville et al. 2002,
+ * sec. 4.4; the paper's element-by-element operator of section 3.1).
+ * in = SEM_F64: u, w double.  in = SEM_F32: u, w float (needs SEM_PREP_F32).
+ * in = SEM_BF16: u bf16 (uint16 bit patterns), w float, contractions on the
+ * matrix cores with fp32 accumulation (needs SEM_PREP_BF16). */
+sem_status sem_ax(const sem_mesh *mesh, double h1, double h2, sem_dtype in,
+                  const void *u, void *w, void *stream);
+
+/* Direct-stiffness summation in place (async): every copy of a global node
+ * receives the sum of all its copies (the gather-scatter of section 3.1);
+ * with apply_mask != 0 the Dirichlet nodes are then zeroed.  dt = SEM_F64
+ * (double) or SEM_F32 (float).  The sum runs over copies in ascending local
+ * index, so repeated calls are bitwise reproducible. */
+sem_status sem_dssum(const sem_mesh *mesh, sem_dtype dt, void *u, int apply_mask, void *stream);
+
+/* Right-hand side (async): b = mask(dssum(B o f)); f, b local double. */
+sem_status sem_rhs(const sem_mesh *mesh, const double *f, double *b, void *stream);
+
+/* Inverse of the assembled Jacobi diagonal (async): d = mask(dssum(diag A_L)),
+ * with d = 1 on Dirichlet nodes; writes 1/d to dinv (local double). */
+sem_status sem_jacobi(const sem_mesh *mesh, double h1, double h2, double *dinv, void *stream);
+
+/* Inner product of two continuous local fields with each global node counted
+ * once, sum_l u_l v_l / mult_l (async); the double result is written to the
+ * DEVICE address `result`.  Deterministic summation order. */
+sem_status sem_dot(const sem_mesh *mesh, const double *u, const double *v, double *result,
+                   void *stream);
+
+/* Solver forms. */
+typedef enum {
+    SEM_FORM_JACOBI_PCG = 0,     /* FP64 Jacobi-preconditioned CG */
+    SEM_FORM_DC_FP32 = 1,        /* FP64 defect correction around FP32 Jacobi-PCG */
+    SEM_FORM_DC_BF16 = 2,        /* FP64 defect correction around BF16-operator PCG */
+    SEM_FORM_FCG_LEARNED = 3,    /* flexible CG with the learned smoother */
+    SEM_FORM_FCG_LEARNED_DC_F32 = 4 /* learned FCG, FP32 operator, FP64 refinement */
+} sem_form;
+
+typedef struct {
+    double h1, h2;              /* Helmholtz coefficients (Poisson: 1, 0) */
+    double rel_tol;             /* stop when ||r|| <= rel_tol ||b|| (e.g. 1e-10) */
+    int32_t max_iter;           /* cap on operator applications (all levels) */
+    int32_t check_every;        /* iterations between host polls of the flag */
+    int32_t form;               /* sem_form */
+    int32_t max_outer;          /* defect-correction outer steps (DC forms) */
+    double inner_tol;           /* inner relative tolerance (DC forms) */
+    const sem_smoother *smoother; /* learned forms */
+    double *history;            /* HOST, optional: relative residual per iteration */
+    int32_t history_len;        /* capacity of history */
+} sem_solve_opts;
+
+typedef struct {
+    int32_t status;             /* sem_status of the solve */
+    int32_t iterations;         /* operator applications in the Krylov loop(s) */
+    int32_t outer_iterations;   /* defect-correction steps (DC forms), else 0 */
+    int32_t restarts;           /* true-residual restarts */
+    int32_t fallback_used;      /* learned forms: 1 if Jacobi-PCG took over */
+    int32_t history_written;
+    double rel_res;             /* final recursive relative residual */
+    double true_rel_res;        /* ||b - S x|| / ||b|| in FP64 */
+    double elapsed_ms;          /* wall time of the solve */
+} sem_solve_report;
+
+/* Device workspace the solve needs, in bytes. */
+sem_status sem_solve_workspace_bytes(const sem_mesh *mesh, const sem_solve_opts *opts,
+                                     size_t *bytes);
+
+/* Solve S x = b, S = mask o dssum o A_L (blocking: returns after the true
+ * residual has been checked).  b is a continuous, masked local field; x
+ * receives the solution (x starts from zero).  Jacobi-PCG is Hestenes &
+ * Stiefel CG with z = dinv o r; after the recursive residual meets rel_tol
+ * the true residual is evaluated and CG restarts from x (at most 3 times)
+ * while it does not.  workspace: device, >= sem_solve_workspace_bytes. */
+sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const double *b,
+                         double *x, void *workspace, size_t ws_bytes, sem_solve_report *rep,
+                         void *stream);
+
+const char *sem_last_error(void);
+
+/* Library version string, e.g. "sem 0.1 gfx950". */
+const char *sem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEM_H */

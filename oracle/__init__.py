@@ -181,6 +181,15 @@ class Mesh:
         lib().ora_ax(self.E, self.N, _p(self.D), _p(self.G), _p(self.B), h1, h2, _p(u), _p(w))
         return w
 
+    def ax_abs_bound(self, u, h1=1.0, h2=0.0):
+        """The local operator with |D|, |G|, |B| and |u|: the magnitude that
+        bounds rounding errors of any evaluation order of A_L u."""
+        u = np.abs(_c(u, np.float64).reshape(self.shape))
+        Da, Ga, Ba = np.abs(self.D), np.abs(self.G), np.abs(self.B)
+        w = np.zeros(self.shape)
+        lib().ora_ax(self.E, self.N, _p(Da), _p(Ga), _p(Ba), abs(h1), abs(h2), _p(u), _p(w))
+        return w
+
     def dssum(self, u):
         """Direct-stiffness summation (returns a new array)."""
         v = _c(u, np.float64).reshape(self.shape).copy()

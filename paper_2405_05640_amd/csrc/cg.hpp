@@ -1,0 +1,46 @@
+// cg.hpp -- internal interface of the assembled-vector Krylov kernels.
+#pragma once
+
+#include "sem_internal.hpp"
+
+namespace sem {
+
+constexpr int kBS = 256;             // threads per block of the vector kernels
+constexpr int kMaxVecBlocks = 4096;  // grid cap (partials buffers are sized for it)
+
+// Device-resident scalars of one CG run.
+struct CgState {
+    double rz, pw, rr, bb, alpha, beta, tol2, true_rr;
+    int32_t it, done, status, max_it;
+    int32_t hist_len, pad0, pad1, pad2;
+};
+// done: 0 running, 1 converged (recursive residual), 2 breakdown, 3 max_iter
+
+// Vectors of one CG run: x, r, p, dinv are assembled (n_global); w is local
+// (n_local, the unassembled operator output); part_e has n_elem entries,
+// part_b 2 * kMaxVecBlocks.
+template <typename T>
+struct CgVecs {
+    T *x, *r, *p, *dinv, *w;
+    double *part_e, *part_b;
+};
+
+int cg_blocks(int64_t n);
+
+template <typename T> hipError_t cg_gather(const Mesh &m, const double *u, T *ug, hipStream_t s);
+template <typename T> hipError_t cg_scatter(const Mesh &m, const T *ug, double *u, hipStream_t s);
+template <typename T> hipError_t cg_dinv(const Mesh &m, const double *diag_local, T *dinv, hipStream_t s);
+template <typename T>
+hipError_t cg_init(const Mesh &m, const CgVecs<T> &v, const T *b, CgState *st, double tol, double *hist, hipStream_t s);
+// after the operator has written v.w = A_L p and v.part_e = per-element p.w:
+// alpha, update (with assembly), beta / convergence test, p update
+template <typename T>
+hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, double *hist, hipStream_t s);
+// r = b - Q^T v.w (Dirichlet nodes 0), st->true_rr = (r, r)
+template <typename T>
+hipError_t cg_resid(const Mesh &m, const CgVecs<T> &v, const T *b, T *r, CgState *st, hipStream_t s);
+template <typename T> hipError_t cg_restart(const Mesh &m, const CgVecs<T> &v, CgState *st, hipStream_t s);
+template <typename T> hipError_t cg_axpy(const Mesh &m, double *y, const T *d, double scale, hipStream_t s);
+template <typename T> hipError_t cg_scale(const Mesh &m, const double *in, T *out, double scale, hipStream_t s);
+
+}  // namespace sem

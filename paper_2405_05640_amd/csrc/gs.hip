@@ -1,0 +1,161 @@
+// gs.hip -- gather-scatter (direct-stiffness summation), mask, and the small
+// vector kernels behind sem_rhs / sem_jacobi / sem_dot.
+//
+// The gather-scatter is the only coupling between elements (paper section
+// 3.1) and the part the paper's section 4.2 identifies as the communication
+// bottleneck.  On one GPU it is an owner-computes pass over the unique nodes
+// that have more than one copy: one thread per such node enumerates its
+// copies in closed form (no index arrays are read), sums them in ascending
+// local index and writes the sum back to every copy.  Interior nodes (a
+// single copy) are never touched.
+//
+// Thread layout: one wavefront per run of 64 consecutive global nodes of a
+// lattice row (gj, gk).  In a row on an element face plane every node is
+// shared and the wave walks contiguous element rows; in any other row only
+// the x-face nodes (gi = m N) are shared and the wave takes 64 consecutive
+// x-faces, so lanes m and m+1 hit the two ends of the same 64-byte element
+// row.  Every element row is therefore fetched once per pass.
+#include "lattice.hpp"
+#include "sem_internal.hpp"
+
+namespace sem {
+namespace {
+
+template <typename T, int MASK>
+__global__ void __launch_bounds__(64)
+gs_kernel(T *__restrict__ u, Lattice L, int64_t xblocks, const int32_t *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    const int64_t b = blockIdx.x;
+    const int64_t row = b / xblocks;
+    const int64_t q = (b - row * xblocks) * 64 + threadIdx.x;
+    const int64_t gj = row % L.ny, gk = row / L.ny;
+    int64_t gi;
+    if (gj % L.N == 0 || gk % L.N == 0) {
+        if (q >= L.nx) return;
+        gi = q;
+    } else {
+        if (q >= (L.per[0] ? L.nelx : L.nelx + 1)) return;
+        gi = q * L.N;
+    }
+    int64_t loc[8];
+    const int n = lattice_locals(L, gi, gj, gk, loc);
+    const bool msk = MASK && lattice_masked(L, gi, gj, gk);
+    if (n == 1 && !msk) return;
+    T s = T(0);
+    if (!msk)
+        for (int c = 0; c < n; ++c) s += u[loc[c]];
+    for (int c = 0; c < n; ++c) u[loc[c]] = s;
+}
+
+__global__ void scale_by_B_kernel(const double *__restrict__ f, const double *__restrict__ Bm,
+                                  double *__restrict__ b, int64_t nl)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < nl) b[l] = Bm[l] * f[l];
+}
+
+// d <- 1/d on free nodes, 1 on Dirichlet nodes (wcode == 0)
+__global__ void jacobi_finish_kernel(double *__restrict__ d, const uint8_t *__restrict__ wcode,
+                                     int64_t nl)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < nl) d[l] = wcode[l] == 0 ? 1.0 : 1.0 / d[l];
+}
+
+constexpr int kDotBlock = 256;
+constexpr int kDotMaxBlocks = 2048;
+
+// partial[b] = sum over a grid-stride range of u v / mult, fixed order
+__global__ void __launch_bounds__(kDotBlock)
+dot_partial_kernel(const double *__restrict__ u, const double *__restrict__ v,
+                   const uint8_t *__restrict__ mult, int64_t nl, double *__restrict__ partial)
+{
+    __shared__ double red[kDotBlock];
+    double s = 0.0;
+    for (int64_t l = (int64_t)blockIdx.x * kDotBlock + threadIdx.x; l < nl;
+         l += (int64_t)gridDim.x * kDotBlock)
+        s += u[l] * v[l] / (double)mult[l];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kDotBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kDotBlock)
+sum_partials_kernel(const double *__restrict__ partial, int n, double *__restrict__ out)
+{
+    __shared__ double red[kDotBlock];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < n; q += kDotBlock) s += partial[q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kDotBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename T>
+hipError_t dssum_impl(const Mesh &m, T *u, int apply_mask, hipStream_t s, const int32_t *skip)
+{
+    const Lattice &L = m.lat;
+    const int64_t xblocks = (L.nx + 63) / 64;
+    const int64_t nblocks = xblocks * L.ny * L.nz;
+    if (nblocks == 0) return hipSuccess;
+    if (apply_mask)
+        hipLaunchKernelGGL((gs_kernel<T, 1>), dim3((unsigned)nblocks), dim3(64), 0, s, u, L, xblocks, skip);
+    else
+        hipLaunchKernelGGL((gs_kernel<T, 0>), dim3((unsigned)nblocks), dim3(64), 0, s, u, L, xblocks, skip);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_dssum_f64(const Mesh &m, double *u, int apply_mask, hipStream_t s,
+                           const int32_t *skip)
+{
+    return dssum_impl<double>(m, u, apply_mask, s, skip);
+}
+
+hipError_t launch_dssum_f32(const Mesh &m, float *u, int apply_mask, hipStream_t s,
+                           const int32_t *skip)
+{
+    return dssum_impl<float>(m, u, apply_mask, s, skip);
+}
+
+hipError_t launch_scale_by_B(const Mesh &m, const double *f, double *b, hipStream_t s)
+{
+    if (m.nl == 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_by_B_kernel, dim3(blocks_for(m.nl, 256)), dim3(256), 0, s, f, m.d_B, b, m.nl);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_finish(const Mesh &m, double *d, hipStream_t s)
+{
+    if (m.nl == 0) return hipSuccess;
+    hipLaunchKernelGGL(jacobi_finish_kernel, dim3(blocks_for(m.nl, 256)), dim3(256), 0, s, d, m.d_wcode, m.nl);
+    return hipGetLastError();
+}
+
+int dot_blocks(const Mesh &m)
+{
+    const int64_t b = (m.nl + kDotBlock - 1) / kDotBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, kDotMaxBlocks));
+}
+
+hipError_t launch_dot(const Mesh &m, const double *u, const double *v, double *partials,
+                      int nblocks, double *result, hipStream_t s)
+{
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(nblocks), dim3(kDotBlock), 0, s, u, v, m.d_mult, m.nl, partials);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kDotBlock), 0, s, partials, nblocks, result);
+    return hipGetLastError();
+}
+
+}  // namespace sem

@@ -1,0 +1,107 @@
+// lattice.hpp -- closed-form structure of a box of hexahedral spectral
+// elements (device and host).
+//
+// Global node (gi, gj, gk), gi in [0, nx): the lexicographic numbering
+// glo = gi + nx (gj + ny gk) with gi = ex N + i (mod nx in a periodic
+// direction).  A node with gi a multiple of N lies on an element face and has
+// one local copy on each side (two in total, or one on a non-periodic domain
+// boundary).  Its copies across the three directions form a tensor product
+// of up to 2 x 2 x 2 (element, local index) pairs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sem {
+
+struct Lattice {
+    int nelx, nely, nelz, N, NP;
+    int64_t nx, ny, nz;   // global nodes per direction
+    int64_t P;            // (N+1)^3
+    uint8_t per[3];
+    uint8_t dir;          // Dirichlet bits x-, x+, y-, y+, z-, z+
+};
+
+// Copies of a global index g along one direction, ascending in (element, local).
+// Returns the count (1 or 2); ec = element coordinate, lc = local coordinate.
+__host__ __device__ inline int lattice_copies(int64_t g, int nel, int N, bool per, int ec[2], int lc[2])
+{
+    const int64_t m = g / N;
+    const int r = (int)(g - m * N);
+    if (r != 0) {
+        ec[0] = (int)m;
+        lc[0] = r;
+        return 1;
+    }
+    if (per) {
+        if (m == 0) {
+            ec[0] = 0; lc[0] = 0;
+            ec[1] = nel - 1; lc[1] = N;   // equals (0, N) when nel == 1
+            return 2;
+        }
+        ec[0] = (int)m - 1; lc[0] = N;
+        ec[1] = (int)m; lc[1] = 0;
+        return 2;
+    }
+    if (m == 0) { ec[0] = 0; lc[0] = 0; return 1; }
+    if (m == nel) { ec[0] = nel - 1; lc[0] = N; return 1; }
+    ec[0] = (int)m - 1; lc[0] = N;
+    ec[1] = (int)m; lc[1] = 0;
+    return 2;
+}
+
+__host__ __device__ inline bool lattice_masked(const Lattice &L, int64_t gi, int64_t gj, int64_t gk)
+{
+    const int64_t g[3] = {gi, gj, gk};
+    const int nel[3] = {L.nelx, L.nely, L.nelz};
+    for (int d = 0; d < 3; ++d) {
+        if (L.per[d]) continue;
+        if (g[d] == 0 && ((L.dir >> (2 * d)) & 1)) return true;
+        if (g[d] == (int64_t)nel[d] * L.N && ((L.dir >> (2 * d + 1)) & 1)) return true;
+    }
+    return false;
+}
+
+// All local indices of global node (gi, gj, gk), sorted ascending.  Returns
+// the number of copies (1..8).
+__host__ __device__ inline int lattice_locals(const Lattice &L, int64_t gi, int64_t gj, int64_t gk,
+                                              int64_t loc[8])
+{
+    int ex[2], ix[2], ey[2], iy[2], ez[2], iz[2];
+    const int cx = lattice_copies(gi, L.nelx, L.N, L.per[0], ex, ix);
+    const int cy = lattice_copies(gj, L.nely, L.N, L.per[1], ey, iy);
+    const int cz = lattice_copies(gk, L.nelz, L.N, L.per[2], ez, iz);
+    int n = 0;
+    for (int c = 0; c < cz; ++c)
+        for (int b = 0; b < cy; ++b)
+            for (int a = 0; a < cx; ++a) {
+                const int64_t e = ex[a] + (int64_t)L.nelx * (ey[b] + (int64_t)L.nely * ez[c]);
+                loc[n++] = e * L.P + ix[a] + L.NP * (iy[b] + (int64_t)L.NP * iz[c]);
+            }
+    // insertion sort (the enumeration is already ascending except in
+    // periodic directions with a single element)
+    for (int q = 1; q < n; ++q) {
+        const int64_t v = loc[q];
+        int r = q - 1;
+        while (r >= 0 && loc[r] > v) {
+            loc[r + 1] = loc[r];
+            --r;
+        }
+        loc[r + 1] = v;
+    }
+    return n;
+}
+
+// Global id of local node (e, i, j, k).
+__host__ __device__ inline int64_t lattice_glo(const Lattice &L, int64_t e, int i, int j, int k)
+{
+    const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);
+    int64_t gi = ex * L.N + i, gj = ey * L.N + j, gk = ez * L.N + k;
+    if (gi >= L.nx) gi -= L.nx;
+    if (gj >= L.ny) gj -= L.ny;
+    if (gk >= L.nz) gk -= L.nz;
+    return gi + L.nx * (gj + L.ny * gk);
+}
+
+}  // namespace sem

@@ -1,0 +1,361 @@
+// solve.hip -- Jacobi-preconditioned conjugate gradients on S = mask o dssum o A_L
+// (the paper's preconditioned Krylov solve of Ax = b, section 3.1; CG after
+// Hestenes & Stiefel 1952 with point-Jacobi z = dinv o r), plus the small
+// operator entry points of the C ABI.
+//
+// Iteration (all scalars stay on the device; the host only polls a flag):
+//   1. w = A_L p                  ax kernel, fused per-element partial of p.w
+//   2. w = dssum(w)               gather-scatter
+//   3. alpha = rz / (p, w)        one-block finalize (deterministic tree)
+//   4. x += alpha p, r -= alpha w fused update, block partials of (r,r), (r,z)
+//   5. convergence test, beta     one-block finalize
+//   6. p = dinv r + beta p
+// For a continuous p that is zero on Dirichlet nodes, (p, S p) equals the
+// unassembled sum p.(A_L p), so step 1 yields the denominator before the
+// gather-scatter.  The preconditioner is stored with zeros on Dirichlet
+// nodes and the inner-product weights 1/mult are zero there too, so no mask
+// pass is needed inside the loop: p, x stay zero on those nodes and r's
+// values there never enter a sum.
+// solve.hip -- the solve drivers (paper section 3.1: a preconditioned Krylov
+// solve of Ax = b every time step) and the operator entry points of the C ABI.
+//
+// FP64 Jacobi-PCG (Hestenes & Stiefel 1952; z = dinv o r) on assembled
+// vectors, one iteration =
+//   1. w = A_L p          operator, p read through the numbering, per-element
+//                         partial of p.w (= (p, S p) for a continuous p)
+//   2. alpha = rz / pw    one-block finalize
+//   3. Q^T w, x += a p, r -= a Q^T w, partials of (r,r), (r,z)
+//   4. beta, convergence test (one block);  5. p = dinv r + beta p.
+// The host only polls the device convergence flag every check_every
+// iterations; kernels queued after convergence exit at once.
+//
+// FP32 defect correction (Wilkinson-style iterative refinement): the FP64
+// true residual r = b - S x is scaled to unit norm, rounded to FP32, an FP32
+// PCG on the FP32 operator solves S d = r to inner_tol, and x += |r| d in
+// FP64.  FP64 is kept for the outer residual, every inner product and the
+// convergence tests.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "cg.hpp"
+#include "sem_internal.hpp"
+
+#define SEM_TRY(x)                   \
+    do {                             \
+        sem_status _s = (x);         \
+        if (_s != SEM_OK) return _s; \
+    } while (0)
+
+namespace sem {
+namespace {
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Workspace {
+    CgVecs<double> v64;      // x, r, p, dinv (assembled), w (local)
+    double *b64;             // assembled right-hand side
+    CgVecs<float> v32;       // inner FP32 vectors (DC form)
+    float *b32;
+    CgState *st64, *st32;
+    double *hist;
+    size_t bytes;
+};
+
+bool uses_f32(int form) { return form == SEM_FORM_DC_FP32; }
+
+Workspace carve(const Mesh &m, int form, int hist_len, char *base)
+{
+    Workspace ws{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    const size_t nl = (size_t)m.nl, ng = (size_t)m.ng;
+    ws.v64.x = (double *)take(ng * 8);
+    ws.v64.r = (double *)take(ng * 8);
+    ws.v64.p = (double *)take(ng * 8);
+    ws.v64.dinv = (double *)take(ng * 8);
+    ws.b64 = (double *)take(ng * 8);
+    ws.v64.w = (double *)take(nl * 8);
+    ws.v64.part_e = (double *)take((size_t)std::max<int64_t>(m.E, 1) * 8);
+    ws.v64.part_b = (double *)take((size_t)kMaxVecBlocks * 2 * 8);
+    ws.st64 = (CgState *)take(sizeof(CgState));
+    ws.st32 = (CgState *)take(sizeof(CgState));
+    ws.hist = (double *)take((size_t)std::max(hist_len, 1) * 8);
+    if (uses_f32(form)) {
+        ws.v32.x = (float *)take(ng * 4);
+        ws.v32.r = (float *)take(ng * 4);
+        ws.v32.p = (float *)take(ng * 4);
+        ws.v32.dinv = (float *)take(ng * 4);
+        ws.b32 = (float *)take(ng * 4);
+        ws.v32.w = (float *)take(nl * 4);
+        ws.v32.part_e = ws.v64.part_e;
+        ws.v32.part_b = ws.v64.part_b;
+    }
+    ws.bytes = off;
+    return ws;
+}
+
+int hist_len_for(const sem_solve_opts &o) { return o.max_iter + 1; }
+
+sem_status check_opts(const Mesh &m, const sem_solve_opts *o)
+{
+    if (!o) return fail(SEM_ERR_INVALID_ARG, "null opts");
+    if (o->max_iter < 1) return fail(SEM_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if (!(o->rel_tol > 0.0) || !std::isfinite(o->rel_tol))
+        return fail(SEM_ERR_INVALID_ARG, "rel_tol must be a positive finite number");
+    if (!std::isfinite(o->h1) || !std::isfinite(o->h2)) return fail(SEM_ERR_INVALID_ARG, "non-finite h1/h2");
+    switch (o->form) {
+    case SEM_FORM_JACOBI_PCG:
+        return SEM_OK;
+    case SEM_FORM_DC_FP32:
+        if (!m.d_G32) return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_DC_FP32 needs a mesh created with SEM_PREP_F32");
+        if (!(o->inner_tol > 0.0 && o->inner_tol < 1.0))
+            return fail(SEM_ERR_INVALID_ARG, "inner_tol must be in (0, 1)");
+        if (o->max_outer < 1) return fail(SEM_ERR_INVALID_ARG, "max_outer must be >= 1");
+        return SEM_OK;
+    default:
+        return fail(SEM_ERR_UNSUPPORTED, "solver form " + std::to_string(o->form) + " not available");
+    }
+}
+
+sem_status read_state(CgState &h, const CgState *d, hipStream_t s)
+{
+    SEM_HIP_TRY(hipMemcpyAsync(&h, d, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    SEM_HIP_TRY(hipStreamSynchronize(s));
+    return SEM_OK;
+}
+
+sem_status reset_state(CgState *d, int max_it, int hist_len, hipStream_t s)
+{
+    CgState init{};
+    init.max_it = max_it;
+    init.hist_len = hist_len;
+    SEM_HIP_TRY(hipMemcpyAsync(d, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
+    return SEM_OK;
+}
+
+// Iterate until the device flag says done; returns the final host state.
+template <typename T>
+sem_status iterate(const Mesh &m, double h1, double h2, const CgVecs<T> &v, CgState *st, double *hist,
+                   int check_every, hipStream_t s, CgState &h)
+{
+    for (;;) {
+        SEM_TRY(read_state(h, st, s));
+        if (h.done) return SEM_OK;
+        for (int q = 0; q < check_every; ++q) {
+            if constexpr (sizeof(T) == 8)
+                SEM_HIP_TRY(launch_ax_f64_gather(m, h1, h2, v.p, v.w, v.part_e, s, &st->done));
+            else
+                SEM_HIP_TRY(launch_ax_f32_gather(m, (float)h1, (float)h2, v.p, v.w, v.part_e, s, &st->done));
+            SEM_HIP_TRY(cg_step_after_ax<T>(m, v, st, hist, s));
+        }
+    }
+}
+
+// FP64 true residual of the assembled x: v.r = b - S x, returns (r, r) in h.true_rr
+sem_status true_residual(const Mesh &m, double h1, double h2, const Workspace &ws, hipStream_t s, CgState &h)
+{
+    SEM_HIP_TRY(launch_ax_f64_gather(m, h1, h2, ws.v64.x, ws.v64.w, nullptr, s));
+    SEM_HIP_TRY(cg_resid<double>(m, ws.v64, ws.b64, ws.v64.r, ws.st64, s));
+    return read_state(h, ws.st64, s);
+}
+
+sem_status solve_pcg64(const Mesh &m, const sem_solve_opts &o, const Workspace &ws, int hist_len, hipStream_t s,
+                       int check_every, sem_solve_report *rep, CgState &h)
+{
+    SEM_TRY(reset_state(ws.st64, o.max_iter, hist_len, s));
+    SEM_HIP_TRY(cg_init<double>(m, ws.v64, ws.b64, ws.st64, o.rel_tol, ws.hist, s));
+    int restarts = 0;
+    for (;;) {
+        SEM_TRY(iterate<double>(m, o.h1, o.h2, ws.v64, ws.st64, ws.hist, check_every, s, h));
+        if (h.done != 1 || h.bb == 0.0) break;
+        SEM_TRY(true_residual(m, o.h1, o.h2, ws, s, h));
+        if (h.true_rr <= h.tol2 || restarts == 3 || h.it >= h.max_it) break;
+        ++restarts;   // recursive residual drifted: restart CG from x
+        SEM_HIP_TRY(cg_restart<double>(m, ws.v64, ws.st64, s));
+    }
+    if (h.done != 1 && h.bb > 0.0) SEM_TRY(true_residual(m, o.h1, o.h2, ws, s, h));
+    rep->iterations = h.it;
+    rep->restarts = restarts;
+    return SEM_OK;
+}
+
+sem_status solve_dc32(const Mesh &m, const sem_solve_opts &o, const Workspace &ws, int hist_len, hipStream_t s,
+                      int check_every, sem_solve_report *rep, CgState &h)
+{
+    // (b, b) and tol2 through the FP64 init (x = 0, r = b)
+    SEM_TRY(reset_state(ws.st64, o.max_iter, hist_len, s));
+    SEM_HIP_TRY(cg_init<double>(m, ws.v64, ws.b64, ws.st64, o.rel_tol, ws.hist, s));
+    SEM_TRY(read_state(h, ws.st64, s));
+    if (h.bb == 0.0) return SEM_OK;
+    CgState hi{};
+    int total = 0, outer = 0;
+    double prev = h.bb;
+    h.true_rr = h.bb;
+    h.done = 0;
+    while (outer < o.max_outer) {
+        if (outer > 0) {
+            SEM_TRY(true_residual(m, o.h1, o.h2, ws, s, h));
+            if (h.true_rr <= h.tol2) { h.done = 1; break; }
+            if (!(h.true_rr < prev)) { h.done = 2; break; }   // refinement stalled
+            prev = h.true_rr;
+        } else {
+            // first outer step: r = b, already in v64.r
+        }
+        if (total >= o.max_iter) { h.done = 3; break; }
+        const double rn = std::sqrt(h.true_rr);
+        SEM_HIP_TRY(cg_scale<float>(m, ws.v64.r, ws.b32, 1.0 / rn, s));
+        SEM_TRY(reset_state(ws.st32, o.max_iter - total, 0, s));
+        SEM_HIP_TRY(cg_init<float>(m, ws.v32, ws.b32, ws.st32, o.inner_tol, nullptr, s));
+        SEM_TRY(iterate<float>(m, o.h1, o.h2, ws.v32, ws.st32, nullptr, check_every, s, hi));
+        total += hi.it;
+        SEM_HIP_TRY(cg_axpy<float>(m, ws.v64.x, ws.v32.x, rn, s));
+        ++outer;
+    }
+    if (h.done == 0) {
+        SEM_TRY(true_residual(m, o.h1, o.h2, ws, s, h));
+        h.done = h.true_rr <= h.tol2 ? 1 : 3;
+    }
+    h.rr = h.true_rr;
+    h.it = total;
+    rep->iterations = total;
+    rep->outer_iterations = outer;
+    return SEM_OK;
+}
+
+}  // namespace
+}  // namespace sem
+
+using namespace sem;
+
+extern "C" {
+
+sem_status sem_ax(const sem_mesh *mesh, double h1, double h2, sem_dtype in, const void *u, void *w,
+                  void *stream)
+{
+    if (!mesh || !u || !w) return fail(SEM_ERR_INVALID_ARG, "null mesh, u or w");
+    const Mesh &m = mesh->m;
+    hipStream_t s = (hipStream_t)stream;
+    switch (in) {
+    case SEM_F64:
+        SEM_HIP_TRY(launch_ax_f64(m, h1, h2, (const double *)u, (double *)w, nullptr, s));
+        return SEM_OK;
+    case SEM_F32:
+        if (!m.d_G32) return fail(SEM_ERR_INVALID_ARG, "mesh was created without SEM_PREP_F32");
+        SEM_HIP_TRY(launch_ax_f32(m, (float)h1, (float)h2, (const float *)u, (float *)w, nullptr, s));
+        return SEM_OK;
+    case SEM_BF16:
+        return fail(SEM_ERR_UNSUPPORTED, "bf16 operator not available in this build");
+    default:
+        return fail(SEM_ERR_INVALID_ARG, "unknown dtype");
+    }
+}
+
+sem_status sem_dssum(const sem_mesh *mesh, sem_dtype dt, void *u, int apply_mask, void *stream)
+{
+    if (!mesh || !u) return fail(SEM_ERR_INVALID_ARG, "null mesh or u");
+    hipStream_t s = (hipStream_t)stream;
+    if (dt == SEM_F64) {
+        SEM_HIP_TRY(launch_dssum_f64(mesh->m, (double *)u, apply_mask, s));
+        return SEM_OK;
+    }
+    if (dt == SEM_F32) {
+        SEM_HIP_TRY(launch_dssum_f32(mesh->m, (float *)u, apply_mask, s));
+        return SEM_OK;
+    }
+    return fail(SEM_ERR_INVALID_ARG, "dssum supports SEM_F64 and SEM_F32");
+}
+
+sem_status sem_rhs(const sem_mesh *mesh, const double *f, double *b, void *stream)
+{
+    if (!mesh || !f || !b) return fail(SEM_ERR_INVALID_ARG, "null mesh, f or b");
+    hipStream_t s = (hipStream_t)stream;
+    SEM_HIP_TRY(launch_scale_by_B(mesh->m, f, b, s));
+    SEM_HIP_TRY(launch_dssum_f64(mesh->m, b, 1, s));
+    return SEM_OK;
+}
+
+sem_status sem_jacobi(const sem_mesh *mesh, double h1, double h2, double *dinv, void *stream)
+{
+    if (!mesh || !dinv) return fail(SEM_ERR_INVALID_ARG, "null mesh or dinv");
+    hipStream_t s = (hipStream_t)stream;
+    SEM_HIP_TRY(launch_diag(mesh->m, h1, h2, dinv, s));
+    SEM_HIP_TRY(launch_dssum_f64(mesh->m, dinv, 0, s));
+    SEM_HIP_TRY(launch_jacobi_finish(mesh->m, dinv, s));
+    return SEM_OK;
+}
+
+sem_status sem_dot(const sem_mesh *mesh, const double *u, const double *v, double *result, void *stream)
+{
+    if (!mesh || !u || !v || !result) return fail(SEM_ERR_INVALID_ARG, "null argument");
+    const Mesh &m = mesh->m;
+    SEM_HIP_TRY(launch_dot(m, u, v, m.d_scratch, m.scratch_len - 1, result, (hipStream_t)stream));
+    return SEM_OK;
+}
+
+sem_status sem_solve_workspace_bytes(const sem_mesh *mesh, const sem_solve_opts *opts, size_t *bytes)
+{
+    if (!mesh || !bytes) return fail(SEM_ERR_INVALID_ARG, "null mesh or bytes");
+    SEM_TRY(check_opts(mesh->m, opts));
+    *bytes = carve(mesh->m, opts->form, hist_len_for(*opts), nullptr).bytes;
+    return SEM_OK;
+}
+
+sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const double *b, double *x,
+                         void *workspace, size_t ws_bytes, sem_solve_report *rep, void *stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!mesh || !b || !x || !workspace || !rep) return fail(SEM_ERR_INVALID_ARG, "null argument");
+    const Mesh &m = mesh->m;
+    SEM_TRY(check_opts(m, opts));
+    std::memset(rep, 0, sizeof(*rep));
+    const int hist_len = hist_len_for(*opts);
+    Workspace ws = carve(m, opts->form, hist_len, (char *)workspace);
+    if (ws_bytes < ws.bytes)
+        return fail(SEM_ERR_INVALID_ARG, "workspace too small: need " + std::to_string(ws.bytes) + " bytes");
+    hipStream_t s = (hipStream_t)stream;
+    const int check_every = std::max(1, opts->check_every > 0 ? opts->check_every : 16);
+
+    // preconditioner (0 on Dirichlet nodes) and the assembled right-hand side
+    SEM_HIP_TRY(launch_diag(m, opts->h1, opts->h2, ws.v64.w, s));
+    SEM_HIP_TRY(cg_dinv<double>(m, ws.v64.w, ws.v64.dinv, s));
+    if (uses_f32(opts->form)) SEM_HIP_TRY(cg_dinv<float>(m, ws.v64.w, ws.v32.dinv, s));
+    SEM_HIP_TRY(cg_gather<double>(m, b, ws.b64, s));
+
+    CgState h{};
+    if (opts->form == SEM_FORM_DC_FP32)
+        SEM_TRY(solve_dc32(m, *opts, ws, hist_len, s, check_every, rep, h));
+    else
+        SEM_TRY(solve_pcg64(m, *opts, ws, hist_len, s, check_every, rep, h));
+    SEM_HIP_TRY(cg_scatter<double>(m, ws.v64.x, x, s));
+
+    rep->rel_res = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    rep->true_rel_res = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
+    if (opts->history && opts->history_len > 0 && opts->form == SEM_FORM_JACOBI_PCG) {
+        const int n = std::min(opts->history_len, std::min(h.it + 1, hist_len));
+        SEM_HIP_TRY(hipMemcpyAsync(opts->history, ws.hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        SEM_HIP_TRY(hipStreamSynchronize(s));
+        rep->history_written = n;
+    } else {
+        SEM_HIP_TRY(hipStreamSynchronize(s));
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    rep->elapsed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    if (h.done == 2) {
+        rep->status = SEM_ERR_BREAKDOWN;
+        return fail(SEM_ERR_BREAKDOWN, "CG breakdown: (p, S p) <= 0, non-finite value, or stalled refinement");
+    }
+    if (h.bb > 0.0 && !(h.true_rr <= h.tol2)) {
+        rep->status = SEM_ERR_NOT_CONVERGED;
+        return fail(SEM_ERR_NOT_CONVERGED, "relative residual above rel_tol after " +
+                                               std::to_string(rep->iterations) + " iterations");
+    }
+    rep->status = SEM_OK;
+    return SEM_OK;
+}
+
+}  // extern "C"

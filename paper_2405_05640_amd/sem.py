@@ -1,0 +1,292 @@
+"""Python binding of libsem (ctypes): argument marshalling only.
+
+Every computation runs in the HIP library; this module checks shapes, dtypes
+and devices on the host (so no kernel is launched on a buffer that does not
+match the mesh), passes raw device pointers and torch's current stream, and
+turns status codes into exceptions.  There is no fallback: if libsem.so is
+missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsem.so")
+
+SEM_OK, SEM_ERR_INVALID_ARG, SEM_ERR_OUT_OF_MEMORY, SEM_ERR_HIP, SEM_ERR_NOT_CONVERGED, \
+    SEM_ERR_BREAKDOWN, SEM_ERR_UNSUPPORTED = range(7)
+SEM_F64, SEM_F32, SEM_BF16 = 0, 1, 2
+SEM_PREP_F32, SEM_PREP_BF16 = 1, 2
+FIELD_GLO_NUM, FIELD_MULT, FIELD_MASK, FIELD_G, FIELD_B, FIELD_XYZ, FIELD_GLL, FIELD_DERIV = range(8)
+FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED, FORM_FCG_LEARNED_DC_F32 = range(5)
+
+EXPORTED_SYMBOLS = [
+    "sem_mesh_create", "sem_mesh_destroy", "sem_mesh_query", "sem_mesh_export", "sem_ax",
+    "sem_dssum", "sem_rhs", "sem_jacobi", "sem_dot", "sem_solve_workspace_bytes",
+    "sem_pcg_solve", "sem_last_error", "sem_version",
+]
+
+
+class SemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("libsem status %d: %s" % (status, msg))
+        self.status = status
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("nelx", ctypes.c_int32), ("nely", ctypes.c_int32), ("nelz", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("vertices", ctypes.POINTER(ctypes.c_double)),
+                ("periodic", ctypes.c_uint8 * 3), ("dirichlet_faces", ctypes.c_uint8),
+                ("prepare", ctypes.c_uint8)]
+
+
+class MeshInfo(ctypes.Structure):
+    _fields_ = [("nelem", ctypes.c_int64), ("n_local", ctypes.c_int64), ("n_global", ctypes.c_int64),
+                ("n_shared_global", ctypes.c_int64), ("n_shared_local", ctypes.c_int64),
+                ("n_masked_global", ctypes.c_int64), ("order", ctypes.c_int32),
+                ("npts_elem", ctypes.c_int32), ("device_bytes", ctypes.c_size_t)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("h1", ctypes.c_double), ("h2", ctypes.c_double), ("rel_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("smoother", ctypes.c_void_p),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int32)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("outer_iterations", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("fallback_used", ctypes.c_int32), ("history_written", ctypes.c_int32),
+                ("rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
+                ("elapsed_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsem.so (built by ``paper_2405_05640_amd.build``)."""
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime with the same soname as the one
+        # libsem links; importing torch first makes the dynamic loader bind
+        # libsem to that single runtime instance (device memory and streams
+        # then come from, and are used by, one runtime).
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsem.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_2405_05640_amd.build); there is no fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        sig = {
+            "sem_mesh_create": [ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)],
+            "sem_mesh_destroy": [vp],
+            "sem_mesh_query": [vp, ctypes.POINTER(MeshInfo)],
+            "sem_mesh_export": [vp, ctypes.c_int, vp, ctypes.c_size_t],
+            "sem_ax": [vp, dbl, dbl, ctypes.c_int, vp, vp, vp],
+            "sem_dssum": [vp, ctypes.c_int, vp, ctypes.c_int, vp],
+            "sem_rhs": [vp, vp, vp, vp],
+            "sem_jacobi": [vp, dbl, dbl, vp, vp],
+            "sem_dot": [vp, vp, vp, vp, vp],
+            "sem_solve_workspace_bytes": [vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(ctypes.c_size_t)],
+            "sem_pcg_solve": [vp, ctypes.POINTER(SolveOpts), vp, vp, vp, ctypes.c_size_t,
+                              ctypes.POINTER(SolveReport), vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.sem_last_error.restype = ctypes.c_char_p
+        L.sem_last_error.argtypes = []
+        L.sem_version.restype = ctypes.c_char_p
+        L.sem_version.argtypes = []
+        _check_single_hip_runtime()
+        _lib = L
+    return _lib
+
+
+def _check_single_hip_runtime():
+    """Fail loudly if two HIP runtimes ended up in this process."""
+    try:
+        maps = open("/proc/self/maps").read().split("\n")
+    except OSError:
+        return
+    paths = {ln.split()[-1] for ln in maps if "libamdhip64" in ln and "/" in ln}
+    real = {os.path.realpath(p) for p in paths}
+    if len(real) > 1:
+        raise RuntimeError("two HIP runtimes loaded in one process: %s" % sorted(real))
+
+
+def _check(st):
+    if st != SEM_OK:
+        raise SemError(st, lib().sem_last_error().decode())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_TORCH_DT = {}
+
+
+def _want(t, dtype_name, numel, what):
+    import torch
+    dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
+          "u16": torch.int16}[dtype_name]
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % what)
+    if not t.is_cuda:
+        raise ValueError("%s must be on a HIP device" % what)
+    if t.dtype != dt and not (dtype_name == "bf16" and t.dtype in (torch.int16, torch.uint16)):
+        raise ValueError("%s must have dtype %s, got %s" % (what, dt, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if t.numel() != numel:
+        raise ValueError("%s has %d elements, mesh needs %d" % (what, t.numel(), numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Report:
+    status: int
+    iterations: int
+    outer_iterations: int
+    restarts: int
+    fallback_used: int
+    rel_res: float
+    true_rel_res: float
+    elapsed_ms: float
+    history: np.ndarray | None = None
+
+
+class Mesh:
+    """A device-resident spectral-element mesh (``sem_mesh``)."""
+
+    def __init__(self, nelx, nely, nelz, order, vertices, periodic=(0, 0, 0), dirichlet=0x3F,
+                 prepare=0):
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        if v.shape != (nelz + 1, nely + 1, nelx + 1, 3):
+            raise ValueError("vertices must have shape (nelz+1, nely+1, nelx+1, 3)")
+        self._vert = v
+        d = MeshDesc(nelx, nely, nelz, order, v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                     (ctypes.c_uint8 * 3)(*[1 if p else 0 for p in periodic]), dirichlet, prepare)
+        h = ctypes.c_void_p()
+        _check(lib().sem_mesh_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        info = MeshInfo()
+        _check(lib().sem_mesh_query(h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in MeshInfo._fields_}
+        self.nelx, self.nely, self.nelz, self.order = nelx, nely, nelz, order
+        self.E = info.nelem
+        self.n_local = info.n_local
+        self.n_global = info.n_global
+        self.shape = (self.E, order + 1, order + 1, order + 1)
+
+    @classmethod
+    def from_spec(cls, spec, prepare=0):
+        return cls(spec.nelx, spec.nely, spec.nelz, spec.order, spec.vertices, spec.periodic,
+                   spec.dirichlet, prepare)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sem_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ export
+    def export(self, field):
+        n, nl = self.order + 1, self.n_local
+        spec = {FIELD_GLO_NUM: (np.int64, (self.E, n, n, n)), FIELD_MULT: (np.int32, (self.E, n, n, n)),
+                FIELD_MASK: (np.uint8, (self.E, n, n, n)), FIELD_G: (np.float64, (6, self.E, n, n, n)),
+                FIELD_B: (np.float64, (self.E, n, n, n)), FIELD_XYZ: (np.float64, (3, self.E, n, n, n)),
+                FIELD_GLL: (np.float64, (2, n)), FIELD_DERIV: (np.float64, (n, n))}[field]
+        out = np.zeros(spec[1], dtype=spec[0])
+        _check(lib().sem_mesh_export(self._h, field, out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
+        return out
+
+    # ------------------------------------------------------------ ops
+    def ax(self, u, w, h1=1.0, h2=0.0, dtype=SEM_F64):
+        name = {SEM_F64: ("f64", "f64"), SEM_F32: ("f32", "f32"), SEM_BF16: ("bf16", "f32")}[dtype]
+        pu = _want(u, name[0], self.n_local, "u")
+        pw = _want(w, name[1], self.n_local, "w")
+        _check(lib().sem_ax(self._h, float(h1), float(h2), dtype, pu, pw, _stream()))
+        return w
+
+    def dssum(self, u, mask=False, dtype=SEM_F64):
+        pu = _want(u, "f64" if dtype == SEM_F64 else "f32", self.n_local, "u")
+        _check(lib().sem_dssum(self._h, dtype, pu, 1 if mask else 0, _stream()))
+        return u
+
+    def rhs(self, f, b):
+        _check(lib().sem_rhs(self._h, _want(f, "f64", self.n_local, "f"),
+                             _want(b, "f64", self.n_local, "b"), _stream()))
+        return b
+
+    def jacobi(self, dinv, h1=1.0, h2=0.0):
+        _check(lib().sem_jacobi(self._h, float(h1), float(h2), _want(dinv, "f64", self.n_local, "dinv"),
+                                _stream()))
+        return dinv
+
+    def dot(self, u, v, out):
+        _check(lib().sem_dot(self._h, _want(u, "f64", self.n_local, "u"), _want(v, "f64", self.n_local, "v"),
+                             _want(out, "f64", 1, "out"), _stream()))
+        return out
+
+    def solve_opts(self, h1=1.0, h2=0.0, rel_tol=1e-10, max_iter=20000, check_every=16,
+                   form=FORM_JACOBI_PCG, max_outer=30, inner_tol=1e-4, smoother=None, history=None):
+        o = SolveOpts()
+        o.h1, o.h2, o.rel_tol, o.max_iter, o.check_every = h1, h2, rel_tol, max_iter, check_every
+        o.form, o.max_outer, o.inner_tol = form, max_outer, inner_tol
+        o.smoother = smoother._h if smoother is not None else None
+        if history is not None:
+            o.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            o.history_len = len(history)
+        return o
+
+    def workspace_bytes(self, opts):
+        n = ctypes.c_size_t()
+        _check(lib().sem_solve_workspace_bytes(self._h, ctypes.byref(opts), ctypes.byref(n)))
+        return n.value
+
+    def workspace(self, opts):
+        import torch
+        nb = self.workspace_bytes(opts)
+        return torch.empty(nb, dtype=torch.uint8, device="cuda")
+
+    def pcg_solve(self, b, x, workspace=None, raise_on_error=True, history=False, **kw):
+        import torch
+        hist = np.zeros(kw.get("max_iter", 20000) + 1) if history else None
+        opts = self.solve_opts(history=hist, **kw)
+        if workspace is None:
+            workspace = self.workspace(opts)
+        need = self.workspace_bytes(opts)
+        if not (isinstance(workspace, torch.Tensor) and workspace.is_cuda and workspace.is_contiguous()):
+            raise ValueError("workspace must be a contiguous device tensor")
+        if workspace.numel() * workspace.element_size() < need:
+            raise ValueError("workspace too small")
+        rep = SolveReport()
+        st = lib().sem_pcg_solve(self._h, ctypes.byref(opts), _want(b, "f64", self.n_local, "b"),
+                                 _want(x, "f64", self.n_local, "x"), ctypes.c_void_p(workspace.data_ptr()),
+                                 workspace.numel() * workspace.element_size(), ctypes.byref(rep), _stream())
+        r = Report(rep.status, rep.iterations, rep.outer_iterations, rep.restarts, rep.fallback_used,
+                   rep.rel_res, rep.true_rel_res, rep.elapsed_ms,
+                   hist[: rep.history_written].copy() if hist is not None else None)
+        if st != SEM_OK and raise_on_error:
+            raise SemError(st, lib().sem_last_error().decode())
+        return r
+
+
+def version():
+    return lib().sem_version().decode()

@@ -1,0 +1,133 @@
+"""Pins for the oracle's learned smoother: convolution against brute force
+and a delta-kernel closed form, adjoint identities, finite-difference
+gradients of the A-norm loss, positive homogeneity, the zero network being
+Jacobi, and flexible CG (= Jacobi-PCG for the zero network, fallback paths)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cnn
+from paper_2405_05640_amd import workloads as wl
+from tests import brute
+
+
+def _mesh(spec):
+    return oracle.Mesh(spec.nelx, spec.nely, spec.nelz, spec.order, spec.vertices,
+                       spec.periodic, spec.dirichlet)
+
+
+def test_conv3d_brute_force():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((2, 3, 4, 4, 4))
+    W = rng.standard_normal((5, 3, 3, 3, 3))
+    out = cnn.conv3d(x, W)
+    ref = np.zeros_like(out)
+    n = 4
+    for e, o, k, j, i in itertools.product(range(2), range(5), range(n), range(n), range(n)):
+        s = 0.0
+        for c, a, b, d in itertools.product(range(3), range(3), range(3), range(3)):
+            kk, jj, ii = k + a - 1, j + b - 1, i + d - 1
+            if 0 <= kk < n and 0 <= jj < n and 0 <= ii < n:
+                s += W[o, c, a, b, d] * x[e, c, kk, jj, ii]
+        ref[e, o, k, j, i] = s
+    assert np.max(np.abs(out - ref)) < 1e-12
+
+
+def test_delta_kernel_is_channel_mixing():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((3, 2, 8, 8, 8))
+    W = np.zeros((4, 2, 3, 3, 3))
+    M = rng.standard_normal((4, 2))
+    W[:, :, 1, 1, 1] = M
+    assert np.allclose(cnn.conv3d(x, W), np.einsum("oc,ecxyz->eoxyz", M, x), rtol=0, atol=1e-14)
+
+
+def test_conv_adjoints():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((2, 3, 5, 5, 5))
+    W = rng.standard_normal((4, 3, 3, 3, 3))
+    g = rng.standard_normal((2, 4, 5, 5, 5))
+    lhs = np.sum(cnn.conv3d(x, W) * g)
+    assert abs(lhs - np.sum(x * cnn.conv3d_grad_input(g, W))) < 1e-10 * abs(lhs)
+    assert abs(lhs - np.sum(W * cnn.conv3d_grad_weight(x, g))) < 1e-10 * abs(lhs)
+
+
+def _pair(m, rng, h2=0.0):
+    e = brute.continuous_random(m, rng)
+    r = m.apply_S(e, 1.0, h2)
+    return r, e
+
+
+def test_zero_net_is_jacobi_and_homogeneity():
+    m = _mesh(wl.deformed_cube(2, 7, amp=0.2))
+    rng = np.random.default_rng(3)
+    r, _ = _pair(m, rng)
+    dinv = m.jacobi_inv()
+    z0 = cnn.smoother(m, cnn.Net.init(16, seed=0), r, dinv)
+    assert np.array_equal(z0, dinv * r)
+    net = cnn.Net.init(16, seed=1)
+    net.W[2] = rng.standard_normal(net.W[2].shape) * 0.05
+    z = cnn.smoother(m, net, r, dinv)
+    assert np.array_equal(cnn.smoother(m, net, 2.0 * r, dinv), 2.0 * z)
+    assert np.array_equal(cnn.smoother(m, net, 0.25 * r, dinv), 0.25 * z)
+    # continuity and mask of the smoother output
+    assert np.array_equal(z, m.gather_global(z)[m.glo])
+    assert np.all(z[m.mask == 1] == 0)
+
+
+@pytest.mark.parametrize("h2", [0.0, 0.1])
+def test_loss_gradient_matches_finite_differences(h2):
+    m = _mesh(wl.deformed_cube(2, 7, amp=0.2))
+    rng = np.random.default_rng(4)
+    net = cnn.Net.init(4, seed=2)
+    net.W[2] = rng.standard_normal(net.W[2].shape) * 0.1
+    r, e = _pair(m, rng, h2)
+    dinv = m.jacobi_inv(1.0, h2)
+    L, grads = cnn.loss_and_grad(m, net, r, e, dinv, 1.0, h2)
+    assert 0 < L
+    h = 1e-6
+    picks = [(0, (1, 0, 1, 1, 1)), (0, (3, 1, 0, 2, 1)), (1, (2, 3, 1, 1, 0)), (1, (0, 0, 2, 2, 2)),
+             (2, (0, 1, 1, 1, 1)), (2, (0, 3, 0, 1, 2))]
+    for layer, idx in picks:
+        W0 = net.W[layer][idx]
+        net.W[layer][idx] = W0 + h
+        Lp, _ = cnn.loss_and_grad(m, net, r, e, dinv, 1.0, h2)
+        net.W[layer][idx] = W0 - h
+        Lm, _ = cnn.loss_and_grad(m, net, r, e, dinv, 1.0, h2)
+        net.W[layer][idx] = W0
+        fd = (Lp - Lm) / (2 * h)
+        g = grads[layer][idx]
+        assert abs(fd - g) <= 1e-6 * max(abs(g), 1e-3 * np.max(np.abs(grads[layer]))), (layer, idx, fd, g)
+
+
+def test_fcg_zero_net_equals_pcg():
+    m = _mesh(wl.deformed_cube(3, 5, amp=0.2))
+    rng = np.random.default_rng(5)
+    b = m.rhs(rng.standard_normal(m.shape))
+    x, info = cnn.fcg(m, cnn.Net.init(16, seed=0), b, 1.0, 0.1)
+    xo, io = m.pcg(b, 1.0, 0.1)
+    assert abs(info["iterations"] - io["iterations"]) <= 2
+    r = b - m.apply_S(x, 1.0, 0.1)
+    assert np.sqrt(m.dot(r, r) / m.dot(b, b)) <= 1.05e-10
+
+
+def test_fcg_fallback_paths_converge():
+    m = _mesh(wl.deformed_cube(3, 5, amp=0.2))
+    rng = np.random.default_rng(6)
+    b = m.rhs(rng.standard_normal(m.shape))
+    net = cnn.Net.init(8, seed=3)
+    net.W[2] = rng.standard_normal(net.W[2].shape) * 0.05
+    for kw in ({}, {"force_fallback_at": 7}):
+        x, info = cnn.fcg(m, net, b, 1.0, 0.0, **kw)
+        r = b - m.apply_S(x, 1.0, 0.0)
+        assert np.sqrt(m.dot(r, r) / m.dot(b, b)) <= 1.05e-10
+        if kw:
+            assert info["fallback_at"] == 7
+    bad = cnn.Net.init(8, seed=3)
+    bad.W[2][:] = np.nan
+    x, info = cnn.fcg(m, bad, b, 1.0, 0.0)
+    assert info["fallback_at"] == 0
+    r = b - m.apply_S(x, 1.0, 0.0)
+    assert np.sqrt(m.dot(r, r) / m.dot(b, b)) <= 1.05e-10
