@@ -135,8 +135,8 @@ typedef enum {
     SEM_FORM_JACOBI_PCG = 0,     /* FP64 Jacobi-preconditioned CG */
     SEM_FORM_DC_FP32 = 1,        /* FP64 defect correction around FP32 Jacobi-PCG */
     SEM_FORM_DC_BF16 = 2,        /* FP64 defect correction around BF16-operator PCG */
-    SEM_FORM_FCG_LEARNED = 3,    /* flexible CG with the learned smoother */
-    SEM_FORM_FCG_LEARNED_DC_F32 = 4 /* learned FCG, FP32 operator, FP64 refinement */
+    SEM_FORM_FCG_LEARNED = 3     /* flexible CG with the learned smoother (opts.smoother),
+                                    Jacobi-PCG fallback */
 } sem_form;
 
 typedef struct {
@@ -177,6 +177,58 @@ sem_status sem_solve_workspace_bytes(const sem_mesh *mesh, const sem_solve_opts 
 sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const double *b,
                          double *x, void *workspace, size_t ws_bytes, sem_solve_report *rep,
                          void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned smoother (not in the paper; this library's accelerated form).
+ * Per element e of an N = 7 mesh, with q = dinv o r, s_e = max|r_e|,
+ * t_e = max|q_e|: X_e = [r_e / s_e, q_e / t_e] (2 channels on the 8^3 tile),
+ * Net = conv(16->1) o relu o conv(16->16) o relu o conv(2->16), 3x3x3
+ * cross-correlations with zero padding and no bias, c_e = t_e Net(X_e), and
+ *     M(r) = dinv o r + mask(Q^T (c / mult)).
+ * A zero last layer gives Jacobi; M(a r) = a M(r) for a > 0.  Weights:
+ * W1[16][2][27] | W2[16][16][27] | W3[16][27] (tap = 9 (dk+1) + 3 (dj+1) + di+1),
+ * 8208 floats, FP32 master copy; inference runs layer 2 in BF16 on the matrix
+ * cores with FP32 accumulation, training runs in FP32.
+ * Training loss of a pair (r = S e, e): L = |e - M(r)|_S^2 / |e|_S^2, Adam. */
+typedef struct {
+    uint32_t seed;            /* He-normal init of layers 1-2; layer 3 starts at zero */
+    float lr, beta1, beta2, eps;  /* Adam (0 = defaults 1e-3, 0.9, 0.999, 1e-8) */
+    int32_t stall_window;     /* flexible-CG stall window (0 = 25 iterations) */
+    double stall_rate;        /* per-iteration residual reduction of plain Jacobi-PCG on the same
+                                 problem; a window reducing less than rate^window switches to
+                                 Jacobi-PCG.  0 disables the stall test. */
+} sem_smoother_desc;
+
+#define SEM_SMOOTHER_PARAMS 8208
+
+/* Allocates weights, Adam moments and training buffers sized for `mesh`. */
+sem_status sem_smoother_create(const sem_mesh *mesh, const sem_smoother_desc *desc, sem_smoother **out);
+sem_status sem_smoother_destroy(sem_smoother *sm);
+/* HOST float[n], n = SEM_SMOOTHER_PARAMS; set also resets the Adam state. */
+sem_status sem_smoother_set_weights(sem_smoother *sm, const float *host, size_t n);
+sem_status sem_smoother_get_weights(const sem_smoother *sm, float *host, size_t n);
+/* z = M(r) for a continuous, masked local r (device double [E][P]); fp32 != 0
+ * runs the FP32 network, else the BF16 inference path.  Blocking on stream. */
+sem_status sem_smoother_apply(const sem_smoother *sm, const sem_mesh *mesh, double h1, double h2, int fp32,
+                              const double *r_local, double *z_local, void *stream);
+/* Loss L and dL/dW (FP32 path) for one error field e (continuous, masked local
+ * double); loss and gradient are written to HOST memory.  Blocking. */
+sem_status sem_smoother_loss_grad(sem_smoother *sm, const sem_mesh *mesh, double h1, double h2,
+                                  const double *e_local, double *loss_host, float *grad_host, void *stream);
+/* One Adam step on the pair (S e, e); e_global: device float[n_global] in the
+ * lexicographic global numbering (as written by sem_pcg_snapshots).  The loss
+ * before the step is copied to the DEVICE double *loss_dev (may be NULL). Async. */
+sem_status sem_smoother_train_step(sem_smoother *sm, const sem_mesh *mesh, double h1, double h2,
+                                   const float *e_global, double *loss_dev, void *stream);
+
+/* Training pairs from plain FP64 Jacobi-PCG on S x = b (x from zero): for
+ * each iteration count iters[q] (HOST, ascending) the error e_q = x* - x_{iters[q]}
+ * of that iterate against the converged solution x* is written to
+ * e_out[q][n_global] (DEVICE double, lexicographic global numbering); counts
+ * past convergence give e_q = 0.  opts as for sem_pcg_solve (form ignored). */
+sem_status sem_pcg_snapshots(const sem_mesh *mesh, const sem_solve_opts *opts, const double *b,
+                             const int32_t *iters, int32_t n_iters, double *e_out, void *workspace,
+                             size_t ws_bytes, sem_solve_report *rep, void *stream);
 
 const char *sem_last_error(void);
 

@@ -29,15 +29,17 @@ __device__ __forceinline__ void g_to_ijk(const Lattice &L, int64_t g, int64_t &g
 }
 
 template <typename T>
-__device__ __forceinline__ double assemble_at(const Lattice &L, const T *__restrict__ w, int64_t g)
+__device__ __forceinline__ double assemble_at(const Lattice &L, const T *__restrict__ w, int gi, int gj, int gk,
+                                              bool &masked)
 {
-    int64_t gi, gj, gk, loc[8];
-    g_to_ijk(L, g, gi, gj, gk);
-    const int n = lattice_locals(L, gi, gj, gk, loc);
+    int loc[8];
+    const int n = node_locals(L, gi, gj, gk, loc, masked);
     T s = T(0);
     for (int c = 0; c < n; ++c) s += w[loc[c]];
     return (double)s;
 }
+
+inline unsigned node_blocks(const Lattice &L) { return (unsigned)std::min<int64_t>(L.ny * L.nz, kMaxVecBlocks); }
 
 template <int NV>
 __device__ __forceinline__ void block_store(double (&v)[NV], double *out, int stride)
@@ -81,13 +83,13 @@ __device__ double block_sum(const double *__restrict__ a, int64_t n)
 
 // ug[g] = u at the first copy of g (u continuous)
 template <typename Tin, typename Tout>
-__global__ void __launch_bounds__(kBS) gather_kernel(const Tin *__restrict__ u, Tout *__restrict__ ug, Lattice L, int64_t ng)
+__global__ void __launch_bounds__(kBS) gather_kernel(const Tin *__restrict__ u, Tout *__restrict__ ug, Lattice L)
 {
-    GRID_STRIDE(g, ng)
+    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
     {
-        int64_t gi, gj, gk, loc[8];
-        g_to_ijk(L, g, gi, gj, gk);
-        lattice_locals(L, gi, gj, gk, loc);
+        int loc[8];
+        bool msk;
+        node_locals(L, gi, gj, gk, loc, msk);
         ug[g] = (Tout)u[loc[0]];
     }
 }
@@ -107,13 +109,13 @@ __global__ void __launch_bounds__(kBS) scatter_kernel(const Tin *__restrict__ ug
 
 // dinv[g] = 1 / sum of local diagonal copies, 0 on Dirichlet nodes
 template <typename T>
-__global__ void __launch_bounds__(kBS) dinv_kernel(const double *__restrict__ dl, T *__restrict__ dinv, Lattice L, int64_t ng)
+__global__ void __launch_bounds__(kBS) dinv_kernel(const double *__restrict__ dl, T *__restrict__ dinv, Lattice L)
 {
-    GRID_STRIDE(g, ng)
+    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
     {
-        int64_t gi, gj, gk;
-        g_to_ijk(L, g, gi, gj, gk);
-        dinv[g] = lattice_masked(L, gi, gj, gk) ? T(0) : (T)(1.0 / assemble_at(L, dl, g));
+        bool msk;
+        const double d = assemble_at(L, dl, gi, gj, gk, msk);
+        dinv[g] = msk ? T(0) : (T)(1.0 / d);
     }
 }
 
@@ -175,16 +177,17 @@ __global__ void __launch_bounds__(kBS) alpha_kernel(CgState *st, const double *_
 template <typename T>
 __global__ void __launch_bounds__(kBS)
 update_kernel(const CgState *__restrict__ st, const T *__restrict__ w, T *__restrict__ x, T *__restrict__ r,
-              const T *__restrict__ p, const T *__restrict__ dinv, Lattice L, int64_t ng, double *__restrict__ part)
+              const T *__restrict__ p, const T *__restrict__ dinv, Lattice L, double *__restrict__ part)
 {
     if (st->done) return;
     const T alpha = (T)st->alpha;
     double acc[2] = {0.0, 0.0};
-    GRID_STRIDE(g, ng)
+    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
     {
         const T d = dinv[g];
         if (d == T(0)) continue;   // Dirichlet node: r, p, x stay zero
-        const T wg = (T)assemble_at(L, w, g);
+        bool msk;
+        const T wg = (T)assemble_at(L, w, gi, gj, gk, msk);
         x[g] += alpha * p[g];
         const T rg = r[g] - alpha * wg;
         r[g] = rg;
@@ -231,13 +234,14 @@ p_kernel(const CgState *__restrict__ st, T *__restrict__ p, const T *__restrict_
 template <typename T>
 __global__ void __launch_bounds__(kBS)
 resid_kernel(const T *__restrict__ b, const T *__restrict__ w, T *__restrict__ r, const T *__restrict__ dinv, Lattice L,
-             int64_t ng, double *__restrict__ part)
+             double *__restrict__ part)
 {
     double acc[1] = {0.0};
-    GRID_STRIDE(g, ng)
+    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
     {
         T rg = T(0);
-        if (dinv[g] != T(0)) rg = b[g] - (T)assemble_at(L, w, g);
+        bool msk;
+        if (dinv[g] != T(0)) rg = b[g] - (T)assemble_at(L, w, gi, gj, gk, msk);
         r[g] = rg;
         acc[0] += (double)rg * (double)rg;
     }
@@ -284,6 +288,11 @@ __global__ void __launch_bounds__(kBS) axpy_kernel(double *__restrict__ y, const
     GRID_STRIDE(g, ng) y[g] += s * (double)d[g];
 }
 
+__global__ void __launch_bounds__(kBS) rsub_kernel(const double *__restrict__ x, double *__restrict__ e, int64_t ng)
+{
+    GRID_STRIDE(g, ng) e[g] = x[g] - e[g];
+}
+
 // out = (T)(s * in)
 template <typename T>
 __global__ void __launch_bounds__(kBS) scale_kernel(const double *__restrict__ in, T *__restrict__ out, double s, int64_t ng)
@@ -306,7 +315,7 @@ int cg_blocks(int64_t n)
 template <typename T>
 hipError_t cg_gather(const Mesh &m, const double *u, T *ug, hipStream_t s)
 {
-    L3((cg::gather_kernel<double, T>), m.ng) u, ug, m.lat, m.ng);
+    hipLaunchKernelGGL((cg::gather_kernel<double, T>), dim3(cg::node_blocks(m.lat)), dim3(kBS), 0, s, u, ug, m.lat);
     return hipGetLastError();
 }
 
@@ -320,7 +329,7 @@ hipError_t cg_scatter(const Mesh &m, const T *ug, double *u, hipStream_t s)
 template <typename T>
 hipError_t cg_dinv(const Mesh &m, const double *diag_local, T *dinv, hipStream_t s)
 {
-    L3((cg::dinv_kernel<T>), m.ng) diag_local, dinv, m.lat, m.ng);
+    hipLaunchKernelGGL((cg::dinv_kernel<T>), dim3(cg::node_blocks(m.lat)), dim3(kBS), 0, s, diag_local, dinv, m.lat);
     return hipGetLastError();
 }
 
@@ -336,9 +345,9 @@ hipError_t cg_init(const Mesh &m, const CgVecs<T> &v, const T *b, CgState *st, d
 template <typename T>
 hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, double *hist, hipStream_t s)
 {
-    const int nb = cg_blocks(m.ng);
+    const int nb = (int)cg::node_blocks(m.lat);
     hipLaunchKernelGGL(cg::alpha_kernel, dim3(1), dim3(kBS), 0, s, st, v.part_e, m.E);
-    L3((cg::update_kernel<T>), m.ng) st, v.w, v.x, v.r, v.p, v.dinv, m.lat, m.ng, v.part_b);
+    hipLaunchKernelGGL((cg::update_kernel<T>), dim3(nb), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv, m.lat, v.part_b);
     hipLaunchKernelGGL(cg::beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb, hist);
     L3((cg::p_kernel<T>), m.ng) st, v.p, v.r, v.dinv, m.ng);
     return hipGetLastError();
@@ -347,8 +356,8 @@ hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, doub
 template <typename T>
 hipError_t cg_resid(const Mesh &m, const CgVecs<T> &v, const T *b, T *r, CgState *st, hipStream_t s)
 {
-    const int nb = cg_blocks(m.ng);
-    L3((cg::resid_kernel<T>), m.ng) b, v.w, r, v.dinv, m.lat, m.ng, v.part_b);
+    const int nb = (int)cg::node_blocks(m.lat);
+    hipLaunchKernelGGL((cg::resid_kernel<T>), dim3(nb), dim3(kBS), 0, s, b, v.w, r, v.dinv, m.lat, v.part_b);
     hipLaunchKernelGGL(cg::resid_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb);
     return hipGetLastError();
 }
@@ -373,6 +382,18 @@ template <typename T>
 hipError_t cg_scale(const Mesh &m, const double *in, T *out, double scale, hipStream_t s)
 {
     L3((cg::scale_kernel<T>), m.ng) in, out, scale, m.ng);
+    return hipGetLastError();
+}
+
+hipError_t cg_alpha(const Mesh &m, const double *part_e, CgState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(cg::alpha_kernel, dim3(1), dim3(kBS), 0, s, st, part_e, m.E);
+    return hipGetLastError();
+}
+
+hipError_t cg_rsub(const Mesh &m, const double *x, double *e, hipStream_t s)
+{
+    L3(cg::rsub_kernel, m.ng) x, e, m.ng);
     return hipGetLastError();
 }
 

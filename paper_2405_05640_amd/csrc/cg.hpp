@@ -12,9 +12,14 @@ constexpr int kMaxVecBlocks = 4096;  // grid cap (partials buffers are sized for
 struct CgState {
     double rz, pw, rr, bb, alpha, beta, tol2, true_rr;
     int32_t it, done, status, max_it;
-    int32_t hist_len, pad0, pad1, pad2;
+    int32_t hist_len, learned, redo, fallback_at;
+    int32_t nn_skip, pad0, pad1, pad2;
 };
 // done: 0 running, 1 converged (recursive residual), 2 breakdown, 3 max_iter
+// flexible CG: learned = 1 while the learned smoother is in use, redo = 1 when
+// the last smoother output was rejected (p restarts from dinv r),
+// fallback_at = iteration of the switch to Jacobi (-1: none), nn_skip =
+// done || !learned
 
 // Vectors of one CG run: x, r, p, dinv are assembled (n_global); w is local
 // (n_local, the unassembled operator output); part_e has n_elem entries,
@@ -40,6 +45,9 @@ hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, doub
 template <typename T>
 hipError_t cg_resid(const Mesh &m, const CgVecs<T> &v, const T *b, T *r, CgState *st, hipStream_t s);
 template <typename T> hipError_t cg_restart(const Mesh &m, const CgVecs<T> &v, CgState *st, hipStream_t s);
+hipError_t cg_alpha(const Mesh &m, const double *part_e, CgState *st, hipStream_t s);
+// e = x - e on assembled vectors
+hipError_t cg_rsub(const Mesh &m, const double *x, double *e, hipStream_t s);
 template <typename T> hipError_t cg_axpy(const Mesh &m, double *y, const T *d, double scale, hipStream_t s);
 template <typename T> hipError_t cg_scale(const Mesh &m, const double *in, T *out, double scale, hipStream_t s);
 

@@ -9,41 +9,66 @@
 // local index and writes the sum back to every copy.  Interior nodes (a
 // single copy) are never touched.
 //
-// Thread layout: one wavefront per run of 64 consecutive global nodes of a
-// lattice row (gj, gk).  In a row on an element face plane every node is
-// shared and the wave walks contiguous element rows; in any other row only
-// the x-face nodes (gi = m N) are shared and the wave takes 64 consecutive
-// x-faces, so lanes m and m+1 hit the two ends of the same 64-byte element
-// row.  Every element row is therefore fetched once per pass.
+// Copies come from three small per-axis tables (no index lists, no integer
+// division per node).  Two passes that touch disjoint nodes: lattice rows
+// (gj, gk) lying on an element-face plane, walked node by node (contiguous
+// element rows per wave), and the x-face nodes of all other rows, one thread
+// per (x-face, row) so lanes m and m+1 hit the two ends of one 64-byte
+// element row.  Every element row is fetched once per pass.
 #include "lattice.hpp"
 #include "sem_internal.hpp"
 
 namespace sem {
 namespace {
 
+// Rows on an element-face plane (or, with the mask, on a Dirichlet plane):
+// every node of the row is visited.
 template <typename T, int MASK>
-__global__ void __launch_bounds__(64)
-gs_kernel(T *__restrict__ u, Lattice L, int64_t xblocks, const int32_t *__restrict__ skip)
+__global__ void __launch_bounds__(256)
+gs_rows_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip)
 {
     if (skip && *skip) return;
-    const int64_t b = blockIdx.x;
-    const int64_t row = b / xblocks;
-    const int64_t q = (b - row * xblocks) * 64 + threadIdx.x;
-    const int64_t gj = row % L.ny, gk = row / L.ny;
-    int64_t gi;
-    if (gj % L.N == 0 || gk % L.N == 0) {
-        if (q >= L.nx) return;
-        gi = q;
-    } else {
-        if (q >= (L.per[0] ? L.nelx : L.nelx + 1)) return;
-        gi = q * L.N;
+    for (int64_t row = blockIdx.x; row < L.ny * L.nz; row += gridDim.x) {
+        const int gj = (int)(row % L.ny), gk = (int)(row / L.ny);
+        const int2 ay = L.tab[1][gj], az = L.tab[2][gk];
+        const bool full = axis_count(ay) > 1 || axis_count(az) > 1 ||
+                          (MASK && (axis_masked(ay) || axis_masked(az)));
+        if (!full) continue;   // uniform over the block
+        for (int gi = threadIdx.x; gi < L.nx; gi += blockDim.x) {
+            int loc[8];
+            bool msk;
+            const int n = node_locals(L, gi, gj, gk, loc, msk);
+            const bool zero = MASK && msk;
+            if (n == 1 && !zero) continue;
+            T s = T(0);
+            if (!zero)
+                for (int c = 0; c < n; ++c) s += u[loc[c]];
+            for (int c = 0; c < n; ++c) u[loc[c]] = s;
+        }
     }
-    int64_t loc[8];
-    const int n = lattice_locals(L, gi, gj, gk, loc);
-    const bool msk = MASK && lattice_masked(L, gi, gj, gk);
-    if (n == 1 && !msk) return;
+}
+
+// Every other row shares only its x-face nodes gi = m N: one thread per
+// (x-face, row); lanes m and m+1 touch the two ends of one element row.
+template <typename T, int MASK>
+__global__ void __launch_bounds__(256)
+gs_xface_kernel(T *__restrict__ u, Lattice L, int mx, const int32_t *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)mx * L.ny * L.nz) return;
+    const int64_t row = id / mx;
+    const int m = (int)(id - row * mx);
+    const int gj = (int)(row % L.ny), gk = (int)(row / L.ny);
+    const int2 ay = L.tab[1][gj], az = L.tab[2][gk];
+    if (axis_count(ay) > 1 || axis_count(az) > 1 || (MASK && (axis_masked(ay) || axis_masked(az)))) return;
+    int loc[8];
+    bool msk;
+    const int n = node_locals(L, m * L.N, gj, gk, loc, msk);
+    const bool zero = MASK && msk;
+    if (n == 1 && !zero) return;
     T s = T(0);
-    if (!msk)
+    if (!zero)
         for (int c = 0; c < n; ++c) s += u[loc[c]];
     for (int c = 0; c < n; ++c) u[loc[c]] = s;
 }
@@ -106,13 +131,18 @@ template <typename T>
 hipError_t dssum_impl(const Mesh &m, T *u, int apply_mask, hipStream_t s, const int32_t *skip)
 {
     const Lattice &L = m.lat;
-    const int64_t xblocks = (L.nx + 63) / 64;
-    const int64_t nblocks = xblocks * L.ny * L.nz;
-    if (nblocks == 0) return hipSuccess;
-    if (apply_mask)
-        hipLaunchKernelGGL((gs_kernel<T, 1>), dim3((unsigned)nblocks), dim3(64), 0, s, u, L, xblocks, skip);
-    else
-        hipLaunchKernelGGL((gs_kernel<T, 0>), dim3((unsigned)nblocks), dim3(64), 0, s, u, L, xblocks, skip);
+    const int64_t rows = L.ny * L.nz;
+    if (rows == 0) return hipSuccess;
+    const unsigned g1 = (unsigned)std::min<int64_t>(rows, 8192);
+    const int mx = L.per[0] ? L.nelx : L.nelx + 1;
+    const unsigned g2 = (unsigned)((mx * rows + 255) / 256);
+    if (apply_mask) {
+        hipLaunchKernelGGL((gs_rows_kernel<T, 1>), dim3(g1), dim3(256), 0, s, u, L, skip);
+        hipLaunchKernelGGL((gs_xface_kernel<T, 1>), dim3(g2), dim3(256), 0, s, u, L, mx, skip);
+    } else {
+        hipLaunchKernelGGL((gs_rows_kernel<T, 0>), dim3(g1), dim3(256), 0, s, u, L, skip);
+        hipLaunchKernelGGL((gs_xface_kernel<T, 0>), dim3(g2), dim3(256), 0, s, u, L, mx, skip);
+    }
     return hipGetLastError();
 }
 

@@ -21,7 +21,57 @@ struct Lattice {
     int64_t P;            // (N+1)^3
     uint8_t per[3];
     uint8_t dir;          // Dirichlet bits x-, x+, y-, y+, z-, z+
+    // Per-axis copy tables (device), one int2 per global index g of the axis:
+    //   .x = e0 | e1 << 16           element coordinates of the copies
+    //   .y = l0 | l1 << 8 | cnt << 16 | masked << 24   local coordinates, count
+    // so kernels enumerate copies with table reads instead of divisions.
+    const int2 *tab[3];
+    int unsorted;         // 1 if some axis is periodic with a single element
 };
+
+// Decode one axis entry.
+__host__ __device__ inline int axis_count(int2 a) { return (a.y >> 16) & 0xff; }
+__host__ __device__ inline int axis_elem(int2 a, int c) { return c ? (a.x >> 16) & 0xffff : a.x & 0xffff; }
+__host__ __device__ inline int axis_loc(int2 a, int c) { return c ? (a.y >> 8) & 0xff : a.y & 0xff; }
+__host__ __device__ inline bool axis_masked(int2 a) { return ((a.y >> 24) & 1) != 0; }
+
+// All local indices (ascending) of global node (gi, gj, gk) from the axis
+// tables, 32-bit arithmetic (n_local < 2^31).  Returns the copy count.
+__device__ inline int node_locals(const Lattice &L, int gi, int gj, int gk, int loc[8], bool &masked)
+{
+    const int2 ax = L.tab[0][gi], ay = L.tab[1][gj], az = L.tab[2][gk];
+    masked = axis_masked(ax) || axis_masked(ay) || axis_masked(az);
+    const int cx = axis_count(ax), cy = axis_count(ay), cz = axis_count(az);
+    const int P = (int)L.P, NP = L.NP;
+    int n = 0;
+    for (int c = 0; c < cz; ++c)
+        for (int b = 0; b < cy; ++b)
+            for (int a = 0; a < cx; ++a) {
+                const int e = axis_elem(ax, a) + L.nelx * (axis_elem(ay, b) + L.nely * axis_elem(az, c));
+                loc[n++] = e * P + axis_loc(ax, a) + NP * (axis_loc(ay, b) + NP * axis_loc(az, c));
+            }
+    if (L.unsorted) {
+        for (int q = 1; q < n; ++q) {
+            const int v = loc[q];
+            int r = q - 1;
+            while (r >= 0 && loc[r] > v) {
+                loc[r + 1] = loc[r];
+                --r;
+            }
+            loc[r + 1] = v;
+        }
+    }
+    return n;
+}
+
+// Loop over the global nodes of a block's share of lattice rows (gj, gk):
+// blocks stride over rows, threads over gi, so no index is divided per node.
+// Binds gi, gj, gk (int) and g (int64 lexicographic id) for the body.
+#define SEM_FOR_EACH_NODE(L, gi, gj, gk, g)                                                      \
+    for (int64_t row_ = blockIdx.x; row_ < (L).ny * (L).nz; row_ += gridDim.x)                  \
+        for (int gj = (int)(row_ % (L).ny), gk = (int)(row_ / (L).ny), gi = (int)threadIdx.x;   \
+             gi < (L).nx; gi += (int)blockDim.x)                                                \
+            if (const int64_t g = gi + (L).nx * row_; true)
 
 // Copies of a global index g along one direction, ascending in (element, local).
 // Returns the count (1 or 2); ec = element coordinate, lc = local coordinate.

@@ -151,7 +151,7 @@ static sem_status upload(T **dst, const T *src, size_t count, size_t &acc)
 static void release(Mesh &m)
 {
     void *ptrs[] = {m.d_D, m.d_D32, m.d_Dbf, m.d_G, m.d_B, m.d_xyz, m.d_wcode, m.d_mult,
-                    m.d_G32, m.d_B32, m.d_Gbf, m.d_Bbf, m.d_scratch};
+                    m.d_G32, m.d_B32, m.d_Gbf, m.d_Bbf, m.d_scratch, m.d_tab};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -257,7 +257,24 @@ static sem_status build(const sem_mesh_desc &d, Mesh &m)
     const int64_t nx = ndir(m.nelx, N, px), ny = ndir(m.nely, N, py), nz = ndir(m.nelz, N, pz);
     m.ng = nx * ny * nz;
     m.lat = Lattice{m.nelx, m.nely, m.nelz, N, NP, nx, ny, nz, P, {m.periodic[0], m.periodic[1], m.periodic[2]},
-                    m.dirichlet};
+                    m.dirichlet, {nullptr, nullptr, nullptr}, 0};
+    std::vector<int2> tab(nx + ny + nz);
+    {
+        const int nel[3] = {m.nelx, m.nely, m.nelz};
+        const int64_t nd[3] = {nx, ny, nz};
+        int64_t base = 0;
+        for (int d = 0; d < 3; ++d) {
+            for (int64_t g = 0; g < nd[d]; ++g) {
+                int ec[2] = {0, 0}, lc[2] = {0, 0};
+                const int cnt = lattice_copies(g, nel[d], N, m.periodic[d] != 0, ec, lc);
+                const bool msk = masked1(g, nel[d], N, m.periodic[d] != 0, m.dirichlet, d);
+                tab[base + g].x = ec[0] | (ec[1] << 16);
+                tab[base + g].y = lc[0] | (lc[1] << 8) | (cnt << 16) | ((msk ? 1 : 0) << 24);
+            }
+            base += nd[d];
+            if (m.periodic[d] && nel[d] == 1) m.lat.unsorted = 1;
+        }
+    }
     std::vector<uint8_t> wcode(nl), mult(nl);
     int64_t ns = 0, nmask = 0, nsl = 0;
 #pragma omp parallel for schedule(static) reduction(+ : ns, nmask)
@@ -295,6 +312,10 @@ static sem_status build(const sem_mesh_desc &d, Mesh &m)
 
     // ---- upload
     size_t acc = 0;
+    SEM_TRY(upload(&m.d_tab, tab.data(), tab.size(), acc));
+    m.lat.tab[0] = m.d_tab;
+    m.lat.tab[1] = m.d_tab + nx;
+    m.lat.tab[2] = m.d_tab + nx + ny;
     SEM_TRY(upload(&m.d_D, m.D.data(), m.D.size(), acc));
     // element-blocked geometric factors are already [E][6][P]
     SEM_TRY(upload(&m.d_G, G.get(), (size_t)6 * nl, acc));
@@ -361,6 +382,8 @@ sem_status sem_mesh_create(const sem_mesh_desc *desc, sem_mesh **out)
     const int64_t nl = (int64_t)desc->nelx * desc->nely * desc->nelz * np * np * np;
     if (nl >= ((int64_t)1 << 31))
         return fail(SEM_ERR_UNSUPPORTED, "more than 2^31 local nodes");
+    if (desc->nelx > 32767 || desc->nely > 32767 || desc->nelz > 32767)
+        return fail(SEM_ERR_UNSUPPORTED, "more than 32767 elements along one direction");
     sem_mesh *h = new (std::nothrow) sem_mesh();
     if (!h) return fail(SEM_ERR_OUT_OF_MEMORY, "host allocation");
     sem_status st = build(*desc, h->m);

@@ -1,0 +1,58 @@
+// nn.hpp -- internal interface of the learned smoother.
+#pragma once
+
+#include "cg.hpp"
+#include "sem_internal.hpp"
+
+namespace sem {
+
+constexpr int kChannels = 16;
+constexpr int kW1 = kChannels * 2 * 27;          // layer 1: [o][c][tap]
+constexpr int kW2 = kChannels * kChannels * 27;  // layer 2: [o][c][tap]
+constexpr int kW3 = kChannels * 27;              // layer 3: [c][tap]
+constexpr int kParams = kW1 + kW2 + kW3;         // 8208
+
+struct Smoother {
+    int64_t E = 0, ng = 0, nl = 0;
+    float *W = nullptr;             // FP32 master weights [W1 | W2 | W3]
+    float *m = nullptr, *v = nullptr;  // Adam moments
+    float *grad = nullptr;          // reduced gradient
+    unsigned short *W2b = nullptr;  // BF16 layer-2 operands [tap][o][c]
+    float *dW_elem = nullptr;       // [E][kParams] per-element gradients
+    float *c_local = nullptr;       // [nl] element outputs
+    double *buf = nullptr;          // training vectors: e, r, z, d, sd (5 x ng), w (nl)
+    double *part = nullptr;         // partial sums
+    double *scal = nullptr;         // device scalars: |e|_S^2, loss, ...
+    int step = 0;
+    float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    int stall_window = 25;
+    double stall_rate = 0.0;        // 0: stall test off
+    double dinv_h1 = -1.0, dinv_h2 = -1.0;   // coefficients of the cached training dinv
+    size_t device_bytes = 0;
+};
+
+// flexible CG with the learned smoother (learned.hip)
+// v: x, r, p, dinv (assembled), w (local); z, q: assembled scratch; the
+// smoother's c_local buffer holds the element outputs.
+sem_status solve_fcg(const Mesh &m, const Smoother &sm, const sem_solve_opts &o, const CgVecs<double> &v,
+                     const double *b64, double *z, double *q, CgState *st, double *hist, int hist_len,
+                     int check_every, hipStream_t s, sem_solve_report *rep, CgState &h);
+
+template <typename TR>
+hipError_t nn_infer(const Smoother &sm, const Mesh &m, const TR *rg, const TR *dinvg, float *c_local, hipStream_t s,
+                    const int32_t *skip);
+template <typename TR>
+hipError_t nn_assemble_z(const Mesh &m, const TR *rg, const TR *dinvg, const float *c_local, TR *z, hipStream_t s,
+                         const int32_t *use_c);
+hipError_t nn_grad(const Smoother &sm, const Mesh &m, const double *rg, const double *dinvg, const double *gz,
+                   float *dW_elem, double scale, float *grad, hipStream_t s);
+hipError_t nn_adam(Smoother &sm, const float *grad, hipStream_t s);
+hipError_t nn_pack(Smoother &sm, hipStream_t s);
+hipError_t nn_infer32(const Smoother &sm, const Mesh &m, const double *rg, const double *dinvg, float *c_local,
+                      hipStream_t s);
+
+}  // namespace sem
+
+struct sem_smoother {
+    sem::Smoother s;
+};

@@ -46,6 +46,7 @@ struct Mesh {
     uint8_t *d_wcode = nullptr;  // per local node: 0 masked, else 1 + log2(mult)
     uint8_t *d_mult = nullptr;   // per local node: mult
     Lattice lat{};               // closed-form numbering used by the kernels
+    int2 *d_tab = nullptr;       // axis copy tables (x, y, z concatenated)
     float *d_G32 = nullptr, *d_B32 = nullptr;          // [E][6][P], [E][P]
     uint16_t *d_Gbf = nullptr, *d_Bbf = nullptr;       // bf16 copies
     double *d_scratch = nullptr;  // small device scratch for sem_dot partials

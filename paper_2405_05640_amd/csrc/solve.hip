@@ -39,6 +39,7 @@
 #include <cstring>
 
 #include "cg.hpp"
+#include "nn.hpp"
 #include "sem_internal.hpp"
 
 #define SEM_TRY(x)                   \
@@ -57,6 +58,7 @@ struct Workspace {
     double *b64;             // assembled right-hand side
     CgVecs<float> v32;       // inner FP32 vectors (DC form)
     float *b32;
+    double *z, *q;           // flexible CG: smoother output and S p (assembled)
     CgState *st64, *st32;
     double *hist;
     size_t bytes;
@@ -85,6 +87,10 @@ Workspace carve(const Mesh &m, int form, int hist_len, char *base)
     ws.st64 = (CgState *)take(sizeof(CgState));
     ws.st32 = (CgState *)take(sizeof(CgState));
     ws.hist = (double *)take((size_t)std::max(hist_len, 1) * 8);
+    if (form == SEM_FORM_FCG_LEARNED) {
+        ws.z = (double *)take(ng * 8);
+        ws.q = (double *)take(ng * 8);
+    }
     if (uses_f32(form)) {
         ws.v32.x = (float *)take(ng * 4);
         ws.v32.r = (float *)take(ng * 4);
@@ -116,6 +122,10 @@ sem_status check_opts(const Mesh &m, const sem_solve_opts *o)
         if (!(o->inner_tol > 0.0 && o->inner_tol < 1.0))
             return fail(SEM_ERR_INVALID_ARG, "inner_tol must be in (0, 1)");
         if (o->max_outer < 1) return fail(SEM_ERR_INVALID_ARG, "max_outer must be >= 1");
+        return SEM_OK;
+    case SEM_FORM_FCG_LEARNED:
+        if (!o->smoother) return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_FCG_LEARNED needs opts.smoother");
+        if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "the learned smoother needs order N = 7");
         return SEM_OK;
     default:
         return fail(SEM_ERR_UNSUPPORTED, "solver form " + std::to_string(o->form) + " not available");
@@ -329,13 +339,16 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
     CgState h{};
     if (opts->form == SEM_FORM_DC_FP32)
         SEM_TRY(solve_dc32(m, *opts, ws, hist_len, s, check_every, rep, h));
+    else if (opts->form == SEM_FORM_FCG_LEARNED)
+        SEM_TRY(solve_fcg(m, opts->smoother->s, *opts, ws.v64, ws.b64, ws.z, ws.q, ws.st64, ws.hist, hist_len,
+                          check_every, s, rep, h));
     else
         SEM_TRY(solve_pcg64(m, *opts, ws, hist_len, s, check_every, rep, h));
     SEM_HIP_TRY(cg_scatter<double>(m, ws.v64.x, x, s));
 
     rep->rel_res = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
     rep->true_rel_res = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
-    if (opts->history && opts->history_len > 0 && opts->form == SEM_FORM_JACOBI_PCG) {
+    if (opts->history && opts->history_len > 0 && opts->form != SEM_FORM_DC_FP32) {
         const int n = std::min(opts->history_len, std::min(h.it + 1, hist_len));
         SEM_HIP_TRY(hipMemcpyAsync(opts->history, ws.hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         SEM_HIP_TRY(hipStreamSynchronize(s));
@@ -355,6 +368,57 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
                                                std::to_string(rep->iterations) + " iterations");
     }
     rep->status = SEM_OK;
+    return SEM_OK;
+}
+
+sem_status sem_pcg_snapshots(const sem_mesh *mesh, const sem_solve_opts *opts, const double *b, const int32_t *iters,
+                             int32_t n_iters, double *e_out, void *workspace, size_t ws_bytes, sem_solve_report *rep,
+                             void *stream)
+{
+    if (!mesh || !opts || !b || !workspace || !rep || (n_iters > 0 && (!iters || !e_out)))
+        return fail(SEM_ERR_INVALID_ARG, "null argument");
+    const Mesh &m = mesh->m;
+    sem_solve_opts o = *opts;
+    o.form = SEM_FORM_JACOBI_PCG;
+    SEM_TRY(check_opts(m, &o));
+    for (int q = 0; q < n_iters; ++q)
+        if (iters[q] < 0 || (q > 0 && iters[q] < iters[q - 1]))
+            return fail(SEM_ERR_INVALID_ARG, "iters must be non-negative and ascending");
+    std::memset(rep, 0, sizeof(*rep));
+    const int hist_len = hist_len_for(o);
+    Workspace ws = carve(m, o.form, hist_len, (char *)workspace);
+    if (ws_bytes < ws.bytes)
+        return fail(SEM_ERR_INVALID_ARG, "workspace too small: need " + std::to_string(ws.bytes) + " bytes");
+    hipStream_t s = (hipStream_t)stream;
+    const int check_every = std::max(1, o.check_every > 0 ? o.check_every : 16);
+    SEM_HIP_TRY(launch_diag(m, o.h1, o.h2, ws.v64.w, s));
+    SEM_HIP_TRY(cg_dinv<double>(m, ws.v64.w, ws.v64.dinv, s));
+    SEM_HIP_TRY(cg_gather<double>(m, b, ws.b64, s));
+    SEM_TRY(reset_state(ws.st64, o.max_iter, hist_len, s));
+    SEM_HIP_TRY(cg_init<double>(m, ws.v64, ws.b64, ws.st64, o.rel_tol, ws.hist, s));
+    CgState h{};
+    for (int q = 0; q < n_iters; ++q) {
+        // advance exactly to iteration iters[q] (or to convergence)
+        for (;;) {
+            SEM_TRY(read_state(h, ws.st64, s));
+            if (h.done || h.it >= iters[q]) break;
+            const int n = std::min(check_every, iters[q] - h.it);
+            for (int k = 0; k < n; ++k) {
+                SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, ws.v64.p, ws.v64.w, ws.v64.part_e, s, &ws.st64->done));
+                SEM_HIP_TRY(cg_step_after_ax<double>(m, ws.v64, ws.st64, ws.hist, s));
+            }
+        }
+        SEM_HIP_TRY(hipMemcpyAsync(e_out + (size_t)q * m.ng, ws.v64.x, (size_t)m.ng * 8, hipMemcpyDeviceToDevice, s));
+    }
+    SEM_TRY(iterate<double>(m, o.h1, o.h2, ws.v64, ws.st64, ws.hist, check_every, s, h));
+    for (int q = 0; q < n_iters; ++q) SEM_HIP_TRY(cg_rsub(m, ws.v64.x, e_out + (size_t)q * m.ng, s));
+    if (h.bb > 0.0) SEM_TRY(true_residual(m, o.h1, o.h2, ws, s, h));
+    rep->iterations = h.it;
+    rep->rel_res = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    rep->true_rel_res = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
+    rep->status = (h.bb == 0.0 || h.true_rr <= h.tol2) ? SEM_OK : SEM_ERR_NOT_CONVERGED;
+    SEM_HIP_TRY(hipStreamSynchronize(s));
+    if (rep->status != SEM_OK) return fail((sem_status)rep->status, "snapshot solve did not converge");
     return SEM_OK;
 }
 

@@ -22,12 +22,15 @@ SEM_OK, SEM_ERR_INVALID_ARG, SEM_ERR_OUT_OF_MEMORY, SEM_ERR_HIP, SEM_ERR_NOT_CON
 SEM_F64, SEM_F32, SEM_BF16 = 0, 1, 2
 SEM_PREP_F32, SEM_PREP_BF16 = 1, 2
 FIELD_GLO_NUM, FIELD_MULT, FIELD_MASK, FIELD_G, FIELD_B, FIELD_XYZ, FIELD_GLL, FIELD_DERIV = range(8)
-FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED, FORM_FCG_LEARNED_DC_F32 = range(5)
+FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED = range(4)
+SMOOTHER_PARAMS = 8208
 
 EXPORTED_SYMBOLS = [
     "sem_mesh_create", "sem_mesh_destroy", "sem_mesh_query", "sem_mesh_export", "sem_ax",
     "sem_dssum", "sem_rhs", "sem_jacobi", "sem_dot", "sem_solve_workspace_bytes",
-    "sem_pcg_solve", "sem_last_error", "sem_version",
+    "sem_pcg_solve", "sem_last_error", "sem_version", "sem_smoother_create", "sem_smoother_destroy",
+    "sem_smoother_set_weights", "sem_smoother_get_weights", "sem_smoother_apply", "sem_smoother_loss_grad",
+    "sem_smoother_train_step", "sem_pcg_snapshots",
 ]
 
 
@@ -57,6 +60,12 @@ class SolveOpts(ctypes.Structure):
                 ("form", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("smoother", ctypes.c_void_p),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int32)]
+
+
+class SmootherDesc(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("stall_window", ctypes.c_int32),
+                ("stall_rate", ctypes.c_double)]
 
 
 class SolveReport(ctypes.Structure):
@@ -97,6 +106,15 @@ def lib():
             "sem_solve_workspace_bytes": [vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(ctypes.c_size_t)],
             "sem_pcg_solve": [vp, ctypes.POINTER(SolveOpts), vp, vp, vp, ctypes.c_size_t,
                               ctypes.POINTER(SolveReport), vp],
+            "sem_smoother_create": [vp, ctypes.POINTER(SmootherDesc), ctypes.POINTER(vp)],
+            "sem_smoother_destroy": [vp],
+            "sem_smoother_set_weights": [vp, vp, ctypes.c_size_t],
+            "sem_smoother_get_weights": [vp, vp, ctypes.c_size_t],
+            "sem_smoother_apply": [vp, vp, dbl, dbl, ctypes.c_int, vp, vp, vp],
+            "sem_smoother_loss_grad": [vp, vp, dbl, dbl, vp, ctypes.POINTER(dbl), vp, vp],
+            "sem_smoother_train_step": [vp, vp, dbl, dbl, vp, vp, vp],
+            "sem_pcg_snapshots": [vp, ctypes.POINTER(SolveOpts), vp, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t,
+                                  ctypes.POINTER(SolveReport), vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -249,7 +267,7 @@ class Mesh:
         o = SolveOpts()
         o.h1, o.h2, o.rel_tol, o.max_iter, o.check_every = h1, h2, rel_tol, max_iter, check_every
         o.form, o.max_outer, o.inner_tol = form, max_outer, inner_tol
-        o.smoother = smoother._h if smoother is not None else None
+        o.smoother = smoother._h.value if smoother is not None else None
         if history is not None:
             o.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             o.history_len = len(history)
@@ -286,6 +304,82 @@ class Mesh:
         if st != SEM_OK and raise_on_error:
             raise SemError(st, lib().sem_last_error().decode())
         return r
+
+
+class Smoother:
+    """Learned per-element smoother (``sem_smoother``) bound to one N = 7 mesh."""
+
+    def __init__(self, mesh, seed=0, lr=1e-3, stall_window=25, stall_rate=0.0):
+        d = SmootherDesc(seed, lr, 0.9, 0.999, 1e-8, stall_window, stall_rate)
+        h = ctypes.c_void_p()
+        _check(lib().sem_smoother_create(mesh._h, ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.mesh = mesh
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sem_smoother_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32).ravel()
+        if w.size != SMOOTHER_PARAMS:
+            raise ValueError("expected %d weights" % SMOOTHER_PARAMS)
+        _check(lib().sem_smoother_set_weights(self._h, w.ctypes.data_as(ctypes.c_void_p), w.size))
+
+    def get_weights(self):
+        w = np.zeros(SMOOTHER_PARAMS, dtype=np.float32)
+        _check(lib().sem_smoother_get_weights(self._h, w.ctypes.data_as(ctypes.c_void_p), w.size))
+        return w
+
+    def apply(self, r, z, h1=1.0, h2=0.0, fp32=False):
+        m = self.mesh
+        _check(lib().sem_smoother_apply(self._h, m._h, float(h1), float(h2), 1 if fp32 else 0,
+                                        _want(r, "f64", m.n_local, "r"), _want(z, "f64", m.n_local, "z"), _stream()))
+        return z
+
+    def loss_grad(self, e, h1=1.0, h2=0.0):
+        m = self.mesh
+        loss = ctypes.c_double()
+        g = np.zeros(SMOOTHER_PARAMS, dtype=np.float32)
+        _check(lib().sem_smoother_loss_grad(self._h, m._h, float(h1), float(h2), _want(e, "f64", m.n_local, "e"),
+                                            ctypes.byref(loss), g.ctypes.data_as(ctypes.c_void_p), _stream()))
+        return loss.value, g
+
+    def train_step(self, e_global, loss_out=None, h1=1.0, h2=0.0):
+        m = self.mesh
+        _check(lib().sem_smoother_train_step(self._h, m._h, float(h1), float(h2),
+                                             _want(e_global, "f32", m.n_global, "e_global"),
+                                             _want(loss_out, "f64", 1, "loss_out") if loss_out is not None else None,
+                                             _stream()))
+
+
+def pcg_snapshots(mesh, b, iters, e_out, workspace=None, **kw):
+    """Errors x* - x_k of Jacobi-PCG iterates (assembled, lexicographic) into e_out[len(iters), n_global]."""
+    import torch
+    it = np.ascontiguousarray(iters, dtype=np.int32)
+    opts = mesh.solve_opts(**kw)
+    if workspace is None:
+        workspace = mesh.workspace(opts)
+    need = mesh.workspace_bytes(opts)
+    if workspace.numel() * workspace.element_size() < need:
+        raise ValueError("workspace too small")
+    if not (isinstance(e_out, torch.Tensor) and e_out.is_cuda and e_out.dtype == torch.float64 and
+            e_out.is_contiguous() and e_out.numel() == len(it) * mesh.n_global):
+        raise ValueError("e_out must be a contiguous device float64 tensor of len(iters) * n_global")
+    rep = SolveReport()
+    _check(lib().sem_pcg_snapshots(mesh._h, ctypes.byref(opts), _want(b, "f64", mesh.n_local, "b"),
+                                   it.ctypes.data_as(ctypes.c_void_p), len(it), ctypes.c_void_p(e_out.data_ptr()),
+                                   ctypes.c_void_p(workspace.data_ptr()),
+                                   workspace.numel() * workspace.element_size(), ctypes.byref(rep), _stream()))
+    return Report(rep.status, rep.iterations, rep.outer_iterations, rep.restarts, rep.fallback_used, rep.rel_res,
+                  rep.true_rel_res, rep.elapsed_ms)
 
 
 def version():
