@@ -42,7 +42,139 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-solve", action="store_true")
     p.add_argument("--nel", type=int, default=32, help="elements per direction (32 = headline)")
+    p.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 defect-correction solves")
+    p.add_argument("--no-learned", action="store_true", help="skip training and timing the learned smoother")
+    p.add_argument("--train-fields", type=int, default=48, help="channel fields used for training pairs")
+    p.add_argument("--train-epochs", type=int, default=4)
+    p.add_argument("--heldout", type=int, default=4)
+    p.add_argument("--profile-kernels", action="store_true",
+                   help="only launch the operator, gather-scatter and CG kernels a few times plus a "
+                        "1 GiB torch copy (reference for hardware byte counters), then exit")
     return p.parse_args()
+
+
+def profile_kernels():
+    """Short, fixed launch sequence for rocprofv3 counter runs: 5 x (sem_ax,
+    sem_dssum) on the 32^3 workload, one 300-iteration FP64 PCG solve, and
+    5 copies of a 1 GiB buffer (exactly 1 GiB read + 1 GiB written each)."""
+    import torch
+
+    from paper_2405_05640_amd import sem
+    from paper_2405_05640_amd import workloads as wl
+    torch.cuda.set_device(0)
+    spec = wl.deformed_cube(32, 7)
+    mesh = sem.Mesh.from_spec(spec)
+    u = torch.rand(mesh.shape, dtype=torch.float64, device="cuda")
+    w = torch.empty_like(u)
+    for _ in range(5):
+        mesh.ax(u, w, 1.0, 0.1)
+        mesh.dssum(w, mask=True)
+    b = torch.empty_like(u)
+    mesh.rhs(u, b)
+    x = torch.zeros_like(b)
+    mesh.pcg_solve(b, x, h1=1.0, h2=0.1, max_iter=300, raise_on_error=False)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print("profile-kernels: done", flush=True)
+
+
+def timed_solves(mesh, b, reps, **kw):
+    """Median wall time of `reps` solves from x = 0 (after one warm-up)."""
+    import torch
+    x = torch.zeros_like(b)
+    ws = mesh.workspace(mesh.solve_opts(**{k: v for k, v in kw.items() if k != "smoother"}))
+    times, rep = [], None
+    for q in range(reps + 1):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = mesh.pcg_solve(b, x, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        if q > 0:
+            times.append((time.perf_counter() - t0) * 1e3)
+    med = statistics.median(times)
+    ci = 1.96 * statistics.stdev(times) / math.sqrt(len(times)) if len(times) > 1 else 0.0
+    return {"median": round(med, 2), "ci95": round(ci, 2), "iterations": rep.iterations,
+            "outer_iterations": rep.outer_iterations, "true_rel_res": rep.true_rel_res,
+            "fallback_used": rep.fallback_used}, x
+
+
+def learned_section(args):
+    """Train the smoother on the 16^3 channel workload, then time flexible CG
+    with it against Jacobi-PCG on held-out fields (same GPU, same process)."""
+    import numpy as np
+    import torch
+
+    from paper_2405_05640_amd import sem
+    from paper_2405_05640_amd import workloads as wl
+
+    spec = wl.config("c3")
+    mesh = sem.Mesh.from_spec(spec)
+    xyz = mesh.export(sem.FIELD_XYZ)
+    vm = wl.kolmogorov_velocity(wl.RHS_SEED["c3"])
+
+    def rhs(t):
+        f = torch.from_numpy(wl.fourier_on_elements(wl.divergence_source(vm, t), xyz, (16, 16, 16))).cuda()
+        b = torch.empty_like(f)
+        mesh.rhs(f, b)
+        return b
+
+    # training pairs: errors of Jacobi-PCG iterates
+    t0 = time.perf_counter()
+    iters = [2, 8, 32, 128]
+    pairs = []
+    ws = mesh.workspace(mesh.solve_opts())
+    for t in range(args.train_fields):
+        b = rhs(t)
+        e = torch.zeros(len(iters) * mesh.n_global, dtype=torch.float64, device="cuda")
+        sem.pcg_snapshots(mesh, b, iters, e, workspace=ws)
+        for q in range(len(iters)):
+            pairs.append(e[q * mesh.n_global:(q + 1) * mesh.n_global].float().contiguous())
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    # Jacobi-PCG reference rate for the stall test
+    b0 = rhs(args.train_fields + 1000)
+    r0, _ = timed_solves(mesh, b0, 1)
+    rate = (1e-10) ** (1.0 / max(r0["iterations"], 1))
+    sm = sem.Smoother(mesh, seed=0, lr=1e-3, stall_window=25, stall_rate=rate)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    losses = []
+    t0 = time.perf_counter()
+    order = np.random.default_rng(0).permutation(len(pairs))
+    for ep in range(args.train_epochs):
+        acc = []
+        for k in order:
+            sm.train_step(pairs[k], loss)
+            acc.append(loss)
+            loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        losses.append(float(torch.cat(acc).mean().item()))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del pairs
+    # held-out fields (t beyond the training range)
+    res_j, res_l = [], []
+    for h in range(args.heldout):
+        b = rhs(2000 + h)
+        rj, _ = timed_solves(mesh, b, 2)
+        rl, _ = timed_solves(mesh, b, 2, form=sem.FORM_FCG_LEARNED, smoother=sm)
+        res_j.append(rj)
+        res_l.append(rl)
+    tj = statistics.mean(r["median"] for r in res_j)
+    tl = statistics.mean(r["median"] for r in res_l)
+    return {"workload": "16^3 tanh-stretched channel, N=7, periodic x/z, Poisson, k^-5/3 divergence RHS",
+            "train_fields": args.train_fields, "pairs": args.train_fields * len(iters),
+            "snapshot_iters": iters, "epochs": args.train_epochs, "loss_per_epoch": [round(v, 5) for v in losses],
+            "data_gen_s": round(t_data, 2), "train_s": round(t_train, 2),
+            "heldout": args.heldout,
+            "jacobi_pcg": {"median_ms": round(tj, 2),
+                           "iterations": [r["iterations"] for r in res_j]},
+            "fcg_learned": {"median_ms": round(tl, 2), "iterations": [r["iterations"] for r in res_l],
+                            "fallback_used": [r["fallback_used"] for r in res_l],
+                            "true_rel_res_max": max(r["true_rel_res"] for r in res_l)},
+            "speedup_vs_jacobi_pcg": round(tj / tl, 3)}
 
 
 def traffic_record(kernel_src):
@@ -74,7 +206,7 @@ def cpu_baseline(spec, h1, h2, budget_s=12.0):
         om.apply_S(u, h1, h2)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 50:
+        if el >= budget_s:
             break
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     return {"value": om.nl * reps / el / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
@@ -85,6 +217,9 @@ def cpu_baseline(spec, h1, h2, budget_s=12.0):
 
 def main():
     args = parse()
+    if args.profile_kernels:
+        profile_kernels()
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no sharding or collectives); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -169,27 +304,35 @@ def main():
     }
 
     if not args.no_solve:
-        times, its, rel = [], [], []
-        x = torch.zeros_like(b)
-        ws = mesh.workspace(mesh.solve_opts(h1=h1, h2=h2))
-        for rep in range(args.solve_reps + 1):
-            x.zero_()
-            torch.cuda.synchronize()
-            ts = time.perf_counter()
-            r = mesh.pcg_solve(b, x, workspace=ws, h1=h1, h2=h2, rel_tol=1e-10, check_every=32)
-            torch.cuda.synchronize()
-            te = time.perf_counter()
-            if rep > 0:
-                times.append((te - ts) * 1e3)
-                its.append(r.iterations)
-                rel.append(r.true_rel_res)
-        med = statistics.median(times)
-        ci = 1.96 * statistics.stdev(times) / math.sqrt(len(times)) if len(times) > 1 else 0.0
-        out["time_to_1e-10_ms"] = {"fp64_jacobi_pcg": {"median": round(med, 2), "ci95": round(ci, 2),
-                                                       "iterations": its[0], "true_rel_res": rel[0],
-                                                       "ms_per_iteration": round(med / its[0], 4)}}
-        print("PCG: %d iterations, %.1f ms (%.1f us/iter), true rel res %.2e" %
-              (its[0], med, med / its[0] * 1e3, rel[0]), flush=True)
+        sol = {}
+        r64, x64 = timed_solves(mesh, b, args.solve_reps, h1=h1, h2=h2, rel_tol=1e-10, check_every=32)
+        r64["ms_per_iteration"] = round(r64["median"] / max(r64["iterations"], 1), 4)
+        sol["fp64_jacobi_pcg"] = r64
+        print("PCG: %d iterations, %.1f ms, true rel res %.2e" % (r64["iterations"], r64["median"],
+                                                                r64["true_rel_res"]), flush=True)
+        if not args.no_mixed:
+            del mesh
+            torch.cuda.empty_cache()
+            mesh = sem.Mesh.from_spec(spec, prepare=sem.SEM_PREP_F32 | sem.SEM_PREP_BF16)
+            for name, form, itol in (("dc_fp32", sem.FORM_DC_FP32, 1e-5), ("dc_bf16", sem.FORM_DC_BF16, 1e-2)):
+                try:
+                    rr, xx = timed_solves(mesh, b, args.solve_reps, h1=h1, h2=h2, rel_tol=1e-10, check_every=32,
+                                          form=form, inner_tol=itol, max_outer=60)
+                except sem.SemError as exc:
+                    sol[name] = {"status": "failed", "error": str(exc), "inner_tol": itol}
+                    print("%s: %s" % (name, exc), flush=True)
+                    continue
+                d = xx - x64
+                rr["rel_diff_vs_fp64_pcg"] = float(torch.linalg.norm(d) / torch.linalg.norm(x64))
+                rr["inner_tol"] = itol
+                rr["speedup_vs_fp64_pcg"] = round(r64["median"] / rr["median"], 3)
+                sol[name] = rr
+                print("%s: %d inner / %d outer, %.1f ms, true rel res %.2e" %
+                      (name, rr["iterations"], rr["outer_iterations"], rr["median"], rr["true_rel_res"]), flush=True)
+        out["time_to_1e-10_ms"] = sol
+    if not args.no_learned:
+        out["learned_smoother"] = learned_section(args)
+        print("learned: %s" % json.dumps(out["learned_smoother"]), flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, h1, h2)

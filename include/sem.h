@@ -135,8 +135,11 @@ typedef enum {
     SEM_FORM_JACOBI_PCG = 0,     /* FP64 Jacobi-preconditioned CG */
     SEM_FORM_DC_FP32 = 1,        /* FP64 defect correction around FP32 Jacobi-PCG */
     SEM_FORM_DC_BF16 = 2,        /* FP64 defect correction around BF16-operator PCG */
-    SEM_FORM_FCG_LEARNED = 3     /* flexible CG with the learned smoother (opts.smoother),
+    SEM_FORM_FCG_LEARNED = 3,    /* flexible CG with the learned smoother (opts.smoother),
                                     Jacobi-PCG fallback */
+    SEM_FORM_FCG_INNER_FP32 = 4, /* FP64 flexible CG preconditioned by inner_iters steps of
+                                    FP32 Jacobi-PCG (FP32 operator) on the unit-scaled defect */
+    SEM_FORM_FCG_INNER_BF16 = 5  /* same with the BF16 matrix-core operator in the inner steps */
 } sem_form;
 
 typedef struct {
@@ -150,12 +153,14 @@ typedef struct {
     const sem_smoother *smoother; /* learned forms */
     double *history;            /* HOST, optional: relative residual per iteration */
     int32_t history_len;        /* capacity of history */
+    int32_t inner_iters;        /* inner steps per outer iteration (FCG_INNER forms) */
 } sem_solve_opts;
 
 typedef struct {
     int32_t status;             /* sem_status of the solve */
-    int32_t iterations;         /* operator applications in the Krylov loop(s) */
-    int32_t outer_iterations;   /* defect-correction steps (DC forms), else 0 */
+    int32_t iterations;         /* operator applications in the Krylov loop(s); for the
+                                   DC and FCG_INNER forms: low-precision inner iterations */
+    int32_t outer_iterations;   /* DC steps, or FP64 outer iterations (FCG_INNER forms) */
     int32_t restarts;           /* true-residual restarts */
     int32_t fallback_used;      /* learned forms: 1 if Jacobi-PCG took over */
     int32_t history_written;

@@ -13,7 +13,7 @@ struct CgState {
     double rz, pw, rr, bb, alpha, beta, tol2, true_rr;
     int32_t it, done, status, max_it;
     int32_t hist_len, learned, redo, fallback_at;
-    int32_t nn_skip, pad0, pad1, pad2;
+    int32_t nn_skip, inner_its, pad1, pad2;
 };
 // done: 0 running, 1 converged (recursive residual), 2 breakdown, 3 max_iter
 // flexible CG: learned = 1 while the learned smoother is in use, redo = 1 when

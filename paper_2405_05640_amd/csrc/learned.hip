@@ -269,6 +269,39 @@ __global__ void __launch_bounds__(kBS) fcg_redo_finalize(CgState *st, const doub
     }
 }
 
+// ------------------------------------------------------------ nested solver
+
+// b32 = r / |r| rounded to FP32 (outer residual norm from the device state)
+__global__ void __launch_bounds__(kBS)
+scale_defect_kernel(const CgState *__restrict__ st, const double *__restrict__ r, float *__restrict__ b32, int64_t ng)
+{
+    if (st->done || !st->learned) return;
+    const double s = st->rr > 0.0 ? 1.0 / sqrt(st->rr) : 0.0;
+    GRID_STRIDE(g, ng) b32[g] = (float)(s * r[g]);
+}
+
+// z = |r| x32 (inner solution) while the inner solver is active, else
+// dinv r; accumulates the inner iteration count; partials (r, z), (z, q)
+__global__ void __launch_bounds__(kBS)
+nested_z_kernel(CgState *st, const CgState *__restrict__ st_in, const float *__restrict__ x32,
+                const double *__restrict__ r, const double *__restrict__ dinv, const double *__restrict__ q,
+                double *__restrict__ z, int64_t ng, double *__restrict__ part)
+{
+    if (st->done) return;
+    const bool inner = st->learned != 0;
+    const double s = sqrt(st->rr);
+    double acc[2] = {0.0, 0.0};
+    GRID_STRIDE(g, ng)
+    {
+        const double zz = inner ? s * (double)x32[g] : dinv[g] * r[g];
+        z[g] = zz;
+        acc[0] += r[g] * zz;
+        acc[1] += zz * (q ? q[g] : 0.0);
+    }
+    block_store<2>(acc, part, gridDim.x);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && inner) st->inner_its += st_in->it;
+}
+
 __global__ void zero_kernel(double *__restrict__ a, int64_t n)
 {
     GRID_STRIDE(g, n) a[g] = 0.0;
@@ -438,6 +471,98 @@ sem_status solve_fcg(const Mesh &m, const Smoother &sm, const sem_solve_opts &o,
         SEM_TRY(read_state(h, st, s));
     }
     rep->iterations = h.it;
+    rep->restarts = restarts;
+    rep->fallback_used = h.fallback_at >= 0 ? 1 : 0;
+    return SEM_OK;
+}
+
+// queue one preconditioner application: z = |r| * (inner_iters steps of
+// low-precision Jacobi-PCG on r / |r|), then the partials (r, z), (z, q)
+static sem_status nested_precondition(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v,
+                                      const CgVecs<float> &v32, float *b32, double *z, const double *q,
+                                      CgState *st, CgState *st32, bool bf16, bool inner_active, hipStream_t s)
+{
+    const int nb = cg_blocks(m.ng);
+    if (inner_active) {
+        hipLaunchKernelGGL(lk::scale_defect_kernel, dim3(nb), dim3(kBS), 0, s, st, v.r, b32, m.ng);
+        SEM_HIP_TRY(cg_init<float>(m, v32, b32, st32, o.inner_tol, nullptr, s));
+        for (int k = 0; k < o.inner_iters; ++k) {
+            if (bf16)
+                SEM_HIP_TRY(launch_ax_bf16_gather(m, (float)o.h1, (float)o.h2, v32.p, v32.w, v32.part_e, s, &st32->done));
+            else
+                SEM_HIP_TRY(launch_ax_f32_gather(m, (float)o.h1, (float)o.h2, v32.p, v32.w, v32.part_e, s, &st32->done));
+            SEM_HIP_TRY(cg_step_after_ax<float>(m, v32, st32, nullptr, s));
+        }
+    }
+    hipLaunchKernelGGL(lk::nested_z_kernel, dim3(nb), dim3(kBS), 0, s, st, st32, v32.x, v.r, v.dinv, q, z, m.ng,
+                       v.part_b);
+    SEM_HIP_TRY(hipGetLastError());
+    return SEM_OK;
+}
+
+sem_status solve_fcg_nested(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const CgVecs<float> &v32,
+                            float *b32, const double *b64, double *z, double *q, CgState *st, CgState *st32,
+                            double *hist, int hist_len, int check_every, bool bf16, hipStream_t s,
+                            sem_solve_report *rep, CgState &h)
+{
+    const int nb = cg_blocks(m.ng);
+    const int nbn = node_blocks(m);
+    CgState init{};
+    init.max_it = o.max_iter;
+    init.hist_len = hist_len;
+    init.learned = 1;
+    init.fallback_at = -1;
+    SEM_HIP_TRY(hipMemcpyAsync(st, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
+    CgState init32{};
+    init32.max_it = o.inner_iters;
+    SEM_HIP_TRY(hipMemcpyAsync(st32, &init32, sizeof(CgState), hipMemcpyHostToDevice, s));
+    SEM_HIP_TRY(cg_init<double>(m, v, b64, st, o.rel_tol, hist, s));
+    hipLaunchKernelGGL(lk::zero_kernel, dim3(nb), dim3(kBS), 0, s, v.p, m.ng);
+    bool inner_active = true;
+    auto direction = [&](int first) -> sem_status {
+        SEM_TRY(nested_precondition(m, o, v, v32, b32, z, first ? nullptr : q, st, st32, bf16, inner_active, s));
+        hipLaunchKernelGGL(lk::fcg_beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb, first);
+        hipLaunchKernelGGL(lk::fcg_p_kernel, dim3(nb), dim3(kBS), 0, s, st, v.p, z, v.r, v.dinv, m.ng, v.part_b);
+        hipLaunchKernelGGL(lk::fcg_redo_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb);
+        SEM_HIP_TRY(hipGetLastError());
+        return SEM_OK;
+    };
+    SEM_TRY(direction(1));
+    int restarts = 0;
+    for (;;) {
+        for (;;) {
+            SEM_TRY(read_state(h, st, s));
+            if (h.done) break;
+            inner_active = h.learned != 0;
+            for (int it = 0; it < check_every; ++it) {
+                SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.p, v.w, v.part_e, s, &st->done));
+                SEM_HIP_TRY(cg_alpha(m, v.part_e, st, s));
+                hipLaunchKernelGGL(lk::fcg_update_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,
+                                   q, m.lat, v.part_b);
+                hipLaunchKernelGGL(lk::fcg_check_kernel, dim3(1), dim3(kBS), 0, s, st, v.part_b, nbn, hist, 25, 0.0);
+                SEM_TRY(direction(0));
+            }
+        }
+        if (h.done != 1 || h.bb == 0.0) break;
+        SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.x, v.w, nullptr, s));
+        SEM_HIP_TRY(cg_resid<double>(m, v, b64, v.r, st, s));
+        SEM_TRY(read_state(h, st, s));
+        if (h.true_rr <= h.tol2 || restarts == 3 || h.it >= h.max_it) break;
+        ++restarts;
+        CgState patch = h;
+        patch.done = 0;
+        patch.rr = h.true_rr;
+        SEM_HIP_TRY(hipMemcpyAsync(st, &patch, sizeof(CgState), hipMemcpyHostToDevice, s));
+        inner_active = h.learned != 0;
+        SEM_TRY(direction(1));
+    }
+    if (h.done != 1 && h.bb > 0.0) {
+        SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.x, v.w, nullptr, s));
+        SEM_HIP_TRY(cg_resid<double>(m, v, b64, v.r, st, s));
+        SEM_TRY(read_state(h, st, s));
+    }
+    rep->iterations = h.inner_its;
+    rep->outer_iterations = h.it;
     rep->restarts = restarts;
     rep->fallback_used = h.fallback_at >= 0 ? 1 : 0;
     return SEM_OK;

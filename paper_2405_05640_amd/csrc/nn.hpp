@@ -38,6 +38,13 @@ sem_status solve_fcg(const Mesh &m, const Smoother &sm, const sem_solve_opts &o,
                      const double *b64, double *z, double *q, CgState *st, double *hist, int hist_len,
                      int check_every, hipStream_t s, sem_solve_report *rep, CgState &h);
 
+// FP64 flexible CG preconditioned by inner_iters steps of FP32-vector
+// Jacobi-PCG with the FP32 or BF16 operator (learned.hip)
+sem_status solve_fcg_nested(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const CgVecs<float> &v32,
+                            float *b32, const double *b64, double *z, double *q, CgState *st, CgState *st32,
+                            double *hist, int hist_len, int check_every, bool bf16, hipStream_t s,
+                            sem_solve_report *rep, CgState &h);
+
 template <typename TR>
 hipError_t nn_infer(const Smoother &sm, const Mesh &m, const TR *rg, const TR *dinvg, float *c_local, hipStream_t s,
                     const int32_t *skip);

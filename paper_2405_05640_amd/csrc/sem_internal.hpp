@@ -68,6 +68,11 @@ hipError_t launch_ax_f64_gather(const Mesh &m, double h1, double h2, const doubl
                                 double *partial_uw, hipStream_t s, const int32_t *skip = nullptr);
 hipError_t launch_ax_f32_gather(const Mesh &m, float h1, float h2, const float *ug, float *w,
                                 double *partial_uw, hipStream_t s, const int32_t *skip = nullptr);
+// BF16 operator on the matrix cores (N = 7): u local bf16 bits, or (gather)
+// an assembled float vector rounded to bf16 on load; w float local.
+hipError_t launch_ax_bf16(const Mesh &m, float h1, float h2, const uint16_t *u, float *w, hipStream_t s);
+hipError_t launch_ax_bf16_gather(const Mesh &m, float h1, float h2, const float *ug, float *w, double *partial_uw,
+                                 hipStream_t s, const int32_t *skip = nullptr);
 hipError_t launch_diag(const Mesh &m, double h1, double h2, double *d, hipStream_t s);
 hipError_t launch_dssum_f64(const Mesh &m, double *u, int apply_mask, hipStream_t s,
                            const int32_t *skip = nullptr);

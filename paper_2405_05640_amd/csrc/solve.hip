@@ -64,7 +64,15 @@ struct Workspace {
     size_t bytes;
 };
 
-bool uses_f32(int form) { return form == SEM_FORM_DC_FP32; }
+bool uses_f32(int form)
+{
+    return form == SEM_FORM_DC_FP32 || form == SEM_FORM_DC_BF16 || form == SEM_FORM_FCG_INNER_FP32 ||
+           form == SEM_FORM_FCG_INNER_BF16;
+}
+bool uses_fcg(int form)
+{
+    return form == SEM_FORM_FCG_LEARNED || form == SEM_FORM_FCG_INNER_FP32 || form == SEM_FORM_FCG_INNER_BF16;
+}
 
 Workspace carve(const Mesh &m, int form, int hist_len, char *base)
 {
@@ -87,7 +95,7 @@ Workspace carve(const Mesh &m, int form, int hist_len, char *base)
     ws.st64 = (CgState *)take(sizeof(CgState));
     ws.st32 = (CgState *)take(sizeof(CgState));
     ws.hist = (double *)take((size_t)std::max(hist_len, 1) * 8);
-    if (form == SEM_FORM_FCG_LEARNED) {
+    if (uses_fcg(form)) {
         ws.z = (double *)take(ng * 8);
         ws.q = (double *)take(ng * 8);
     }
@@ -118,10 +126,27 @@ sem_status check_opts(const Mesh &m, const sem_solve_opts *o)
     case SEM_FORM_JACOBI_PCG:
         return SEM_OK;
     case SEM_FORM_DC_FP32:
-        if (!m.d_G32) return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_DC_FP32 needs a mesh created with SEM_PREP_F32");
+    case SEM_FORM_DC_BF16:
+        if (o->form == SEM_FORM_DC_FP32 && !m.d_G32)
+            return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_DC_FP32 needs a mesh created with SEM_PREP_F32");
+        if (o->form == SEM_FORM_DC_BF16 && !m.d_Gbf)
+            return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_DC_BF16 needs a mesh created with SEM_PREP_BF16");
+        if (o->form == SEM_FORM_DC_BF16 && m.N != 7)
+            return fail(SEM_ERR_UNSUPPORTED, "the bf16 operator needs order N = 7");
         if (!(o->inner_tol > 0.0 && o->inner_tol < 1.0))
             return fail(SEM_ERR_INVALID_ARG, "inner_tol must be in (0, 1)");
         if (o->max_outer < 1) return fail(SEM_ERR_INVALID_ARG, "max_outer must be >= 1");
+        return SEM_OK;
+    case SEM_FORM_FCG_INNER_FP32:
+    case SEM_FORM_FCG_INNER_BF16:
+        if (o->form == SEM_FORM_FCG_INNER_FP32 && !m.d_G32)
+            return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_FCG_INNER_FP32 needs a mesh created with SEM_PREP_F32");
+        if (o->form == SEM_FORM_FCG_INNER_BF16 && !m.d_Gbf)
+            return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_FCG_INNER_BF16 needs a mesh created with SEM_PREP_BF16");
+        if (o->form == SEM_FORM_FCG_INNER_BF16 && m.N != 7)
+            return fail(SEM_ERR_UNSUPPORTED, "the bf16 operator needs order N = 7");
+        if (o->inner_iters < 1 || o->inner_iters > 10000) return fail(SEM_ERR_INVALID_ARG, "inner_iters must be in 1..10000");
+        if (!(o->inner_tol >= 0.0 && o->inner_tol < 1.0)) return fail(SEM_ERR_INVALID_ARG, "inner_tol must be in [0, 1)");
         return SEM_OK;
     case SEM_FORM_FCG_LEARNED:
         if (!o->smoother) return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_FCG_LEARNED needs opts.smoother");
@@ -149,18 +174,23 @@ sem_status reset_state(CgState *d, int max_it, int hist_len, hipStream_t s)
 }
 
 // Iterate until the device flag says done; returns the final host state.
+// bf16: the float inner solve applies the BF16 matrix-core operator.
 template <typename T>
 sem_status iterate(const Mesh &m, double h1, double h2, const CgVecs<T> &v, CgState *st, double *hist,
-                   int check_every, hipStream_t s, CgState &h)
+                   int check_every, hipStream_t s, CgState &h, bool bf16 = false)
 {
     for (;;) {
         SEM_TRY(read_state(h, st, s));
         if (h.done) return SEM_OK;
         for (int q = 0; q < check_every; ++q) {
-            if constexpr (sizeof(T) == 8)
+            if constexpr (sizeof(T) == 8) {
                 SEM_HIP_TRY(launch_ax_f64_gather(m, h1, h2, v.p, v.w, v.part_e, s, &st->done));
-            else
-                SEM_HIP_TRY(launch_ax_f32_gather(m, (float)h1, (float)h2, v.p, v.w, v.part_e, s, &st->done));
+            } else {
+                if (bf16)
+                    SEM_HIP_TRY(launch_ax_bf16_gather(m, (float)h1, (float)h2, v.p, v.w, v.part_e, s, &st->done));
+                else
+                    SEM_HIP_TRY(launch_ax_f32_gather(m, (float)h1, (float)h2, v.p, v.w, v.part_e, s, &st->done));
+            }
             SEM_HIP_TRY(cg_step_after_ax<T>(m, v, st, hist, s));
         }
     }
@@ -221,7 +251,8 @@ sem_status solve_dc32(const Mesh &m, const sem_solve_opts &o, const Workspace &w
         SEM_HIP_TRY(cg_scale<float>(m, ws.v64.r, ws.b32, 1.0 / rn, s));
         SEM_TRY(reset_state(ws.st32, o.max_iter - total, 0, s));
         SEM_HIP_TRY(cg_init<float>(m, ws.v32, ws.b32, ws.st32, o.inner_tol, nullptr, s));
-        SEM_TRY(iterate<float>(m, o.h1, o.h2, ws.v32, ws.st32, nullptr, check_every, s, hi));
+        SEM_TRY(iterate<float>(m, o.h1, o.h2, ws.v32, ws.st32, nullptr, check_every, s, hi,
+                               o.form == SEM_FORM_DC_BF16));
         total += hi.it;
         SEM_HIP_TRY(cg_axpy<float>(m, ws.v64.x, ws.v32.x, rn, s));
         ++outer;
@@ -259,7 +290,10 @@ sem_status sem_ax(const sem_mesh *mesh, double h1, double h2, sem_dtype in, cons
         SEM_HIP_TRY(launch_ax_f32(m, (float)h1, (float)h2, (const float *)u, (float *)w, nullptr, s));
         return SEM_OK;
     case SEM_BF16:
-        return fail(SEM_ERR_UNSUPPORTED, "bf16 operator not available in this build");
+        if (!m.d_Gbf) return fail(SEM_ERR_INVALID_ARG, "mesh was created without SEM_PREP_BF16");
+        if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "the bf16 operator needs order N = 7");
+        SEM_HIP_TRY(launch_ax_bf16(m, (float)h1, (float)h2, (const uint16_t *)u, (float *)w, s));
+        return SEM_OK;
     default:
         return fail(SEM_ERR_INVALID_ARG, "unknown dtype");
     }
@@ -337,8 +371,12 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
     SEM_HIP_TRY(cg_gather<double>(m, b, ws.b64, s));
 
     CgState h{};
-    if (opts->form == SEM_FORM_DC_FP32)
+    if (opts->form == SEM_FORM_DC_FP32 || opts->form == SEM_FORM_DC_BF16)
         SEM_TRY(solve_dc32(m, *opts, ws, hist_len, s, check_every, rep, h));
+    else if (opts->form == SEM_FORM_FCG_INNER_FP32 || opts->form == SEM_FORM_FCG_INNER_BF16)
+        SEM_TRY(solve_fcg_nested(m, *opts, ws.v64, ws.v32, ws.b32, ws.b64, ws.z, ws.q, ws.st64, ws.st32, ws.hist,
+                                 hist_len, std::max(1, std::min(check_every, 4)),
+                                 opts->form == SEM_FORM_FCG_INNER_BF16, s, rep, h));
     else if (opts->form == SEM_FORM_FCG_LEARNED)
         SEM_TRY(solve_fcg(m, opts->smoother->s, *opts, ws.v64, ws.b64, ws.z, ws.q, ws.st64, ws.hist, hist_len,
                           check_every, s, rep, h));
@@ -348,7 +386,7 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
 
     rep->rel_res = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
     rep->true_rel_res = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
-    if (opts->history && opts->history_len > 0 && opts->form != SEM_FORM_DC_FP32) {
+    if (opts->history && opts->history_len > 0 && (opts->form == SEM_FORM_JACOBI_PCG || uses_fcg(opts->form))) {
         const int n = std::min(opts->history_len, std::min(h.it + 1, hist_len));
         SEM_HIP_TRY(hipMemcpyAsync(opts->history, ws.hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         SEM_HIP_TRY(hipStreamSynchronize(s));

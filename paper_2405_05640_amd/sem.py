@@ -22,7 +22,7 @@ SEM_OK, SEM_ERR_INVALID_ARG, SEM_ERR_OUT_OF_MEMORY, SEM_ERR_HIP, SEM_ERR_NOT_CON
 SEM_F64, SEM_F32, SEM_BF16 = 0, 1, 2
 SEM_PREP_F32, SEM_PREP_BF16 = 1, 2
 FIELD_GLO_NUM, FIELD_MULT, FIELD_MASK, FIELD_G, FIELD_B, FIELD_XYZ, FIELD_GLL, FIELD_DERIV = range(8)
-FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED = range(4)
+FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED, FORM_FCG_INNER_FP32, FORM_FCG_INNER_BF16 = range(6)
 SMOOTHER_PARAMS = 8208
 
 EXPORTED_SYMBOLS = [
@@ -59,7 +59,8 @@ class SolveOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("smoother", ctypes.c_void_p),
-                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int32)]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int32)]
 
 
 class SmootherDesc(ctypes.Structure):
@@ -263,10 +264,11 @@ class Mesh:
         return out
 
     def solve_opts(self, h1=1.0, h2=0.0, rel_tol=1e-10, max_iter=20000, check_every=16,
-                   form=FORM_JACOBI_PCG, max_outer=30, inner_tol=1e-4, smoother=None, history=None):
+                   form=FORM_JACOBI_PCG, max_outer=30, inner_tol=1e-4, smoother=None, history=None,
+                   inner_iters=8):
         o = SolveOpts()
         o.h1, o.h2, o.rel_tol, o.max_iter, o.check_every = h1, h2, rel_tol, max_iter, check_every
-        o.form, o.max_outer, o.inner_tol = form, max_outer, inner_tol
+        o.form, o.max_outer, o.inner_tol, o.inner_iters = form, max_outer, inner_tol, inner_iters
         o.smoother = smoother._h.value if smoother is not None else None
         if history is not None:
             o.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

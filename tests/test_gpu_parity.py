@@ -224,3 +224,61 @@ def test_dc_fp32_solve_reaches_fp64_tolerance(spec):
     assert np.sqrt(om.dot(e, om.apply_S(e, 1.0, h2))) <= 1e-6 * np.sqrt(om.dot(xo, om.apply_S(xo, 1.0, h2)))
     print("DC-FP32 %s: inner its %d, outer %d; FP64 PCG its %d" % (spec.name, rep.iterations,
                                                                   rep.outer_iterations, info["iterations"]))
+
+
+def test_ax_bf16_matrix_cores():
+    # bound against FP64 as for FP32 with eps = 2^-8, and closer to the
+    # oracle's BF16 emulation than that emulation is to FP64
+    import torch
+    from oracle import mixed
+    spec = wl.deformed_cube(3, 7)
+    om, gm = pair(spec, prepare=sem.SEM_PREP_BF16)
+    rng = np.random.default_rng(22)
+    u = mixed.bf16_round(rng.standard_normal(om.shape).astype(np.float32)).astype(np.float64)
+    ub = dev(u.astype(np.float32)).to(torch.bfloat16).view(torch.int16)
+    for h2 in (0.0, 0.1):
+        w = torch.empty(gm.shape, dtype=torch.float32, device="cuda")
+        gm.ax(ub, w, 1.0, h2, dtype=sem.SEM_BF16)
+        wg = host(w).astype(np.float64)
+        w64 = om.ax(u, 1.0, h2)
+        bound = (3 * (om.N + 1) + 6) * 2.0 ** -8 * om.ax_abs_bound(u, 1.0, h2)
+        assert np.all(np.abs(wg - w64) <= bound + 1e-30)
+        we = mixed.ax_lowp(om, u, 1.0, h2, "bf16")
+        assert np.linalg.norm(wg - we) <= np.linalg.norm(we - w64)
+
+
+@pytest.mark.parametrize("spec", [wl.deformed_cube(4, 7), wl.channel(3, 7)], ids=["deformed4_N7", "channel3_N7"])
+def test_dc_bf16_solve_reaches_fp64_tolerance(spec):
+    import torch
+    om, gm = pair(spec, prepare=sem.SEM_PREP_BF16)
+    h2 = 0.1 if spec.name.startswith("deformed") else 0.0
+    rng = np.random.default_rng(23)
+    b = om.rhs(rng.standard_normal(om.shape))
+    x = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
+    rep = gm.pcg_solve(dev(b), x, h1=1.0, h2=h2, rel_tol=1e-10, form=sem.FORM_DC_BF16, inner_tol=1e-2,
+                       max_outer=60)
+    xg = host(x)
+    r = b - om.apply_S(xg, 1.0, h2)
+    assert np.sqrt(om.dot(r, r) / om.dot(b, b)) <= 1.05e-10
+    print("DC-BF16 %s: inner its %d, outer %d" % (spec.name, rep.iterations, rep.outer_iterations))
+
+
+@pytest.mark.parametrize("form,prep", [(sem.FORM_FCG_INNER_FP32, sem.SEM_PREP_F32),
+                                       (sem.FORM_FCG_INNER_BF16, sem.SEM_PREP_BF16)], ids=["inner_fp32", "inner_bf16"])
+@pytest.mark.parametrize("spec", [wl.deformed_cube(4, 7), wl.channel(3, 7)], ids=["deformed4_N7", "channel3_N7"])
+def test_nested_fcg_reaches_fp64_tolerance(spec, form, prep):
+    import torch
+    om, gm = pair(spec, prepare=prep)
+    h2 = 0.1 if spec.name.startswith("deformed") else 0.0
+    rng = np.random.default_rng(24)
+    b = om.rhs(rng.standard_normal(om.shape))
+    x = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
+    rep = gm.pcg_solve(dev(b), x, h1=1.0, h2=h2, rel_tol=1e-10, form=form, inner_iters=8, inner_tol=0.0)
+    xg = host(x)
+    r = b - om.apply_S(xg, 1.0, h2)
+    assert np.sqrt(om.dot(r, r) / om.dot(b, b)) <= 1.05e-10
+    assert rep.fallback_used == 0 and rep.outer_iterations > 0
+    assert rep.iterations <= 8 * rep.outer_iterations + 8
+    _, info = om.pcg(b, 1.0, h2)
+    print("nested %s %s: %d outer, %d inner; FP64 PCG %d" % (spec.name, form, rep.outer_iterations, rep.iterations,
+                                                            info["iterations"]))

@@ -131,3 +131,26 @@ def test_fcg_fallback_paths_converge():
     assert info["fallback_at"] == 0
     r = b - m.apply_S(x, 1.0, 0.0)
     assert np.sqrt(m.dot(r, r) / m.dot(b, b)) <= 1.05e-10
+
+
+def test_bf16_rounding_and_lowp_operator_bounds():
+    from oracle import mixed
+    # rounding: exact values stay, ties go to even, relative error <= 2^-9
+    v = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7, 3.0, -2.5], dtype=np.float32)
+    r = mixed.bf16_round(v)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -7 and r[3] == 3.0 and r[4] == -2.5
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(10000).astype(np.float32)
+    assert np.max(np.abs(mixed.bf16_round(x) - x) / np.abs(x)) <= 2 ** -8   # unit roundoff (8-bit significand)
+    m = _mesh(wl.deformed_cube(2, 7, amp=0.2))
+    u = rng.standard_normal(m.shape)
+    w64 = m.ax(u, 1.0, 0.1)
+    bound = m.ax_abs_bound(u, 1.0, 0.1)
+    c = 3 * (m.N + 1) + 6
+    for prec, eps in (("f32", 2.0 ** -24), ("bf16", 2.0 ** -8)):
+        w = mixed.ax_lowp(m, u, 1.0, 0.1, prec)
+        assert np.all(np.abs(w - w64) <= c * eps * bound + 1e-30), prec
+    # bf16 is really coarser than f32
+    e16 = np.linalg.norm(mixed.ax_lowp(m, u, 1.0, 0.1, "bf16") - w64)
+    e32 = np.linalg.norm(mixed.ax_lowp(m, u, 1.0, 0.1, "f32") - w64)
+    assert e16 > 100 * e32
