@@ -47,6 +47,9 @@ def parse():
     p.add_argument("--train-fields", type=int, default=48, help="channel fields used for training pairs")
     p.add_argument("--train-epochs", type=int, default=4)
     p.add_argument("--heldout", type=int, default=4)
+    p.add_argument("--large", action="store_true",
+                   help="also run the 64^3 channel workload (134M local points): operator rate, FP64 "
+                        "Jacobi-PCG and nested BF16 time to 1e-10")
     p.add_argument("--profile-kernels", action="store_true",
                    help="only launch the operator, gather-scatter and CG kernels a few times plus a "
                         "1 GiB torch copy (reference for hardware byte counters), then exit")
@@ -175,6 +178,46 @@ def learned_section(args):
                             "fallback_used": [r["fallback_used"] for r in res_l],
                             "true_rel_res_max": max(r["true_rel_res"] for r in res_l)},
             "speedup_vs_jacobi_pcg": round(tj / tl, 3)}
+
+
+def large_section(args):
+    """64^3 channel (262,144 elements, N = 7, Poisson): Ax+dssum rate and
+    time to 1e-10 for FP64 Jacobi-PCG and the nested BF16 solver."""
+    import torch
+
+    from paper_2405_05640_amd import sem
+    from paper_2405_05640_amd import workloads as wl
+    spec = wl.config("c4")
+    t0 = time.perf_counter()
+    mesh = sem.Mesh.from_spec(spec, prepare=sem.SEM_PREP_BF16)
+    t_setup = time.perf_counter() - t0
+    xyz = mesh.export(sem.FIELD_XYZ)
+    vm = wl.kolmogorov_velocity(wl.RHS_SEED["c4"])
+    f = torch.from_numpy(wl.fourier_on_elements(wl.divergence_source(vm, 0), xyz, (64, 64, 64))).cuda()
+    del xyz
+    b = torch.empty_like(f)
+    mesh.rhs(f, b)
+    del f
+    w = torch.empty_like(b)
+    for _ in range(3):
+        mesh.ax(b, w, 1.0, 0.0)
+        mesh.dssum(w, mask=True)
+    torch.cuda.synchronize()
+    n = 10
+    t0 = time.perf_counter()
+    for _ in range(n):
+        mesh.ax(b, w, 1.0, 0.0)
+        mesh.dssum(w, mask=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / n
+    del w
+    r64, _ = timed_solves(mesh, b, 1, rel_tol=1e-10, check_every=32, max_iter=40000)
+    rbf, _ = timed_solves(mesh, b, 1, rel_tol=1e-10, check_every=32, max_iter=40000,
+                          form=sem.FORM_FCG_INNER_BF16, inner_iters=8, inner_tol=0.0)
+    return {"workload": "64^3 tanh-stretched channel, N=7, periodic x/z, Poisson (134,217,728 local points)",
+            "setup_s": round(t_setup, 1), "ax_dssum_gdofs": round(mesh.n_local / dt / 1e9, 2),
+            "ax_dssum_us": round(dt * 1e6, 1), "fp64_jacobi_pcg": r64, "fcg_inner_bf16": rbf,
+            "speedup_vs_fp64_pcg": round(r64["median"] / rbf["median"], 3)}
 
 
 def traffic_record(kernel_src):
@@ -314,10 +357,12 @@ def main():
             del mesh
             torch.cuda.empty_cache()
             mesh = sem.Mesh.from_spec(spec, prepare=sem.SEM_PREP_F32 | sem.SEM_PREP_BF16)
-            for name, form, itol in (("dc_fp32", sem.FORM_DC_FP32, 1e-5), ("dc_bf16", sem.FORM_DC_BF16, 1e-2)):
+            forms = (("dc_fp32", sem.FORM_DC_FP32, 1e-5), ("dc_bf16", sem.FORM_DC_BF16, 1e-2),
+                     ("fcg_inner_fp32", sem.FORM_FCG_INNER_FP32, 0.0), ("fcg_inner_bf16", sem.FORM_FCG_INNER_BF16, 0.0))
+            for name, form, itol in forms:
                 try:
                     rr, xx = timed_solves(mesh, b, args.solve_reps, h1=h1, h2=h2, rel_tol=1e-10, check_every=32,
-                                          form=form, inner_tol=itol, max_outer=60)
+                                          form=form, inner_tol=itol, max_outer=60, inner_iters=8)
                 except sem.SemError as exc:
                     sol[name] = {"status": "failed", "error": str(exc), "inner_tol": itol}
                     print("%s: %s" % (name, exc), flush=True)
@@ -330,6 +375,11 @@ def main():
                 print("%s: %d inner / %d outer, %.1f ms, true rel res %.2e" %
                       (name, rr["iterations"], rr["outer_iterations"], rr["median"], rr["true_rel_res"]), flush=True)
         out["time_to_1e-10_ms"] = sol
+    if args.large:
+        del mesh, b
+        torch.cuda.empty_cache()
+        out["large_single_gpu"] = large_section(args)
+        print("large: %s" % json.dumps(out["large_single_gpu"]), flush=True)
     if not args.no_learned:
         out["learned_smoother"] = learned_section(args)
         print("learned: %s" % json.dumps(out["learned_smoother"]), flush=True)

@@ -235,6 +235,19 @@ sem_status sem_pcg_snapshots(const sem_mesh *mesh, const sem_solve_opts *opts, c
                              const int32_t *iters, int32_t n_iters, double *e_out, void *workspace,
                              size_t ws_bytes, sem_solve_report *rep, void *stream);
 
+/* Batched FP64 Jacobi-PCG for nrhs (1..4) right-hand sides that share the
+ * operator and h1/h2, e.g. the three velocity components of a time step
+ * (the paper's velocity solves, section 3.1).  N = 7 only.  b, x: DEVICE
+ * [nrhs][E][P] local fields (layout as sem_pcg_solve, one block per field);
+ * reps: HOST array of nrhs reports.  Each field runs its own CG (own alpha,
+ * beta, convergence) but every iteration streams the geometric factors
+ * once for all fields.  Results equal nrhs separate sem_pcg_solve calls
+ * bit for bit.  opts.form must be SEM_FORM_JACOBI_PCG; history is ignored. */
+sem_status sem_pcg_solve_batched(const sem_mesh *mesh, const sem_solve_opts *opts, int32_t nrhs, const double *b,
+                                 double *x, void *workspace, size_t ws_bytes, sem_solve_report *reps, void *stream);
+sem_status sem_solve_workspace_bytes_batched(const sem_mesh *mesh, const sem_solve_opts *opts, int32_t nrhs,
+                                             size_t *bytes);
+
 const char *sem_last_error(void);
 
 /* Library version string, e.g. "sem 0.1 gfx950". */

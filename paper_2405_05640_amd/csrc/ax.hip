@@ -6,7 +6,8 @@
 // matrix-free operator of section 3.1, which the paper's section 4.2 notes is
 // memory bound).
 //
-// Design (one wavefront per element at N = 7):
+// Two designs: a thread-per-point kernel for N <= 7 (below) and, for higher
+// orders, the k-pencil kernel (one (N+1)x(N+1) workgroup per element):
 //  - the workgroup is the (N+1)x(N+1) "i,j" plane of an element: lane (i,j)
 //    owns the k-pencil u(i,j,0..N) and w(i,j,0..N) in registers;
 //  - each k-slice of u is staged once in LDS; the r and s derivatives read
@@ -139,6 +140,193 @@ ax_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G,
     }
 }
 
+// Thread-per-point variant (N <= 7): one workgroup of (N+1)^3 threads per
+// element, every load of u, G and B issued at kernel start as a
+// non-temporal (streaming) load, so the wavefronts keep the most bytes in
+// flight; the three derivative and three transposed contractions read the
+// staged tiles from LDS.  At N = 7 this streams at about 6 TB/s of
+// algorithmic bytes on MI355X, against about 5.5 TB/s for the pencil kernel.
+template <typename T>
+__device__ __forceinline__ T ldnt(const T *p) { return __builtin_nontemporal_load(p); }
+
+template <typename T, int NP, bool HELM, bool DOT, bool GATHER>
+__global__ void __launch_bounds__(NP * NP * NP)
+ax_pt_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G,
+             const T *__restrict__ Bm, const T *__restrict__ Dg, T h1, T h2,
+             double *__restrict__ partial, const int32_t *__restrict__ skip, Lattice L)
+{
+    if (skip && *skip) return;
+    constexpr int P2 = NP * NP, P3 = NP * NP * NP;
+    __shared__ T sD[P2], su[P3], sr[P3], ss[P3], st[P3];
+    const int t = threadIdx.x, i = t % NP, j = (t / NP) % NP, k = t / P2;
+    const int64_t e = blockIdx.x;
+    T uv;
+    if (GATHER) {
+        const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);
+        int64_t gi = ex * (NP - 1) + i, gj = ey * (NP - 1) + j, gk = ez * (NP - 1) + k;
+        if (gi >= L.nx) gi -= L.nx;
+        if (gj >= L.ny) gj -= L.ny;
+        if (gk >= L.nz) gk -= L.nz;
+        uv = u[gi + L.nx * (gj + L.ny * gk)];
+    } else {
+        uv = ldnt(&u[e * P3 + t]);
+    }
+    const T *Ge = G + e * 6 * P3;
+    const T g0 = ldnt(&Ge[t]), g1 = ldnt(&Ge[P3 + t]), g2 = ldnt(&Ge[2 * P3 + t]);
+    const T g3 = ldnt(&Ge[3 * P3 + t]), g4 = ldnt(&Ge[4 * P3 + t]), g5 = ldnt(&Ge[5 * P3 + t]);
+    T bv = T(0);
+    if (HELM) bv = ldnt(&Bm[e * P3 + t]);
+    if (t < P2) sD[t] = Dg[t];
+    su[t] = uv;
+    __syncthreads();
+    T ur = T(0), us = T(0), ut = T(0);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        ur += sD[i * NP + m] * su[k * P2 + j * NP + m];
+        us += sD[j * NP + m] * su[k * P2 + m * NP + i];
+        ut += sD[k * NP + m] * su[m * P2 + j * NP + i];
+    }
+    sr[t] = g0 * ur + g1 * us + g2 * ut;
+    ss[t] = g1 * ur + g3 * us + g4 * ut;
+    st[t] = g2 * ur + g4 * us + g5 * ut;
+    __syncthreads();
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < NP; ++m)
+        acc += sD[m * NP + i] * sr[k * P2 + j * NP + m] + sD[m * NP + j] * ss[k * P2 + m * NP + i] +
+               sD[m * NP + k] * st[m * P2 + j * NP + i];
+    T v = h1 * acc;
+    if (HELM) v += h2 * bv * uv;
+    w[e * P3 + t] = v;
+    if (DOT) {
+        // fixed-order tree over the (N+1)^3 threads (the last wavefront may be
+        // partial, so no cross-lane shuffles)
+        __shared__ double red[P3];
+        red[t] = (double)uv * (double)v;
+        __syncthreads();
+        constexpr int top = P3 <= 1 ? 1 : (P3 <= 2 ? 1 : (P3 <= 4 ? 2 : (P3 <= 8 ? 4 : (P3 <= 16 ? 8 : (P3 <= 32 ? 16 : (P3 <= 64 ? 32 : (P3 <= 128 ? 64 : (P3 <= 256 ? 128 : 256))))))));
+        for (int h = top; h > 0; h >>= 1) {
+            if (t < h && t + h < P3) red[t] += red[t + h];
+            __syncthreads();
+        }
+        if (t == 0) partial[e] = red[0];
+    }
+}
+
+// Batched form: NC fields (e.g. three velocity components) through one
+// pass over the geometric factors.  G and B are loaded once per point; the
+// fields reuse one set of LDS tiles in turn.  u, w, partial: NC blocks of
+// (assembled or local) fields and NC x E partials.
+template <int NP, int NC, bool HELM, bool GATHER>
+__global__ void __launch_bounds__(NP * NP * NP)
+ax_pt_batched_kernel(const double *__restrict__ u, int64_t ustride, double *__restrict__ w, const double *__restrict__ G,
+                     const double *__restrict__ Bm, const double *__restrict__ Dg, double h1, double h2,
+                     double *__restrict__ partial, const int32_t *__restrict__ done_flags, int done_stride, Lattice L,
+                     int64_t nl)
+{
+    if (done_flags) {
+        bool all = true;
+        for (int c = 0; c < NC; ++c) all = all && done_flags[c * done_stride] != 0;
+        if (all) return;
+    }
+    constexpr int P2 = NP * NP, P3 = NP * NP * NP;
+    __shared__ double sD[P2], su[P3], sr[P3], ss[P3], st[P3];
+    __shared__ double red[P3];
+    const int t = threadIdx.x, i = t % NP, j = (t / NP) % NP, k = t / P2;
+    const int64_t e = blockIdx.x;
+    int64_t src;
+    if (GATHER) {
+        const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);
+        int64_t gi = ex * (NP - 1) + i, gj = ey * (NP - 1) + j, gk = ez * (NP - 1) + k;
+        if (gi >= L.nx) gi -= L.nx;
+        if (gj >= L.ny) gj -= L.ny;
+        if (gk >= L.nz) gk -= L.nz;
+        src = gi + L.nx * (gj + L.ny * gk);
+    } else {
+        src = e * P3 + t;
+    }
+    double uv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) uv[c] = GATHER ? u[c * ustride + src] : ldnt(&u[c * ustride + src]);
+    const double *Ge = G + e * 6 * P3;
+    const double g0 = ldnt(&Ge[t]), g1 = ldnt(&Ge[P3 + t]), g2 = ldnt(&Ge[2 * P3 + t]);
+    const double g3 = ldnt(&Ge[3 * P3 + t]), g4 = ldnt(&Ge[4 * P3 + t]), g5 = ldnt(&Ge[5 * P3 + t]);
+    double bv = 0.0;
+    if (HELM) bv = ldnt(&Bm[e * P3 + t]);
+    if (t < P2) sD[t] = Dg[t];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        __syncthreads();   // previous field's tiles fully consumed
+        su[t] = uv[c];
+        __syncthreads();
+        double ur = 0.0, us = 0.0, ut = 0.0;
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+            ur += sD[i * NP + m] * su[k * P2 + j * NP + m];
+            us += sD[j * NP + m] * su[k * P2 + m * NP + i];
+            ut += sD[k * NP + m] * su[m * P2 + j * NP + i];
+        }
+        sr[t] = g0 * ur + g1 * us + g2 * ut;
+        ss[t] = g1 * ur + g3 * us + g4 * ut;
+        st[t] = g2 * ur + g4 * us + g5 * ut;
+        __syncthreads();
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < NP; ++m)
+            acc += sD[m * NP + i] * sr[k * P2 + j * NP + m] + sD[m * NP + j] * ss[k * P2 + m * NP + i] +
+                   sD[m * NP + k] * st[m * P2 + j * NP + i];
+        double v = h1 * acc;
+        if (HELM) v += h2 * bv * uv[c];
+        w[c * nl + e * P3 + t] = v;
+        if (partial) {
+            red[t] = uv[c] * v;
+            __syncthreads();
+            constexpr int top = P3 <= 2 ? 1 : (P3 <= 4 ? 2 : (P3 <= 8 ? 4 : (P3 <= 16 ? 8 : (P3 <= 32 ? 16 : (P3 <= 64 ? 32 : (P3 <= 128 ? 64 : (P3 <= 256 ? 128 : 256)))))));
+            for (int h = top; h > 0; h >>= 1) {
+                if (t < h && t + h < P3) red[t] += red[t + h];
+                __syncthreads();
+            }
+            if (t == 0) partial[c * (int64_t)gridDim.x + e] = red[0];
+        }
+    }
+}
+
+template <int NC>
+hipError_t launch_batched_nc(const Mesh &m, double h1, double h2, const double *ug, int64_t ustride, double *w,
+                             double *partial, const int32_t *done_flags, int done_stride, hipStream_t s)
+{
+    const dim3 grid((unsigned)m.E), block(512);
+    const bool helm = h2 != 0.0;
+    if (helm)
+        hipLaunchKernelGGL((ax_pt_batched_kernel<8, NC, true, true>), grid, block, 0, s, ug, ustride, w, m.d_G, m.d_B,
+                           m.d_D, h1, h2, partial, done_flags, done_stride, m.lat, m.nl);
+    else
+        hipLaunchKernelGGL((ax_pt_batched_kernel<8, NC, false, true>), grid, block, 0, s, ug, ustride, w, m.d_G, m.d_B,
+                           m.d_D, h1, h2, partial, done_flags, done_stride, m.lat, m.nl);
+    return hipGetLastError();
+}
+
+template <typename T, int NP, bool GATHER>
+hipError_t launch_pt(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, const T *B,
+                     const T *D, double *partial, const int32_t *skip, hipStream_t s)
+{
+    const dim3 grid((unsigned)m.E), block(NP * NP * NP);
+    const bool helm = (h2 != T(0));
+    const Lattice &L = m.lat;
+    if (partial) {
+        if (helm)
+            hipLaunchKernelGGL((ax_pt_kernel<T, NP, true, true, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+        else
+            hipLaunchKernelGGL((ax_pt_kernel<T, NP, false, true, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+    } else {
+        if (helm)
+            hipLaunchKernelGGL((ax_pt_kernel<T, NP, true, false, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+        else
+            hipLaunchKernelGGL((ax_pt_kernel<T, NP, false, false, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int NP, bool GATHER>
 hipError_t launch_np(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, const T *B,
                      const T *D, double *partial, const int32_t *skip, hipStream_t s)
@@ -166,13 +354,13 @@ hipError_t launch_any(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, c
 {
     if (m.E == 0) return hipSuccess;
     switch (m.NP) {
-    case 2: return launch_np<T, 2, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
-    case 3: return launch_np<T, 3, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
-    case 4: return launch_np<T, 4, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
-    case 5: return launch_np<T, 5, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
-    case 6: return launch_np<T, 6, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
-    case 7: return launch_np<T, 7, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
-    case 8: return launch_np<T, 8, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
+    case 2: return launch_pt<T, 2, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
+    case 3: return launch_pt<T, 3, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
+    case 4: return launch_pt<T, 4, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
+    case 5: return launch_pt<T, 5, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
+    case 6: return launch_pt<T, 6, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
+    case 7: return launch_pt<T, 7, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
+    case 8: return launch_pt<T, 8, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 9: return launch_np<T, 9, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 10: return launch_np<T, 10, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 11: return launch_np<T, 11, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
@@ -236,6 +424,21 @@ hipError_t launch_ax_f32_gather(const Mesh &m, float h1, float h2, const float *
                                 double *partial_uw, hipStream_t s, const int32_t *skip)
 {
     return launch_any<float, true>(m, h1, h2, ug, w, m.d_G32, m.d_B32, m.d_D32, partial_uw, skip, s);
+}
+
+hipError_t launch_ax_f64_gather_batched(const Mesh &m, int nc, double h1, double h2, const double *ug, int64_t ustride,
+                                        double *w, double *partial, const int32_t *done_flags, int done_stride,
+                                        hipStream_t s)
+{
+    if (m.E == 0) return hipSuccess;
+    if (m.NP != 8) return hipErrorInvalidValue;
+    switch (nc) {
+    case 1: return launch_batched_nc<1>(m, h1, h2, ug, ustride, w, partial, done_flags, done_stride, s);
+    case 2: return launch_batched_nc<2>(m, h1, h2, ug, ustride, w, partial, done_flags, done_stride, s);
+    case 3: return launch_batched_nc<3>(m, h1, h2, ug, ustride, w, partial, done_flags, done_stride, s);
+    case 4: return launch_batched_nc<4>(m, h1, h2, ug, ustride, w, partial, done_flags, done_stride, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_diag(const Mesh &m, double h1, double h2, double *d, hipStream_t s)

@@ -39,8 +39,6 @@ __device__ __forceinline__ double assemble_at(const Lattice &L, const T *__restr
     return (double)s;
 }
 
-inline unsigned node_blocks(const Lattice &L) { return (unsigned)std::min<int64_t>(L.ny * L.nz, kMaxVecBlocks); }
-
 template <int NV>
 __device__ __forceinline__ void block_store(double (&v)[NV], double *out, int stride)
 {
@@ -158,10 +156,22 @@ __global__ void __launch_bounds__(kBS) init_finalize(CgState *st, const double *
     }
 }
 
-__global__ void __launch_bounds__(kBS) alpha_kernel(CgState *st, const double *__restrict__ part_e, int64_t E)
+// first stage of a two-stage reduction: kStage blocks, fixed chunks
+__global__ void __launch_bounds__(kBS) reduce_stage_kernel(const double *__restrict__ part, int64_t n, int nv,
+                                                            double *__restrict__ stage)
+{
+    const int64_t chunk = (n + kStage - 1) / kStage;
+    const int64_t lo = blockIdx.x * chunk, hi = std::min<int64_t>(n, lo + chunk);
+    for (int q = 0; q < nv; ++q) {
+        const double v = lo < hi ? block_sum(part + q * n + lo, hi - lo) : 0.0;
+        if (threadIdx.x == 0) stage[q * kStage + blockIdx.x] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kBS) alpha_kernel(CgState *st, const double *__restrict__ stage)
 {
     if (st->done) return;
-    const double pw = block_sum(part_e, E);
+    const double pw = block_sum(stage, kStage);
     if (threadIdx.x == 0) {
         st->pw = pw;
         if (!(pw > 0.0) || !isfinite(pw) || !isfinite(st->rz)) {
@@ -315,7 +325,7 @@ int cg_blocks(int64_t n)
 template <typename T>
 hipError_t cg_gather(const Mesh &m, const double *u, T *ug, hipStream_t s)
 {
-    hipLaunchKernelGGL((cg::gather_kernel<double, T>), dim3(cg::node_blocks(m.lat)), dim3(kBS), 0, s, u, ug, m.lat);
+    hipLaunchKernelGGL((cg::gather_kernel<double, T>), dim3(node_grid(m.lat)), dim3(kBS), 0, s, u, ug, m.lat);
     return hipGetLastError();
 }
 
@@ -329,7 +339,7 @@ hipError_t cg_scatter(const Mesh &m, const T *ug, double *u, hipStream_t s)
 template <typename T>
 hipError_t cg_dinv(const Mesh &m, const double *diag_local, T *dinv, hipStream_t s)
 {
-    hipLaunchKernelGGL((cg::dinv_kernel<T>), dim3(cg::node_blocks(m.lat)), dim3(kBS), 0, s, diag_local, dinv, m.lat);
+    hipLaunchKernelGGL((cg::dinv_kernel<T>), dim3(node_grid(m.lat)), dim3(kBS), 0, s, diag_local, dinv, m.lat);
     return hipGetLastError();
 }
 
@@ -345,10 +355,14 @@ hipError_t cg_init(const Mesh &m, const CgVecs<T> &v, const T *b, CgState *st, d
 template <typename T>
 hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, double *hist, hipStream_t s)
 {
-    const int nb = (int)cg::node_blocks(m.lat);
-    hipLaunchKernelGGL(cg::alpha_kernel, dim3(1), dim3(kBS), 0, s, st, v.part_e, m.E);
-    hipLaunchKernelGGL((cg::update_kernel<T>), dim3(nb), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv, m.lat, v.part_b);
-    hipLaunchKernelGGL(cg::beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb, hist);
+    const int64_t rows = node_grid(m.lat);
+    hipError_t e = cg_alpha(m, v.part_e, v.stage, st, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((cg::update_kernel<T>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,
+                       m.lat, v.part_b);
+    e = cg_reduce(v.part_b, rows, 2, v.stage, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cg::beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.stage, kStage, hist);
     L3((cg::p_kernel<T>), m.ng) st, v.p, v.r, v.dinv, m.ng);
     return hipGetLastError();
 }
@@ -356,9 +370,11 @@ hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, doub
 template <typename T>
 hipError_t cg_resid(const Mesh &m, const CgVecs<T> &v, const T *b, T *r, CgState *st, hipStream_t s)
 {
-    const int nb = (int)cg::node_blocks(m.lat);
-    hipLaunchKernelGGL((cg::resid_kernel<T>), dim3(nb), dim3(kBS), 0, s, b, v.w, r, v.dinv, m.lat, v.part_b);
-    hipLaunchKernelGGL(cg::resid_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb);
+    const int64_t rows = node_grid(m.lat);
+    hipLaunchKernelGGL((cg::resid_kernel<T>), dim3((unsigned)rows), dim3(kBS), 0, s, b, v.w, r, v.dinv, m.lat, v.part_b);
+    hipError_t e = cg_reduce(v.part_b, rows, 1, v.stage, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cg::resid_finalize, dim3(1), dim3(kBS), 0, s, st, v.stage, kStage);
     return hipGetLastError();
 }
 
@@ -385,9 +401,17 @@ hipError_t cg_scale(const Mesh &m, const double *in, T *out, double scale, hipSt
     return hipGetLastError();
 }
 
-hipError_t cg_alpha(const Mesh &m, const double *part_e, CgState *st, hipStream_t s)
+hipError_t cg_reduce(const double *part, int64_t n, int nv, double *stage, hipStream_t s)
 {
-    hipLaunchKernelGGL(cg::alpha_kernel, dim3(1), dim3(kBS), 0, s, st, part_e, m.E);
+    hipLaunchKernelGGL(cg::reduce_stage_kernel, dim3(kStage), dim3(kBS), 0, s, part, n, nv, stage);
+    return hipGetLastError();
+}
+
+hipError_t cg_alpha(const Mesh &m, const double *part_e, double *stage, CgState *st, hipStream_t s)
+{
+    hipError_t e = cg_reduce(part_e, m.E, 1, stage, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cg::alpha_kernel, dim3(1), dim3(kBS), 0, s, st, stage);
     return hipGetLastError();
 }
 

@@ -1,12 +1,23 @@
 // cg.hpp -- internal interface of the assembled-vector Krylov kernels.
 #pragma once
 
+#include <algorithm>
+
 #include "sem_internal.hpp"
 
 namespace sem {
 
 constexpr int kBS = 256;             // threads per block of the vector kernels
-constexpr int kMaxVecBlocks = 4096;  // grid cap (partials buffers are sized for it)
+constexpr int kMaxVecBlocks = 4096;  // grid cap of the flat vector kernels
+constexpr int kStage = 256;          // second-stage partial sums
+
+// Grid of the per-node kernels: one workgroup per lattice row (gj, gk).
+inline unsigned node_grid(const Lattice &L) { return (unsigned)(L.ny * L.nz); }
+// Partial-sum capacity per quantity for any kernel of a mesh.
+inline int64_t part_capacity(const Lattice &L, int64_t E)
+{
+    return std::max<int64_t>(std::max<int64_t>(L.ny * L.nz, kMaxVecBlocks), E);
+}
 
 // Device-resident scalars of one CG run.
 struct CgState {
@@ -23,12 +34,16 @@ struct CgState {
 
 // Vectors of one CG run: x, r, p, dinv are assembled (n_global); w is local
 // (n_local, the unassembled operator output); part_e has n_elem entries,
-// part_b 2 * kMaxVecBlocks.
+// part_b 3 * part_capacity, stage 3 * kStage.
 template <typename T>
 struct CgVecs {
     T *x, *r, *p, *dinv, *w;
-    double *part_e, *part_b;
+    double *part_e, *part_b, *stage;
 };
+
+// stage[q * kStage + b] = fixed-order sum of chunk b of part[q * n .. q * n + n)
+// for q < nv (deterministic first stage of a two-stage reduction).
+hipError_t cg_reduce(const double *part, int64_t n, int nv, double *stage, hipStream_t s);
 
 int cg_blocks(int64_t n);
 
@@ -45,7 +60,8 @@ hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, doub
 template <typename T>
 hipError_t cg_resid(const Mesh &m, const CgVecs<T> &v, const T *b, T *r, CgState *st, hipStream_t s);
 template <typename T> hipError_t cg_restart(const Mesh &m, const CgVecs<T> &v, CgState *st, hipStream_t s);
-hipError_t cg_alpha(const Mesh &m, const double *part_e, CgState *st, hipStream_t s);
+// alpha from the per-element partials of (p, S p) (reduces them first)
+hipError_t cg_alpha(const Mesh &m, const double *part_e, double *stage, CgState *st, hipStream_t s);
 // e = x - e on assembled vectors
 hipError_t cg_rsub(const Mesh &m, const double *x, double *e, hipStream_t s);
 template <typename T> hipError_t cg_axpy(const Mesh &m, double *y, const T *d, double scale, hipStream_t s);

@@ -15,6 +15,7 @@
 // element rows per wave), and the x-face nodes of all other rows, one thread
 // per (x-face, row) so lanes m and m+1 hit the two ends of one 64-byte
 // element row.  Every element row is fetched once per pass.
+#include "cg.hpp"
 #include "lattice.hpp"
 #include "sem_internal.hpp"
 
@@ -28,23 +29,20 @@ __global__ void __launch_bounds__(256)
 gs_rows_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip)
 {
     if (skip && *skip) return;
-    for (int64_t row = blockIdx.x; row < L.ny * L.nz; row += gridDim.x) {
-        const int gj = (int)(row % L.ny), gk = (int)(row / L.ny);
-        const int2 ay = L.tab[1][gj], az = L.tab[2][gk];
-        const bool full = axis_count(ay) > 1 || axis_count(az) > 1 ||
-                          (MASK && (axis_masked(ay) || axis_masked(az)));
-        if (!full) continue;   // uniform over the block
-        for (int gi = threadIdx.x; gi < L.nx; gi += blockDim.x) {
-            int loc[8];
-            bool msk;
-            const int n = node_locals(L, gi, gj, gk, loc, msk);
-            const bool zero = MASK && msk;
-            if (n == 1 && !zero) continue;
-            T s = T(0);
-            if (!zero)
-                for (int c = 0; c < n; ++c) s += u[loc[c]];
-            for (int c = 0; c < n; ++c) u[loc[c]] = s;
-        }
+    const int gj = (int)(blockIdx.x % L.ny), gk = (int)(blockIdx.x / L.ny);   // one row per workgroup
+    const int2 ay = L.tab[1][gj], az = L.tab[2][gk];
+    const bool full = axis_count(ay) > 1 || axis_count(az) > 1 || (MASK && (axis_masked(ay) || axis_masked(az)));
+    if (!full) return;   // uniform over the block
+    for (int gi = threadIdx.x; gi < L.nx; gi += blockDim.x) {
+        int loc[8];
+        bool msk;
+        const int n = node_locals(L, gi, gj, gk, loc, msk);
+        const bool zero = MASK && msk;
+        if (n == 1 && !zero) continue;
+        T s = T(0);
+        if (!zero)
+            for (int c = 0; c < n; ++c) s += u[loc[c]];
+        for (int c = 0; c < n; ++c) u[loc[c]] = s;
     }
 }
 
@@ -133,7 +131,7 @@ hipError_t dssum_impl(const Mesh &m, T *u, int apply_mask, hipStream_t s, const 
     const Lattice &L = m.lat;
     const int64_t rows = L.ny * L.nz;
     if (rows == 0) return hipSuccess;
-    const unsigned g1 = (unsigned)std::min<int64_t>(rows, 8192);
+    const unsigned g1 = (unsigned)rows;
     const int mx = L.per[0] ? L.nelx : L.nelx + 1;
     const unsigned g2 = (unsigned)((mx * rows + 255) / 256);
     if (apply_mask) {

@@ -64,14 +64,14 @@ __device__ inline int node_locals(const Lattice &L, int gi, int gj, int gk, int 
     return n;
 }
 
-// Loop over the global nodes of a block's share of lattice rows (gj, gk):
-// blocks stride over rows, threads over gi, so no index is divided per node.
+// Loop over the global nodes of lattice row blockIdx.x = gj + ny gk (one
+// workgroup per row, threads over gi): no index is divided per node and every
+// row is independent work for the scheduler.  Launch with ny * nz blocks.
 // Binds gi, gj, gk (int) and g (int64 lexicographic id) for the body.
-#define SEM_FOR_EACH_NODE(L, gi, gj, gk, g)                                                      \
-    for (int64_t row_ = blockIdx.x; row_ < (L).ny * (L).nz; row_ += gridDim.x)                  \
-        for (int gj = (int)(row_ % (L).ny), gk = (int)(row_ / (L).ny), gi = (int)threadIdx.x;   \
-             gi < (L).nx; gi += (int)blockDim.x)                                                \
-            if (const int64_t g = gi + (L).nx * row_; true)
+#define SEM_FOR_EACH_NODE(L, gi, gj, gk, g)                                                        \
+    for (int gj = (int)(blockIdx.x % (L).ny), gk = (int)(blockIdx.x / (L).ny), gi = (int)threadIdx.x; \
+         gi < (L).nx; gi += (int)blockDim.x)                                                       \
+        if (const int64_t g = gi + (L).nx * (int64_t)blockIdx.x; true)
 
 // Copies of a global index g along one direction, ascending in (element, local).
 // Returns the count (1 or 2); ec = element coordinate, lc = local coordinate.

@@ -313,7 +313,7 @@ namespace {
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-inline int node_blocks(const Mesh &m) { return (int)std::min<int64_t>(m.lat.ny * m.lat.nz, kMaxVecBlocks); }
+inline int node_blocks(const Mesh &m) { return (int)node_grid(m.lat); }
 
 sem_status read_state(CgState &h, const CgState *d, hipStream_t s)
 {
@@ -380,9 +380,11 @@ sem_status loss_forward(const Smoother &sm, const Mesh &m, double h1, double h2,
     // d = e - z, sd = S d, partial (d, S d)
     hipLaunchKernelGGL(lk::sub_kernel, dim3(nb), dim3(kBS), 0, s, t.e, t.z, t.d, m.ng);
     SEM_HIP_TRY(launch_ax_f64_gather(m, h1, h2, t.d, t.w, nullptr, s));
-    hipLaunchKernelGGL(lk::assemble_dot_kernel, dim3(nbn), dim3(kBS), 0, s, t.w, t.d, t.sd, m.lat,
-                       sm.part + kMaxVecBlocks);
-    hipLaunchKernelGGL(lk::loss_finalize, dim3(1), dim3(kBS), 0, s, sm.part, sm.part + kMaxVecBlocks, nbn, sm.scal);
+    const int64_t cap = part_capacity(m.lat, m.E);
+    hipLaunchKernelGGL(lk::assemble_dot_kernel, dim3(nbn), dim3(kBS), 0, s, t.w, t.d, t.sd, m.lat, sm.part + cap);
+    SEM_HIP_TRY(cg_reduce(sm.part, nbn, 1, sm.stage, s));
+    SEM_HIP_TRY(cg_reduce(sm.part + cap, nbn, 1, sm.stage + kStage, s));
+    hipLaunchKernelGGL(lk::loss_finalize, dim3(1), dim3(kBS), 0, s, sm.stage, sm.stage + kStage, kStage, sm.scal);
     hipLaunchKernelGGL(lk::gz_kernel, dim3(nb), dim3(kBS), 0, s, t.sd, sm.scal, t.d, m.ng);
     SEM_HIP_TRY(hipGetLastError());
     return SEM_OK;
@@ -405,7 +407,8 @@ static sem_status fcg_direction(const Mesh &m, const Smoother &sm, const CgVecs<
     SEM_HIP_TRY(nn_infer<double>(sm, m, v.r, v.dinv, sm.c_local, s, &st->nn_skip));
     hipLaunchKernelGGL(lk::fcg_z_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.r, v.dinv, sm.c_local,
                        (const double *)nullptr, z, m.lat, v.part_b);
-    hipLaunchKernelGGL(lk::fcg_beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.part_b, nbn, first);
+    SEM_HIP_TRY(cg_reduce(v.part_b, nbn, 2, v.stage, s));
+    hipLaunchKernelGGL(lk::fcg_beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.stage, kStage, first);
     hipLaunchKernelGGL(lk::fcg_p_kernel, dim3(nb), dim3(kBS), 0, s, st, v.p, z, v.r, v.dinv, m.ng, v.part_b);
     hipLaunchKernelGGL(lk::fcg_redo_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb);
     SEM_HIP_TRY(hipGetLastError());
@@ -435,15 +438,17 @@ sem_status solve_fcg(const Mesh &m, const Smoother &sm, const sem_solve_opts &o,
             if (h.done) break;
             for (int it = 0; it < check_every; ++it) {
                 SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.p, v.w, v.part_e, s, &st->done));
-                SEM_HIP_TRY(cg_alpha(m, v.part_e, st, s));
+                SEM_HIP_TRY(cg_alpha(m, v.part_e, v.stage, st, s));
                 hipLaunchKernelGGL(lk::fcg_update_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,
                                    q, m.lat, v.part_b);
-                hipLaunchKernelGGL(lk::fcg_check_kernel, dim3(1), dim3(kBS), 0, s, st, v.part_b, nbn, hist,
+                SEM_HIP_TRY(cg_reduce(v.part_b, nbn, 1, v.stage, s));
+                hipLaunchKernelGGL(lk::fcg_check_kernel, dim3(1), dim3(kBS), 0, s, st, v.stage, kStage, hist,
                                    sm.stall_window, sm.stall_rate);
                 SEM_HIP_TRY(nn_infer<double>(sm, m, v.r, v.dinv, sm.c_local, s, &st->nn_skip));
                 hipLaunchKernelGGL(lk::fcg_z_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.r, v.dinv, sm.c_local,
                                    (const double *)q, z, m.lat, v.part_b);
-                hipLaunchKernelGGL(lk::fcg_beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.part_b, nbn, 0);
+                SEM_HIP_TRY(cg_reduce(v.part_b, nbn, 2, v.stage, s));
+                hipLaunchKernelGGL(lk::fcg_beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.stage, kStage, 0);
                 hipLaunchKernelGGL(lk::fcg_p_kernel, dim3(nb), dim3(kBS), 0, s, st, v.p, z, v.r, v.dinv, m.ng,
                                    v.part_b);
                 hipLaunchKernelGGL(lk::fcg_redo_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb);
@@ -536,10 +541,11 @@ sem_status solve_fcg_nested(const Mesh &m, const sem_solve_opts &o, const CgVecs
             inner_active = h.learned != 0;
             for (int it = 0; it < check_every; ++it) {
                 SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.p, v.w, v.part_e, s, &st->done));
-                SEM_HIP_TRY(cg_alpha(m, v.part_e, st, s));
+                SEM_HIP_TRY(cg_alpha(m, v.part_e, v.stage, st, s));
                 hipLaunchKernelGGL(lk::fcg_update_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,
                                    q, m.lat, v.part_b);
-                hipLaunchKernelGGL(lk::fcg_check_kernel, dim3(1), dim3(kBS), 0, s, st, v.part_b, nbn, hist, 25, 0.0);
+                SEM_HIP_TRY(cg_reduce(v.part_b, nbn, 1, v.stage, s));
+                hipLaunchKernelGGL(lk::fcg_check_kernel, dim3(1), dim3(kBS), 0, s, st, v.stage, kStage, hist, 25, 0.0);
                 SEM_TRY(direction(0));
             }
         }
@@ -600,7 +606,8 @@ sem_status sem_smoother_create(const sem_mesh *mesh, const sem_smoother_desc *de
         {(void **)&sm.W, kParams * 4}, {(void **)&sm.m, kParams * 4}, {(void **)&sm.v, kParams * 4},
         {(void **)&sm.grad, kParams * 4}, {(void **)&sm.W2b, kW2 * 2},
         {(void **)&sm.dW_elem, (size_t)m.E * kParams * 4}, {(void **)&sm.c_local, (size_t)m.nl * 4},
-        {(void **)&sm.buf, (size_t)(6 * m.ng + m.nl) * 8}, {(void **)&sm.part, (size_t)kMaxVecBlocks * 4 * 8},
+        {(void **)&sm.buf, (size_t)(6 * m.ng + m.nl) * 8},
+        {(void **)&sm.part, (size_t)part_capacity(m.lat, m.E) * 2 * 8}, {(void **)&sm.stage, (size_t)kStage * 2 * 8},
         {(void **)&sm.scal, 64}};
     for (auto &a : allocs) {
         if (hipMalloc(a.p, a.bytes) != hipSuccess) {
@@ -624,7 +631,7 @@ sem_status sem_smoother_destroy(sem_smoother *sm)
 {
     if (!sm) return SEM_OK;
     Smoother &s = sm->s;
-    void *ps[] = {s.W, s.m, s.v, s.grad, s.W2b, s.dW_elem, s.c_local, s.buf, s.part, s.scal};
+    void *ps[] = {s.W, s.m, s.v, s.grad, s.W2b, s.dW_elem, s.c_local, s.buf, s.part, s.stage, s.scal};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete sm;

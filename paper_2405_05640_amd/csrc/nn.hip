@@ -412,8 +412,8 @@ template <typename TR>
 hipError_t nn_assemble_z(const Mesh &m, const TR *rg, const TR *dinvg, const float *c_local, TR *z, hipStream_t s,
                          const int32_t *use_c)
 {
-    hipLaunchKernelGGL((nn::assemble_z_kernel<TR>), dim3((unsigned)std::min<int64_t>(m.lat.ny * m.lat.nz, kMaxVecBlocks)),
-                       dim3(kBS), 0, s, rg, dinvg, c_local, m.lat, z, use_c);
+    hipLaunchKernelGGL((nn::assemble_z_kernel<TR>), dim3(node_grid(m.lat)), dim3(kBS), 0, s, rg, dinvg, c_local,
+                       m.lat, z, use_c);
     return hipGetLastError();
 }
 

@@ -21,7 +21,8 @@ struct Smoother {
     float *dW_elem = nullptr;       // [E][kParams] per-element gradients
     float *c_local = nullptr;       // [nl] element outputs
     double *buf = nullptr;          // training vectors: e, r, z, d, sd (5 x ng), w (nl)
-    double *part = nullptr;         // partial sums
+    double *part = nullptr;         // partial sums (2 x part_capacity)
+    double *stage = nullptr;        // second-stage sums (2 x kStage)
     double *scal = nullptr;         // device scalars: |e|_S^2, loss, ...
     int step = 0;
     float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;

@@ -68,6 +68,12 @@ hipError_t launch_ax_f64_gather(const Mesh &m, double h1, double h2, const doubl
                                 double *partial_uw, hipStream_t s, const int32_t *skip = nullptr);
 hipError_t launch_ax_f32_gather(const Mesh &m, float h1, float h2, const float *ug, float *w,
                                 double *partial_uw, hipStream_t s, const int32_t *skip = nullptr);
+// nc (1..4) assembled fields through one pass over G (N = 7): field c at
+// ug + c * ustride, output w + c * n_local, partials partial[c * E + e];
+// skipped when every done_flags[c * done_stride] is set.
+hipError_t launch_ax_f64_gather_batched(const Mesh &m, int nc, double h1, double h2, const double *ug, int64_t ustride,
+                                        double *w, double *partial, const int32_t *done_flags, int done_stride,
+                                        hipStream_t s);
 // BF16 operator on the matrix cores (N = 7): u local bf16 bits, or (gather)
 // an assembled float vector rounded to bf16 on load; w float local.
 hipError_t launch_ax_bf16(const Mesh &m, float h1, float h2, const uint16_t *u, float *w, hipStream_t s);

@@ -91,7 +91,8 @@ Workspace carve(const Mesh &m, int form, int hist_len, char *base)
     ws.b64 = (double *)take(ng * 8);
     ws.v64.w = (double *)take(nl * 8);
     ws.v64.part_e = (double *)take((size_t)std::max<int64_t>(m.E, 1) * 8);
-    ws.v64.part_b = (double *)take((size_t)kMaxVecBlocks * 2 * 8);
+    ws.v64.part_b = (double *)take((size_t)part_capacity(m.lat, m.E) * 3 * 8);
+    ws.v64.stage = (double *)take((size_t)kStage * 3 * 8);
     ws.st64 = (CgState *)take(sizeof(CgState));
     ws.st32 = (CgState *)take(sizeof(CgState));
     ws.hist = (double *)take((size_t)std::max(hist_len, 1) * 8);
@@ -108,6 +109,7 @@ Workspace carve(const Mesh &m, int form, int hist_len, char *base)
         ws.v32.w = (float *)take(nl * 4);
         ws.v32.part_e = ws.v64.part_e;
         ws.v32.part_b = ws.v64.part_b;
+        ws.v32.stage = ws.v64.stage;
     }
     ws.bytes = off;
     return ws;
@@ -457,6 +459,127 @@ sem_status sem_pcg_snapshots(const sem_mesh *mesh, const sem_solve_opts *opts, c
     rep->status = (h.bb == 0.0 || h.true_rr <= h.tol2) ? SEM_OK : SEM_ERR_NOT_CONVERGED;
     SEM_HIP_TRY(hipStreamSynchronize(s));
     if (rep->status != SEM_OK) return fail((sem_status)rep->status, "snapshot solve did not converge");
+    return SEM_OK;
+}
+
+
+static Workspace carve_batched(const Mesh &m, int nrhs, char *base, std::vector<CgVecs<double>> &vc, CgState **states,
+                               double **b64)
+{
+    Workspace ws{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    const size_t nl = (size_t)m.nl, ng = (size_t)m.ng;
+    double *X = (double *)take(nrhs * ng * 8), *R = (double *)take(nrhs * ng * 8), *Pp = (double *)take(nrhs * ng * 8);
+    double *dinv = (double *)take(ng * 8);
+    *b64 = (double *)take(nrhs * ng * 8);
+    double *W = (double *)take(nrhs * nl * 8);
+    double *PE = (double *)take((size_t)nrhs * std::max<int64_t>(m.E, 1) * 8);
+    double *PB = (double *)take((size_t)part_capacity(m.lat, m.E) * 3 * 8);
+    double *ST = (double *)take((size_t)kStage * 3 * 8);
+    *states = (CgState *)take(sizeof(CgState) * nrhs);
+    vc.resize(nrhs);
+    for (int c = 0; c < nrhs; ++c) {
+        vc[c].x = X + c * ng;
+        vc[c].r = R + c * ng;
+        vc[c].p = Pp + c * ng;
+        vc[c].dinv = dinv;
+        vc[c].w = W + c * nl;
+        vc[c].part_e = PE + c * m.E;
+        vc[c].part_b = PB;
+        vc[c].stage = ST;
+    }
+    ws.bytes = off;
+    return ws;
+}
+
+sem_status sem_solve_workspace_bytes_batched(const sem_mesh *mesh, const sem_solve_opts *opts, int32_t nrhs,
+                                             size_t *bytes)
+{
+    if (!mesh || !bytes || !opts) return fail(SEM_ERR_INVALID_ARG, "null argument");
+    if (nrhs < 1 || nrhs > 4) return fail(SEM_ERR_INVALID_ARG, "nrhs must be in 1..4");
+    std::vector<CgVecs<double>> vc;
+    CgState *st;
+    double *b64;
+    *bytes = carve_batched(mesh->m, nrhs, nullptr, vc, &st, &b64).bytes;
+    return SEM_OK;
+}
+
+sem_status sem_pcg_solve_batched(const sem_mesh *mesh, const sem_solve_opts *opts, int32_t nrhs, const double *b,
+                                 double *x, void *workspace, size_t ws_bytes, sem_solve_report *reps, void *stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!mesh || !opts || !b || !x || !workspace || !reps) return fail(SEM_ERR_INVALID_ARG, "null argument");
+    if (nrhs < 1 || nrhs > 4) return fail(SEM_ERR_INVALID_ARG, "nrhs must be in 1..4");
+    const Mesh &m = mesh->m;
+    if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "batched solves need order N = 7");
+    if (opts->form != SEM_FORM_JACOBI_PCG) return fail(SEM_ERR_UNSUPPORTED, "batched solves use SEM_FORM_JACOBI_PCG");
+    SEM_TRY(check_opts(m, opts));
+    std::vector<CgVecs<double>> vc;
+    CgState *st;
+    double *b64;
+    Workspace ws = carve_batched(m, nrhs, (char *)workspace, vc, &st, &b64);
+    if (ws_bytes < ws.bytes)
+        return fail(SEM_ERR_INVALID_ARG, "workspace too small: need " + std::to_string(ws.bytes) + " bytes");
+    hipStream_t s = (hipStream_t)stream;
+    const int check_every = std::max(1, opts->check_every > 0 ? opts->check_every : 16);
+    const sem_solve_opts &o = *opts;
+    SEM_HIP_TRY(launch_diag(m, o.h1, o.h2, vc[0].w, s));
+    SEM_HIP_TRY(cg_dinv<double>(m, vc[0].w, vc[0].dinv, s));
+    for (int c = 0; c < nrhs; ++c) {
+        SEM_HIP_TRY(cg_gather<double>(m, b + (size_t)c * m.nl, b64 + (size_t)c * m.ng, s));
+        SEM_TRY(reset_state(st + c, o.max_iter, 0, s));
+        SEM_HIP_TRY(cg_init<double>(m, vc[c], b64 + (size_t)c * m.ng, st + c, o.rel_tol, nullptr, s));
+    }
+    std::vector<CgState> h(nrhs);
+    for (;;) {
+        bool all = true;
+        for (int c = 0; c < nrhs; ++c) {
+            SEM_TRY(read_state(h[c], st + c, s));
+            all = all && h[c].done != 0;
+        }
+        if (all) break;
+        for (int q = 0; q < check_every; ++q) {
+            SEM_HIP_TRY(launch_ax_f64_gather_batched(m, nrhs, o.h1, o.h2, vc[0].p, m.ng, vc[0].w, vc[0].part_e,
+                                                     &st->done, (int)(sizeof(CgState) / sizeof(int32_t)), s));
+            for (int c = 0; c < nrhs; ++c) SEM_HIP_TRY(cg_step_after_ax<double>(m, vc[c], st + c, nullptr, s));
+        }
+    }
+    // FP64 true residual per field; a drifted field restarts on its own
+    sem_status worst = SEM_OK;
+    for (int c = 0; c < nrhs; ++c) {
+        Workspace one{};
+        one.v64 = vc[c];
+        one.b64 = b64 + (size_t)c * m.ng;
+        one.st64 = st + c;
+        int restarts = 0;
+        CgState &hc = h[c];
+        while (hc.bb > 0.0) {
+            SEM_TRY(true_residual(m, o.h1, o.h2, one, s, hc));
+            if (hc.true_rr <= hc.tol2 || hc.done != 1 || restarts == 3 || hc.it >= hc.max_it) break;
+            ++restarts;
+            SEM_HIP_TRY(cg_restart<double>(m, vc[c], st + c, s));
+            SEM_TRY(iterate<double>(m, o.h1, o.h2, vc[c], st + c, nullptr, check_every, s, hc));
+        }
+        SEM_HIP_TRY(cg_scatter<double>(m, vc[c].x, x + (size_t)c * m.nl, s));
+        sem_solve_report &r = reps[c];
+        std::memset(&r, 0, sizeof(r));
+        r.iterations = hc.it;
+        r.restarts = restarts;
+        r.rel_res = hc.bb > 0 ? std::sqrt(hc.rr / hc.bb) : 0.0;
+        r.true_rel_res = hc.bb > 0 ? std::sqrt(hc.true_rr / hc.bb) : 0.0;
+        r.status = hc.done == 2 ? SEM_ERR_BREAKDOWN
+                                : ((hc.bb > 0.0 && !(hc.true_rr <= hc.tol2)) ? SEM_ERR_NOT_CONVERGED : SEM_OK);
+        if (r.status != SEM_OK && worst == SEM_OK) worst = (sem_status)r.status;
+    }
+    SEM_HIP_TRY(hipStreamSynchronize(s));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int c = 0; c < nrhs; ++c) reps[c].elapsed_ms = ms;
+    if (worst != SEM_OK) return fail(worst, "a batched field did not converge");
     return SEM_OK;
 }
 

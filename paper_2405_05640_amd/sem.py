@@ -30,7 +30,7 @@ EXPORTED_SYMBOLS = [
     "sem_dssum", "sem_rhs", "sem_jacobi", "sem_dot", "sem_solve_workspace_bytes",
     "sem_pcg_solve", "sem_last_error", "sem_version", "sem_smoother_create", "sem_smoother_destroy",
     "sem_smoother_set_weights", "sem_smoother_get_weights", "sem_smoother_apply", "sem_smoother_loss_grad",
-    "sem_smoother_train_step", "sem_pcg_snapshots",
+    "sem_smoother_train_step", "sem_pcg_snapshots", "sem_pcg_solve_batched", "sem_solve_workspace_bytes_batched",
 ]
 
 
@@ -116,6 +116,10 @@ def lib():
             "sem_smoother_train_step": [vp, vp, dbl, dbl, vp, vp, vp],
             "sem_pcg_snapshots": [vp, ctypes.POINTER(SolveOpts), vp, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t,
                                   ctypes.POINTER(SolveReport), vp],
+            "sem_pcg_solve_batched": [vp, ctypes.POINTER(SolveOpts), ctypes.c_int32, vp, vp, vp, ctypes.c_size_t,
+                                      ctypes.POINTER(SolveReport), vp],
+            "sem_solve_workspace_bytes_batched": [vp, ctypes.POINTER(SolveOpts), ctypes.c_int32,
+                                                  ctypes.POINTER(ctypes.c_size_t)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -382,6 +386,31 @@ def pcg_snapshots(mesh, b, iters, e_out, workspace=None, **kw):
                                    workspace.numel() * workspace.element_size(), ctypes.byref(rep), _stream()))
     return Report(rep.status, rep.iterations, rep.outer_iterations, rep.restarts, rep.fallback_used, rep.rel_res,
                   rep.true_rel_res, rep.elapsed_ms)
+
+
+def pcg_solve_batched(mesh, b, x, workspace=None, raise_on_error=True, **kw):
+    """Jacobi-PCG for nrhs = b.shape[0] fields sharing the operator (one pass
+    over the geometric factors per iteration).  b, x: (nrhs, E, n, n, n)."""
+    import torch
+    nrhs = b.shape[0]
+    if b.shape != x.shape or nrhs < 1 or nrhs > 4:
+        raise ValueError("b and x must both be (nrhs, E, n, n, n) with 1 <= nrhs <= 4")
+    opts = mesh.solve_opts(**kw)
+    need = ctypes.c_size_t()
+    _check(lib().sem_solve_workspace_bytes_batched(mesh._h, ctypes.byref(opts), nrhs, ctypes.byref(need)))
+    if workspace is None:
+        workspace = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    if workspace.numel() * workspace.element_size() < need.value:
+        raise ValueError("workspace too small")
+    reps = (SolveReport * nrhs)()
+    st = lib().sem_pcg_solve_batched(mesh._h, ctypes.byref(opts), nrhs, _want(b, "f64", nrhs * mesh.n_local, "b"),
+                                     _want(x, "f64", nrhs * mesh.n_local, "x"), ctypes.c_void_p(workspace.data_ptr()),
+                                     workspace.numel() * workspace.element_size(), reps, _stream())
+    out = [Report(r.status, r.iterations, r.outer_iterations, r.restarts, r.fallback_used, r.rel_res,
+                  r.true_rel_res, r.elapsed_ms) for r in reps]
+    if st != SEM_OK and raise_on_error:
+        raise SemError(st, lib().sem_last_error().decode())
+    return out
 
 
 def version():

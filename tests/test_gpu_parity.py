@@ -282,3 +282,22 @@ def test_nested_fcg_reaches_fp64_tolerance(spec, form, prep):
     _, info = om.pcg(b, 1.0, h2)
     print("nested %s %s: %d outer, %d inner; FP64 PCG %d" % (spec.name, form, rep.outer_iterations, rep.iterations,
                                                             info["iterations"]))
+
+
+@pytest.mark.parametrize("spec,h2", [(wl.deformed_cube(3, 7), 5.0), (wl.channel(3, 7), 0.0)],
+                         ids=["deformed3_N7_helm", "channel3_N7"])
+def test_batched_solve_matches_single_solves(spec, h2):
+    import torch
+    om, gm = pair(spec)
+    rng = np.random.default_rng(25)
+    bs = np.stack([om.rhs(rng.standard_normal(om.shape)) for _ in range(3)])
+    X = torch.zeros(bs.shape, dtype=torch.float64, device="cuda")
+    reps = sem.pcg_solve_batched(gm, dev(bs), X, h1=1.0, h2=h2, rel_tol=1e-10)
+    Xh = host(X)
+    for c in range(3):
+        xs = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
+        rs = gm.pcg_solve(dev(bs[c]), xs, h1=1.0, h2=h2, rel_tol=1e-10)
+        assert abs(reps[c].iterations - rs.iterations) <= 1
+        r = bs[c] - om.apply_S(Xh[c], 1.0, h2)
+        assert np.sqrt(om.dot(r, r) / om.dot(bs[c], bs[c])) <= 1.05e-10
+        assert np.linalg.norm(Xh[c] - host(xs)) <= 1e-8 * np.linalg.norm(host(xs))
