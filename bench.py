@@ -88,7 +88,7 @@ def timed_solves(mesh, b, reps, **kw):
     """Median wall time of `reps` solves from x = 0 (after one warm-up)."""
     import torch
     x = torch.zeros_like(b)
-    ws = mesh.workspace(mesh.solve_opts(**{k: v for k, v in kw.items() if k != "smoother"}))
+    ws = mesh.workspace(mesh.solve_opts(**kw))
     times, rep = [], None
     for q in range(reps + 1):
         x.zero_()

@@ -25,7 +25,9 @@
  *    the next call on the same thread).
  *  - The library allocates device memory only in sem_mesh_create and
  *    sem_smoother_create; hot calls allocate nothing.  Concurrent calls on one
- *    mesh are safe when their output buffers are distinct.
+ *    mesh are safe when their output buffers and workspaces are distinct
+ *    (exceptions: sem_dot; the smoother's apply, loss and training calls
+ *    share the smoother's buffers).
  */
 #ifndef SEM_H
 #define SEM_H
@@ -92,7 +94,7 @@ enum {
 };
 
 /* Host setup (GLL rule, trilinear geometry, geometric factors, numbering,
- * gather-scatter lists) and upload to the current HIP device.  Fails with
+ * per-axis gather-scatter copy tables) and upload to the current HIP device.  Fails with
  * SEM_ERR_INVALID_ARG if any element has detJ <= 0 at a GLL node. */
 sem_status sem_mesh_create(const sem_mesh_desc *desc, sem_mesh **out);
 sem_status sem_mesh_destroy(sem_mesh *mesh);
@@ -126,7 +128,9 @@ sem_status sem_jacobi(const sem_mesh *mesh, double h1, double h2, double *dinv, 
 
 /* Inner product of two continuous local fields with each global node counted
  * once, sum_l u_l v_l / mult_l (async); the double result is written to the
- * DEVICE address `result`.  Deterministic summation order. */
+ * DEVICE address `result`.  Deterministic summation order.  Uses a small
+ * partial-sum buffer owned by the mesh: calls on one mesh must be ordered
+ * (same stream or synchronised), unlike the other operator entry points. */
 sem_status sem_dot(const sem_mesh *mesh, const double *u, const double *v, double *result,
                    void *stream);
 

@@ -1,7 +1,8 @@
 // mesh.cpp -- host-side mesh setup of libsem and the mesh entry points.
 //
 // Reference element, trilinear geometry, geometric factors, structured
-// global numbering and gather-scatter lists (paper section 3.1: hexahedral
+// global numbering and the per-axis copy tables of the gather-scatter
+// (paper section 3.1: hexahedral
 // elements, GLL collocation, gather-scatter coupling; the spectral-element
 // definitions follow Deville, Fischer & Mund 2002, chapters 2 and 4).
 #include <algorithm>

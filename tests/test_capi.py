@@ -36,3 +36,39 @@ def test_error_string_without_device():
     st = sem.lib().sem_mesh_create(None, ctypes.byref(h))
     assert st == sem.SEM_ERR_INVALID_ARG
     assert b"null" in sem.lib().sem_last_error()
+
+
+def test_binding_signatures_cover_exports():
+    # every exported entry point has an argtypes signature in the binding
+    from paper_2405_05640_amd import sem
+    L = sem.lib()
+    for n in sem.EXPORTED_SYMBOLS:
+        f = getattr(L, n)
+        assert f.restype is not None, n
+        if n not in ("sem_last_error", "sem_version"):
+            assert f.argtypes is not None and len(f.argtypes) >= 1, n
+
+
+def test_struct_layouts_match_header():
+    # field counts of the ctypes mirrors follow the C structs in sem.h
+    import re
+    from paper_2405_05640_amd import sem
+    txt = open(os.path.join(ROOT, "include", "sem.h")).read()
+
+    def fields(struct_name):
+        m = re.search(r"typedef struct \{([^{}]*)\}\s*%s;" % struct_name, txt)
+        body = re.sub(r"/\*.*?\*/", "", m.group(1), flags=re.S)
+        names = []
+        for decl in body.split(";"):
+            decl = decl.replace("*", " ").strip()
+            if not decl:
+                continue
+            items = decl.split(",")
+            names.append(items[0].split()[-1].split("[")[0])     # "type qualifiers name"
+            names += [it.strip().split("[")[0] for it in items[1:]]
+        return names
+
+    assert [f for f, _ in sem.SolveOpts._fields_] == fields("sem_solve_opts")
+    assert [f for f, _ in sem.SolveReport._fields_] == fields("sem_solve_report")
+    assert [f for f, _ in sem.MeshInfo._fields_] == fields("sem_mesh_info")
+    assert [f for f, _ in sem.SmootherDesc._fields_] == fields("sem_smoother_desc")
