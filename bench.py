@@ -358,7 +358,8 @@ def main():
             torch.cuda.empty_cache()
             mesh = sem.Mesh.from_spec(spec, prepare=sem.SEM_PREP_F32 | sem.SEM_PREP_BF16)
             forms = (("dc_fp32", sem.FORM_DC_FP32, 1e-5), ("dc_bf16", sem.FORM_DC_BF16, 1e-2),
-                     ("fcg_inner_fp32", sem.FORM_FCG_INNER_FP32, 0.0), ("fcg_inner_bf16", sem.FORM_FCG_INNER_BF16, 0.0))
+                     ("fcg_inner_fp32", sem.FORM_FCG_INNER_FP32, 0.0), ("fcg_inner_bf16", sem.FORM_FCG_INNER_BF16, 0.0),
+                     ("reliable_fp32", sem.FORM_RELIABLE_FP32, 0.1), ("reliable_bf16split", sem.FORM_RELIABLE_BF16, 0.1))
             for name, form, itol in forms:
                 try:
                     rr, xx = timed_solves(mesh, b, args.solve_reps, h1=h1, h2=h2, rel_tol=1e-10, check_every=32,

@@ -49,7 +49,7 @@ typedef enum {
     SEM_ERR_UNSUPPORTED = 6    /* valid request this build does not provide */
 } sem_status;
 
-typedef enum { SEM_F64 = 0, SEM_F32 = 1, SEM_BF16 = 2 } sem_dtype;
+typedef enum { SEM_F64 = 0, SEM_F32 = 1, SEM_BF16 = 2, SEM_BF16_SPLIT = 3 } sem_dtype;
 
 typedef struct sem_mesh sem_mesh;           /* opaque, immutable after create */
 typedef struct sem_smoother sem_smoother;   /* opaque learned smoother */
@@ -108,7 +108,11 @@ sem_status sem_mesh_export(const sem_mesh *mesh, int field, void *host_dst, size
  * sec. 4.4; the paper's element-by-element operator of section 3.1).
  * in = SEM_F64: u, w double.  in = SEM_F32: u, w float (needs SEM_PREP_F32).
  * in = SEM_BF16: u bf16 (uint16 bit patterns), w float, contractions on the
- * matrix cores with fp32 accumulation (needs SEM_PREP_BF16). */
+ * matrix cores with fp32 accumulation (needs SEM_PREP_BF16).
+ * in = SEM_BF16_SPLIT: u, w float; G and B stored in bf16, every contraction
+ * operand carried as a hi + lo bf16 pair on the matrix cores (hi.hi + lo.hi +
+ * hi.lo, fp32 sums): the exact operator with bf16-rounded G and B to about
+ * 2^-16 relative (needs SEM_PREP_BF16).  Both bf16 forms need N = 7. */
 sem_status sem_ax(const sem_mesh *mesh, double h1, double h2, sem_dtype in,
                   const void *u, void *w, void *stream);
 
@@ -143,7 +147,13 @@ typedef enum {
                                     Jacobi-PCG fallback */
     SEM_FORM_FCG_INNER_FP32 = 4, /* FP64 flexible CG preconditioned by inner_iters steps of
                                     FP32 Jacobi-PCG (FP32 operator) on the unit-scaled defect */
-    SEM_FORM_FCG_INNER_BF16 = 5  /* same with the BF16 matrix-core operator in the inner steps */
+    SEM_FORM_FCG_INNER_BF16 = 5, /* same with the BF16 matrix-core operator in the inner steps */
+    SEM_FORM_RELIABLE_FP32 = 6,  /* CG with FP32 vectors and the FP32 operator; the solution is
+                                    accumulated in FP64 and the residual is replaced by the FP64
+                                    true residual whenever it has fallen by inner_tol (reliable
+                                    updates); the search direction is kept */
+    SEM_FORM_RELIABLE_BF16 = 7   /* same with the split-BF16 matrix-core operator
+                                    (SEM_BF16_SPLIT) */
 } sem_form;
 
 typedef struct {
@@ -153,7 +163,8 @@ typedef struct {
     int32_t check_every;        /* iterations between host polls of the flag */
     int32_t form;               /* sem_form */
     int32_t max_outer;          /* defect-correction outer steps (DC forms) */
-    double inner_tol;           /* inner relative tolerance (DC forms) */
+    double inner_tol;           /* inner relative tolerance (DC forms); residual reduction that
+                                   triggers a replacement (RELIABLE forms, e.g. 0.1) */
     const sem_smoother *smoother; /* learned forms */
     double *history;            /* HOST, optional: relative residual per iteration */
     int32_t history_len;        /* capacity of history */
@@ -163,8 +174,9 @@ typedef struct {
 typedef struct {
     int32_t status;             /* sem_status of the solve */
     int32_t iterations;         /* operator applications in the Krylov loop(s); for the
-                                   DC and FCG_INNER forms: low-precision inner iterations */
-    int32_t outer_iterations;   /* DC steps, or FP64 outer iterations (FCG_INNER forms) */
+                                   DC, FCG_INNER and RELIABLE forms: low-precision iterations */
+    int32_t outer_iterations;   /* DC steps, FP64 outer iterations (FCG_INNER forms), or
+                                   residual replacements (RELIABLE forms) */
     int32_t restarts;           /* true-residual restarts */
     int32_t fallback_used;      /* learned forms: 1 if Jacobi-PCG took over */
     int32_t history_written;

@@ -174,11 +174,14 @@ class Mesh:
         return (self.E, n, n, n)
 
     # ---------------------------------------------------------------- ops
-    def ax(self, u, h1=1.0, h2=0.0):
-        """Unassembled local operator w = h1 sum_ab D_a^T G_ab D_b u + h2 B u."""
+    def ax(self, u, h1=1.0, h2=0.0, G=None, B=None):
+        """Unassembled local operator w = h1 sum_ab D_a^T G_ab D_b u + h2 B u
+        (optionally with other geometric factors G [6, E, ...] and B)."""
         u = _c(u, np.float64).reshape(self.shape)
+        G = self.G if G is None else _c(G, np.float64)
+        B = self.B if B is None else _c(B, np.float64)
         w = np.zeros(self.shape)
-        lib().ora_ax(self.E, self.N, _p(self.D), _p(self.G), _p(self.B), h1, h2, _p(u), _p(w))
+        lib().ora_ax(self.E, self.N, _p(self.D), _p(G), _p(B), h1, h2, _p(u), _p(w))
         return w
 
     def ax_abs_bound(self, u, h1=1.0, h2=0.0):

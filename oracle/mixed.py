@@ -12,6 +12,11 @@ precisions so the GPU results can be bounded against them:
   G-combination is float32 and its three results are rounded to BF16; the
   transposed contractions sum in float32 and the r, s, t contributions are
   added in that order; the Helmholtz term h2 B u is float32.
+* BF16 split: G and B are stored in BF16 (rounded through float32); u, D and
+  the intermediate fluxes enter the matrix cores as hi + lo BF16 pairs
+  (three products per contraction, FP32 sums).  Its reference is the exact
+  operator with the BF16-rounded G and B (``ax_bf16_split_reference``); the
+  split reproduces that to about 2^-16 relative.
 """
 from __future__ import annotations
 
@@ -69,3 +74,14 @@ def ax_lowp(mesh, u, h1, h2, precision):
     w = w + _contract(D, wt, "t", True).astype(f32)
     w = f32(h1) * w + f32(h2) * B * uu
     return w.astype(np.float64)
+
+
+def bf16_storage(a):
+    """Geometric factors as the BF16 operators store them (float32, then RNE
+    to bfloat16), returned as float64."""
+    return bf16_round(np.asarray(a).astype(np.float32)).astype(np.float64)
+
+
+def ax_bf16_split_reference(mesh, u, h1, h2):
+    """Exact (FP64) local operator with BF16-stored G and B."""
+    return mesh.ax(u, h1, h2, G=bf16_storage(mesh.G), B=bf16_storage(mesh.B))

@@ -42,7 +42,7 @@ ax_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G,
     const int t = threadIdx.x;
     const int i = t % NP;
     const int j = t / NP;
-    const int64_t e = blockIdx.x;
+    const int64_t e = xcd_block();
     const T *Ge = G + e * (6 * P3);
 
     sD[t] = Dg[t];
@@ -159,7 +159,7 @@ ax_pt_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G
     constexpr int P2 = NP * NP, P3 = NP * NP * NP;
     __shared__ T sD[P2], su[P3], sr[P3], ss[P3], st[P3];
     const int t = threadIdx.x, i = t % NP, j = (t / NP) % NP, k = t / P2;
-    const int64_t e = blockIdx.x;
+    const int64_t e = xcd_block();
     T uv;
     if (GATHER) {
         const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);
@@ -233,7 +233,7 @@ ax_pt_batched_kernel(const double *__restrict__ u, int64_t ustride, double *__re
     __shared__ double sD[P2], su[P3], sr[P3], ss[P3], st[P3];
     __shared__ double red[P3];
     const int t = threadIdx.x, i = t % NP, j = (t / NP) % NP, k = t / P2;
-    const int64_t e = blockIdx.x;
+    const int64_t e = xcd_block();
     int64_t src;
     if (GATHER) {
         const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);

@@ -22,6 +22,7 @@ namespace {
 
 typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
 
 __device__ __forceinline__ unsigned short f2bf(float f)
 {
@@ -31,6 +32,12 @@ __device__ __forceinline__ unsigned short f2bf(float f)
     return (unsigned short)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
+// BF16 number q (0..7) of a 16-byte vector, widened to FP32
+__device__ __forceinline__ float bf_at(const u32x4 &v, int q)
+{
+    const unsigned w = v[q >> 1];
+    return __uint_as_float((q & 1) ? (w & 0xffff0000u) : (w << 16));
+}
 
 // point index of entry c (0..7) of line L along direction dir (0 = r, 1 = s, 2 = t)
 __device__ __forceinline__ int line_point(int dir, int L, int c)
@@ -89,7 +96,17 @@ ax_bf16_kernel(const void *__restrict__ uin, float *__restrict__ w, const unsign
     __shared__ float sd[3][512];
     __shared__ unsigned short sD[64];
     const int lane = threadIdx.x;
-    const int64_t e = blockIdx.x;
+    const int64_t e = xcd_block();
+    // Issue every streaming load of the element first (G: six 16-byte
+    // vectors per lane, each lane owning the contiguous 8-point row 8 lane ..
+    // 8 lane + 7; B likewise) so that their latency overlaps the u gather and
+    // the first contractions.
+    const unsigned short *Ge = G + e * 6 * 512;
+    u32x4 gq[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gq[c] = __builtin_nontemporal_load((const u32x4 *)(Ge + c * 512) + lane);
+    u32x4 bq = {0u, 0u, 0u, 0u};
+    if (HELM) bq = __builtin_nontemporal_load((const u32x4 *)(Bm + e * 512) + lane);
     sD[lane] = Dbf[lane];
     // u tile (BF16) into LDS: each lane 8 consecutive points
     if (GATHER) {
@@ -124,14 +141,13 @@ ax_bf16_kernel(const void *__restrict__ uin, float *__restrict__ w, const unsign
     contract(1, su, sd[1], bT, false);
     contract(2, su, sd[2], bT, false);
     __syncthreads();
-    // G-combination, FP32, rounded to BF16
-    const unsigned short *Ge = G + e * 6 * 512;
+    // G-combination, FP32, rounded to BF16 (lane: points 8 lane .. 8 lane + 7)
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        const int p = lane + 64 * q;
+        const int p = 8 * lane + q;
         const float ur = sd[0][p], us = sd[1][p], ut = sd[2][p];
-        const float g11 = bf2f(Ge[p]), g12 = bf2f(Ge[512 + p]), g13 = bf2f(Ge[1024 + p]);
-        const float g22 = bf2f(Ge[1536 + p]), g23 = bf2f(Ge[2048 + p]), g33 = bf2f(Ge[2560 + p]);
+        const float g11 = bf_at(gq[0], q), g12 = bf_at(gq[1], q), g13 = bf_at(gq[2], q);
+        const float g22 = bf_at(gq[3], q), g23 = bf_at(gq[4], q), g33 = bf_at(gq[5], q);
         sw[0][p] = f2bf(g11 * ur + g12 * us + g13 * ut);
         sw[1][p] = f2bf(g12 * ur + g22 * us + g23 * ut);
         sw[2][p] = f2bf(g13 * ur + g23 * us + g33 * ut);
@@ -145,15 +161,177 @@ ax_bf16_kernel(const void *__restrict__ uin, float *__restrict__ w, const unsign
     contract(2, sw[2], sd[0], bD, true);
     __syncthreads();
     double dot = 0.0;
+    float out[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        const int p = lane + 64 * q;
+        const int p = 8 * lane + q;
         float v = h1 * sd[0][p];
         const float uu = bf2f(su[p]);
-        if (HELM) v += h2 * bf2f(Bm[e * 512 + p]) * uu;
-        w[e * 512 + p] = v;
+        if (HELM) v += h2 * bf_at(bq, q) * uu;
+        out[q] = v;
         if (partial) dot += (double)uu * (double)v;
     }
+    float4 *wo = (float4 *)(w + e * 512) + 2 * lane;
+    wo[0] = make_float4(out[0], out[1], out[2], out[3]);
+    wo[1] = make_float4(out[4], out[5], out[6], out[7]);
+    if (partial) {
+        for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
+        if (lane == 0) partial[e] = dot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Split-BF16 operator: FP32 u through the BF16 matrix cores.  Every operand x
+// of a contraction (u, D, the fluxes, D^T) is carried as a pair of BF16
+// numbers x = hi + lo (hi = bf16(x), lo = bf16(x - hi): 16 significant bits),
+// and a contraction sums hi.Dhi + lo.Dhi + hi.Dlo in FP32 (the lo.lo product,
+// about 2^-18 relative, is dropped).  G and B are BF16 storage, so the
+// operator reproduces the exact operator with BF16-rounded G and B to about
+// 2^-16 relative while streaming 12 + 2 bytes of geometry per point.
+//
+// One 16x16x32 MFMA handles 16 lines of a direction: A row m = line
+// (K = [hi(8) | lo(8) | hi(8) | 0(8)]), B = [Dhi^T; Dhi^T; Dlo^T; 0] in output
+// columns 0..7 (columns 8..15 are zero), four MFMAs per direction.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short s16x8;
+
+__device__ __forceinline__ void contract_split(int dir, const float *src, float *dst, bf16x8 bop, bool acc)
+{
+    const int lane = threadIdx.x & 63;
+    const int m = lane & 15, g = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int L = 16 * t + m;
+        s16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (g < 3) {
+            float v[8];
+            if (dir == 0) {
+                const float4 v0 = *(const float4 *)&src[L * 8], v1 = *(const float4 *)&src[L * 8 + 4];
+                v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+                v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = src[line_point(dir, L, q)];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const unsigned short h = f2bf(v[q]);
+                a[q] = (short)(g == 1 ? f2bf(v[q] - bf2f(h)) : h);
+            }
+        }
+        f4 c = {0.f, 0.f, 0.f, 0.f};
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), bop, c, 0, 0, 0);
+        // C: column n = entry (n < 8), rows 4 g + q = lines 16 t + 4 g + q
+        if (n < 8) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int p = line_point(dir, 16 * t + 4 * g + q, n);
+                if (acc)
+                    dst[p] += c[q];
+                else
+                    dst[p] = c[q];
+            }
+        }
+    }
+}
+
+template <bool GATHER, bool HELM>
+__global__ void __launch_bounds__(64)
+ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsigned short *__restrict__ G,
+                const unsigned short *__restrict__ Bm, const unsigned short *__restrict__ Dhl, float h1, float h2,
+                double *__restrict__ partial, const int32_t *__restrict__ skip, Lattice L)
+{
+    if (skip && *skip) return;
+    __shared__ __attribute__((aligned(16))) float su[512];      // u, then the accumulated output
+    __shared__ __attribute__((aligned(16))) float sd[3][512];   // derivatives, then the fluxes
+    __shared__ unsigned short sD[128];                           // D hi | D lo
+    const int lane = threadIdx.x;
+    const int64_t e = xcd_block();
+    const unsigned short *Ge = G + e * 6 * 512;
+    u32x4 gq[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gq[c] = __builtin_nontemporal_load((const u32x4 *)(Ge + c * 512) + lane);
+    u32x4 bq = {0u, 0u, 0u, 0u};
+    if (HELM) bq = __builtin_nontemporal_load((const u32x4 *)(Bm + e * 512) + lane);
+    sD[lane] = Dhl[lane];
+    sD[64 + lane] = Dhl[64 + lane];
+    // lane owns the 8-point row p = 8 lane + q: i = q, j = lane & 7, k = lane >> 3
+    float uu[8];
+    if (GATHER) {
+        const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);
+        int64_t gj = ey * 7 + (lane & 7), gk = ez * 7 + (lane >> 3);
+        if (gj >= L.ny) gj -= L.ny;
+        if (gk >= L.nz) gk -= L.nz;
+        const float *row = uin + L.nx * (gj + L.ny * gk);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int64_t gi = ex * 7 + q;
+            if (gi >= L.nx) gi -= L.nx;
+            uu[q] = row[gi];
+        }
+    } else {
+        const float4 v0 = ((const float4 *)(uin + e * 512))[2 * lane], v1 = ((const float4 *)(uin + e * 512))[2 * lane + 1];
+        uu[0] = v0.x; uu[1] = v0.y; uu[2] = v0.z; uu[3] = v0.w;
+        uu[4] = v1.x; uu[5] = v1.y; uu[6] = v1.z; uu[7] = v1.w;
+    }
+    ((float4 *)su)[2 * lane] = make_float4(uu[0], uu[1], uu[2], uu[3]);
+    ((float4 *)su)[2 * lane + 1] = make_float4(uu[4], uu[5], uu[6], uu[7]);
+    __syncthreads();
+    // B operands (lane: column n, K rows 8 g + q)
+    const int n = lane & 15, g = lane >> 4;
+    s16x8 bFs = {0, 0, 0, 0, 0, 0, 0, 0}, bTs = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (n < 8 && g < 3) {
+        const int off = g == 2 ? 64 : 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            bFs[q] = (short)sD[off + n * 8 + q];   // forward: out[n] = sum_c in[c] D[n][c]
+            bTs[q] = (short)sD[off + q * 8 + n];   // transposed: out[n] = sum_c in[c] D[c][n]
+        }
+    }
+    const bf16x8 bF = __builtin_bit_cast(bf16x8, bFs), bT = __builtin_bit_cast(bf16x8, bTs);
+    contract_split(0, su, sd[0], bF, false);
+    contract_split(1, su, sd[1], bF, false);
+    contract_split(2, su, sd[2], bF, false);
+    __syncthreads();
+    // G-combination in FP32 (fluxes kept in FP32)
+    float fr[8], fs[8], ft[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int p = 8 * lane + q;
+        const float ur = sd[0][p], us = sd[1][p], ut = sd[2][p];
+        const float g11 = bf_at(gq[0], q), g12 = bf_at(gq[1], q), g13 = bf_at(gq[2], q);
+        const float g22 = bf_at(gq[3], q), g23 = bf_at(gq[4], q), g33 = bf_at(gq[5], q);
+        fr[q] = g11 * ur + g12 * us + g13 * ut;
+        fs[q] = g12 * ur + g22 * us + g23 * ut;
+        ft[q] = g13 * ur + g23 * us + g33 * ut;
+    }
+    __syncthreads();
+    ((float4 *)sd[0])[2 * lane] = make_float4(fr[0], fr[1], fr[2], fr[3]);
+    ((float4 *)sd[0])[2 * lane + 1] = make_float4(fr[4], fr[5], fr[6], fr[7]);
+    ((float4 *)sd[1])[2 * lane] = make_float4(fs[0], fs[1], fs[2], fs[3]);
+    ((float4 *)sd[1])[2 * lane + 1] = make_float4(fs[4], fs[5], fs[6], fs[7]);
+    ((float4 *)sd[2])[2 * lane] = make_float4(ft[0], ft[1], ft[2], ft[3]);
+    ((float4 *)sd[2])[2 * lane + 1] = make_float4(ft[4], ft[5], ft[6], ft[7]);
+    __syncthreads();
+    // transposed contractions accumulated r, s, t into su (u is in registers)
+    contract_split(0, sd[0], su, bT, false);
+    __syncthreads();
+    contract_split(1, sd[1], su, bT, true);
+    __syncthreads();
+    contract_split(2, sd[2], su, bT, true);
+    __syncthreads();
+    double dot = 0.0;
+    float out[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        float v = h1 * su[8 * lane + q];
+        if (HELM) v += h2 * bf_at(bq, q) * uu[q];
+        out[q] = v;
+        if (partial) dot += (double)uu[q] * (double)v;
+    }
+    float4 *wo = (float4 *)(w + e * 512) + 2 * lane;
+    wo[0] = make_float4(out[0], out[1], out[2], out[3]);
+    wo[1] = make_float4(out[4], out[5], out[6], out[7]);
     if (partial) {
         for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
         if (lane == 0) partial[e] = dot;
@@ -180,6 +358,27 @@ static hipError_t launch_bf16(const Mesh &m, float h1, float h2, const void *u, 
         else
             hipLaunchKernelGGL((ax_bf16_kernel<false, false>), grid, block, 0, s, u, w, m.d_Gbf, m.d_Bbf, m.d_Dbf, h1, h2, partial, skip, m.lat);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_ax_bf16s(const Mesh &m, float h1, float h2, const float *u, float *w, double *partial,
+                           hipStream_t s, const int32_t *skip, bool gather)
+{
+    if (m.E == 0) return hipSuccess;
+    if (m.N != 7) return hipErrorInvalidValue;
+    const bool helm = h2 != 0.f;
+    const dim3 grid((unsigned)m.E), block(64);
+#define SEM_BF16S(G_, H_)                                                                                     \
+    hipLaunchKernelGGL((ax_bf16s_kernel<G_, H_>), grid, block, 0, s, u, w, m.d_Gbf, m.d_Bbf, m.d_Dbf, h1, h2, \
+                       partial, skip, m.lat)
+    if (gather) {
+        if (helm) SEM_BF16S(true, true);
+        else SEM_BF16S(true, false);
+    } else {
+        if (helm) SEM_BF16S(false, true);
+        else SEM_BF16S(false, false);
+    }
+#undef SEM_BF16S
     return hipGetLastError();
 }
 

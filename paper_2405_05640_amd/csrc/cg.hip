@@ -291,6 +291,48 @@ __global__ void __launch_bounds__(kBS) restart_finalize(CgState *st, const doubl
     }
 }
 
+// Residual replacement (reliable update) of a low-precision CG: r = inv_sigma
+// * r64 (the FP64 true residual), x = 0, p = first ? dinv r : p_scale * p;
+// partials (r, r), (r, dinv r)
+template <typename T>
+__global__ void __launch_bounds__(kBS)
+replace_kernel(const double *__restrict__ r64, T *__restrict__ x, T *__restrict__ r, T *__restrict__ p,
+               const T *__restrict__ dinv, double inv_sigma, double p_scale, int first, int64_t ng,
+               double *__restrict__ part)
+{
+    double acc[2] = {0.0, 0.0};
+    GRID_STRIDE(g, ng)
+    {
+        const T d = dinv[g];
+        const T rg = d == T(0) ? T(0) : (T)(inv_sigma * r64[g]);
+        const T z = d * rg;
+        x[g] = T(0);
+        r[g] = rg;
+        p[g] = first ? z : (T)(p_scale * (double)p[g]);
+        acc[0] += (double)rg * (double)rg;
+        acc[1] += (double)rg * (double)z;
+    }
+    block_store<2>(acc, part, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBS) replace_finalize(CgState *st, const double *__restrict__ part, int nb, double tol2,
+                                                         int first)
+{
+    const double rr = block_sum(part, nb);
+    const double rz = block_sum(part + nb, nb);
+    if (threadIdx.x == 0) {
+        if (first) {
+            st->it = 0;
+            st->bb = rr;
+        }
+        st->rr = rr;
+        st->rz = rz;
+        st->tol2 = tol2;
+        st->status = 0;
+        st->done = (rr <= tol2) ? 1 : (st->it >= st->max_it ? 3 : 0);
+    }
+}
+
 // y += s * (double)d   (defect correction: x64 += scale * d32)
 template <typename T>
 __global__ void __launch_bounds__(kBS) axpy_kernel(double *__restrict__ y, const T *__restrict__ d, double s, int64_t ng)
@@ -388,6 +430,16 @@ hipError_t cg_restart(const Mesh &m, const CgVecs<T> &v, CgState *st, hipStream_
 }
 
 template <typename T>
+hipError_t cg_replace(const Mesh &m, const CgVecs<T> &v, const double *r64, CgState *st, double inv_sigma,
+                      double p_scale, int first, double tol2, hipStream_t s)
+{
+    const int nb = cg_blocks(m.ng);
+    L3((cg::replace_kernel<T>), m.ng) r64, v.x, v.r, v.p, v.dinv, inv_sigma, p_scale, first, m.ng, v.part_b);
+    hipLaunchKernelGGL(cg::replace_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb, tol2, first);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t cg_axpy(const Mesh &m, double *y, const T *d, double scale, hipStream_t s)
 {
     L3((cg::axpy_kernel<T>), m.ng) y, d, scale, m.ng);
@@ -430,6 +482,8 @@ hipError_t cg_rsub(const Mesh &m, const double *x, double *e, hipStream_t s)
     template hipError_t cg_step_after_ax<T>(const Mesh &, const CgVecs<T> &, CgState *, double *, hipStream_t); \
     template hipError_t cg_resid<T>(const Mesh &, const CgVecs<T> &, const T *, T *, CgState *, hipStream_t); \
     template hipError_t cg_restart<T>(const Mesh &, const CgVecs<T> &, CgState *, hipStream_t);              \
+    template hipError_t cg_replace<T>(const Mesh &, const CgVecs<T> &, const double *, CgState *, double,     \
+                                      double, int, double, hipStream_t);                                     \
     template hipError_t cg_axpy<T>(const Mesh &, double *, const T *, double, hipStream_t);                  \
     template hipError_t cg_scale<T>(const Mesh &, const double *, T *, double, hipStream_t);
 INST(double)

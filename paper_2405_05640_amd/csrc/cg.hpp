@@ -11,8 +11,8 @@ constexpr int kBS = 256;             // threads per block of the vector kernels
 constexpr int kMaxVecBlocks = 4096;  // grid cap of the flat vector kernels
 constexpr int kStage = 256;          // second-stage partial sums
 
-// Grid of the per-node kernels: one workgroup per lattice row (gj, gk).
-inline unsigned node_grid(const Lattice &L) { return (unsigned)(L.ny * L.nz); }
+// Grid of the per-node kernels: one workgroup per rpb lattice rows (gj, gk).
+inline unsigned node_grid(const Lattice &L) { return (unsigned)((L.ny * L.nz + L.rpb - 1) / L.rpb); }
 // Partial-sum capacity per quantity for any kernel of a mesh.
 inline int64_t part_capacity(const Lattice &L, int64_t E)
 {
@@ -64,6 +64,11 @@ template <typename T> hipError_t cg_restart(const Mesh &m, const CgVecs<T> &v, C
 hipError_t cg_alpha(const Mesh &m, const double *part_e, double *stage, CgState *st, hipStream_t s);
 // e = x - e on assembled vectors
 hipError_t cg_rsub(const Mesh &m, const double *x, double *e, hipStream_t s);
+// residual replacement of a low-precision run: r = inv_sigma * r64, x = 0,
+// p = first ? dinv r : p_scale * p; st: rr, rz, tol2 (first: it = 0, bb = rr)
+template <typename T>
+hipError_t cg_replace(const Mesh &m, const CgVecs<T> &v, const double *r64, CgState *st, double inv_sigma,
+                      double p_scale, int first, double tol2, hipStream_t s);
 template <typename T> hipError_t cg_axpy(const Mesh &m, double *y, const T *d, double scale, hipStream_t s);
 template <typename T> hipError_t cg_scale(const Mesh &m, const double *in, T *out, double scale, hipStream_t s);
 

@@ -27,6 +27,7 @@ struct Lattice {
     // so kernels enumerate copies with table reads instead of divisions.
     const int2 *tab[3];
     int unsorted;         // 1 if some axis is periodic with a single element
+    int rpb;              // lattice rows per workgroup of the per-node kernels
 };
 
 // Decode one axis entry.
@@ -64,14 +65,34 @@ __device__ inline int node_locals(const Lattice &L, int gi, int gj, int gk, int 
     return n;
 }
 
-// Loop over the global nodes of lattice row blockIdx.x = gj + ny gk (one
-// workgroup per row, threads over gi): no index is divided per node and every
-// row is independent work for the scheduler.  Launch with ny * nz blocks.
-// Binds gi, gj, gk (int) and g (int64 lexicographic id) for the body.
-#define SEM_FOR_EACH_NODE(L, gi, gj, gk, g)                                                        \
-    for (int gj = (int)(blockIdx.x % (L).ny), gk = (int)(blockIdx.x / (L).ny), gi = (int)threadIdx.x; \
-         gi < (L).nx; gi += (int)blockDim.x)                                                       \
-        if (const int64_t g = gi + (L).nx * (int64_t)blockIdx.x; true)
+// Logical workgroup id with the XCD layout of the chip in mind.  Workgroups
+// are handed to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8) and
+// every XCD has its own L2, so consecutive ids -- neighbouring elements or
+// lattice rows, which share cache lines -- would land in 8 different L2s.
+// The remap gives XCD x one contiguous range of logical ids (a bijection of
+// 0 .. gridDim.x - 1, also when gridDim.x is not a multiple of 8).
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const int64_t b = blockIdx.x, n = gridDim.x;
+    const int64_t q = n / kNumXcd, r = n % kNumXcd;
+    const int64_t x = b % kNumXcd, i = b / kNumXcd;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// Loop over the global nodes of lattice rows gj + ny gk in
+// [rpb xcd_block(), rpb xcd_block() + rpb) (threads over gi): no index is
+// divided per node, and a workgroup takes several consecutive rows so that
+// its partial-sum reduction and launch cost are spread over more nodes.
+// Launch with ceil(ny nz / rpb) blocks.  Binds gi, gj, gk (int) and g (int64
+// lexicographic id) for the body; `continue` skips one node.
+#define SEM_FOR_EACH_NODE(L, gi, gj, gk, g)                                                              \
+    for (int row_ = (int)xcd_block() * (L).rpb,                                                          \
+             rend_ = row_ + (L).rpb < (int)((L).ny * (L).nz) ? row_ + (L).rpb : (int)((L).ny * (L).nz); \
+         row_ < rend_; ++row_)                                                                           \
+        for (int gj = row_ % (int)(L).ny, gk = row_ / (int)(L).ny, gi = (int)threadIdx.x; gi < (L).nx;   \
+             gi += (int)blockDim.x)                                                                      \
+            if (const int64_t g = gi + (L).nx * (int64_t)row_; true)
 
 // Copies of a global index g along one direction, ascending in (element, local).
 // Returns the count (1 or 2); ec = element coordinate, lc = local coordinate.

@@ -258,7 +258,9 @@ static sem_status build(const sem_mesh_desc &d, Mesh &m)
     const int64_t nx = ndir(m.nelx, N, px), ny = ndir(m.nely, N, py), nz = ndir(m.nelz, N, pz);
     m.ng = nx * ny * nz;
     m.lat = Lattice{m.nelx, m.nely, m.nelz, N, NP, nx, ny, nz, P, {m.periodic[0], m.periodic[1], m.periodic[2]},
-                    m.dirichlet, {nullptr, nullptr, nullptr}, 0};
+                    m.dirichlet, {nullptr, nullptr, nullptr}, 0, 1};
+    // rows per workgroup: keep at least ~8k workgroups (32 per CU), at most 8 rows each
+    m.lat.rpb = (int)std::max<int64_t>(1, std::min<int64_t>(8, ny * nz / 8192));
     std::vector<int2> tab(nx + ny + nz);
     {
         const int nel[3] = {m.nelx, m.nely, m.nelz};
@@ -326,8 +328,15 @@ static sem_status build(const sem_mesh_desc &d, Mesh &m)
     SEM_TRY(upload(&m.d_mult, mult.data(), (size_t)nl, acc));
     {
         std::vector<float> D32(m.D.begin(), m.D.end());
-        std::vector<uint16_t> Dbf(m.D.size());
-        for (size_t q = 0; q < m.D.size(); ++q) Dbf[q] = to_bf16((float)m.D[q]);
+        // BF16 D as hi | lo pairs: hi = bf16(D), lo = bf16(D - hi)
+        std::vector<uint16_t> Dbf(2 * m.D.size());
+        for (size_t q = 0; q < m.D.size(); ++q) {
+            Dbf[q] = to_bf16((float)m.D[q]);
+            uint32_t hb = (uint32_t)Dbf[q] << 16;
+            float hf;
+            std::memcpy(&hf, &hb, 4);
+            Dbf[m.D.size() + q] = to_bf16((float)(m.D[q] - (double)hf));
+        }
         SEM_TRY(upload(&m.d_D32, D32.data(), D32.size(), acc));
         SEM_TRY(upload(&m.d_Dbf, Dbf.data(), Dbf.size(), acc));
     }

@@ -95,7 +95,7 @@ infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L,
     __shared__ __attribute__((aligned(16))) unsigned short Ys[PD3 * 16];
     __shared__ float red[8];
     const int p = threadIdx.x, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
-    const int64_t e = blockIdx.x;
+    const int64_t e = xcd_block();
     for (int q = p; q < 2 * PD3; q += 512) Xs[q] = 0.f;
     for (int q = p; q < PD3 * 8; q += 512) ((unsigned *)Ys)[q] = 0u;
     float t;
@@ -223,7 +223,7 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
     __shared__ float red[8];
     const int p = threadIdx.x, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
     const int base = pidx(k, j, i);
-    const int64_t e = blockIdx.x;
+    const int64_t e = xcd_block();
     float *dWe = dW + e * kParams;
     for (int q = p; q < 2 * PD3; q += 512) Xs[q] = 0.f;
     for (int q = p; q < 16 * PD3; q += 512) { Y1s[q] = 0.f; Bs[q] = 0.f; }
@@ -323,7 +323,7 @@ infer32_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice 
     __shared__ float Y2s[16 * PD3];
     __shared__ float red[8];
     const int p = threadIdx.x;
-    const int64_t e = blockIdx.x;
+    const int64_t e = xcd_block();
     for (int q = p; q < 2 * PD3; q += 512) Xs[q] = 0.f;
     for (int q = p; q < 16 * PD3; q += 512) { Y1s[q] = 0.f; Y2s[q] = 0.f; }
     float t;

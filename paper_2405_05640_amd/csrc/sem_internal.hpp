@@ -39,7 +39,7 @@ struct Mesh {
     // device data
     double *d_D = nullptr;     // [NP][NP]
     float *d_D32 = nullptr;
-    uint16_t *d_Dbf = nullptr; // bf16 bits
+    uint16_t *d_Dbf = nullptr; // bf16 bits: D rounded (P2 values), then the remainders D - hi
     double *d_G = nullptr;     // [E][6][P] element-blocked geometric factors
     double *d_B = nullptr;     // [E][P]
     double *d_xyz = nullptr;   // [3][E][P]
@@ -77,6 +77,9 @@ hipError_t launch_ax_f64_gather_batched(const Mesh &m, int nc, double h1, double
 // BF16 operator on the matrix cores (N = 7): u local bf16 bits, or (gather)
 // an assembled float vector rounded to bf16 on load; w float local.
 hipError_t launch_ax_bf16(const Mesh &m, float h1, float h2, const uint16_t *u, float *w, hipStream_t s);
+// split-BF16 operator: FP32 u (local, or assembled when gather), FP32 w, optional per-element u.w
+hipError_t launch_ax_bf16s(const Mesh &m, float h1, float h2, const float *u, float *w, double *partial,
+                           hipStream_t s, const int32_t *skip, bool gather);
 hipError_t launch_ax_bf16_gather(const Mesh &m, float h1, float h2, const float *ug, float *w, double *partial_uw,
                                  hipStream_t s, const int32_t *skip = nullptr);
 hipError_t launch_diag(const Mesh &m, double h1, double h2, double *d, hipStream_t s);

@@ -67,7 +67,7 @@ struct Workspace {
 bool uses_f32(int form)
 {
     return form == SEM_FORM_DC_FP32 || form == SEM_FORM_DC_BF16 || form == SEM_FORM_FCG_INNER_FP32 ||
-           form == SEM_FORM_FCG_INNER_BF16;
+           form == SEM_FORM_FCG_INNER_BF16 || form == SEM_FORM_RELIABLE_FP32 || form == SEM_FORM_RELIABLE_BF16;
 }
 bool uses_fcg(int form)
 {
@@ -149,6 +149,17 @@ sem_status check_opts(const Mesh &m, const sem_solve_opts *o)
             return fail(SEM_ERR_UNSUPPORTED, "the bf16 operator needs order N = 7");
         if (o->inner_iters < 1 || o->inner_iters > 10000) return fail(SEM_ERR_INVALID_ARG, "inner_iters must be in 1..10000");
         if (!(o->inner_tol >= 0.0 && o->inner_tol < 1.0)) return fail(SEM_ERR_INVALID_ARG, "inner_tol must be in [0, 1)");
+        return SEM_OK;
+    case SEM_FORM_RELIABLE_FP32:
+    case SEM_FORM_RELIABLE_BF16:
+        if (o->form == SEM_FORM_RELIABLE_FP32 && !m.d_G32)
+            return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_RELIABLE_FP32 needs a mesh created with SEM_PREP_F32");
+        if (o->form == SEM_FORM_RELIABLE_BF16 && !m.d_Gbf)
+            return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_RELIABLE_BF16 needs a mesh created with SEM_PREP_BF16");
+        if (o->form == SEM_FORM_RELIABLE_BF16 && m.N != 7)
+            return fail(SEM_ERR_UNSUPPORTED, "the bf16 operator needs order N = 7");
+        if (!(o->inner_tol > 0.0 && o->inner_tol < 1.0))
+            return fail(SEM_ERR_INVALID_ARG, "inner_tol (the replacement threshold) must be in (0, 1)");
         return SEM_OK;
     case SEM_FORM_FCG_LEARNED:
         if (!o->smoother) return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_FCG_LEARNED needs opts.smoother");
@@ -270,6 +281,77 @@ sem_status solve_dc32(const Mesh &m, const sem_solve_opts &o, const Workspace &w
     return SEM_OK;
 }
 
+// Low-precision CG with reliable updates (residual replacement after
+// Sleijpen & van der Vorst 1996 and van der Vorst & Ye 2000): the Krylov
+// recursion runs with FP32 vectors and the FP32 or split-BF16 operator on a
+// residual scaled to unit norm; the solution is accumulated in FP64.
+// Whenever the low-precision residual has fallen by delta = inner_tol below
+// its largest value since the last replacement (or meets the tolerance), the
+// host queues x64 += sigma x32, the FP64 true residual r64 = b - S x64, and
+// restarts the low-precision residual from r64 / |r64| while the search
+// direction is kept (rescaled), so the Krylov process is not restarted.
+sem_status solve_reliable(const Mesh &m, const sem_solve_opts &o, const Workspace &ws, int hist_len, hipStream_t s,
+                          int check_every, sem_solve_report *rep, CgState &h)
+{
+    const bool bf16 = o.form == SEM_FORM_RELIABLE_BF16;
+    SEM_TRY(reset_state(ws.st64, o.max_iter, hist_len, s));
+    SEM_HIP_TRY(cg_init<double>(m, ws.v64, ws.b64, ws.st64, o.rel_tol, nullptr, s));
+    SEM_TRY(read_state(h, ws.st64, s));
+    if (h.bb == 0.0) return SEM_OK;
+    h.true_rr = h.bb;
+    SEM_TRY(reset_state(ws.st32, o.max_iter, 0, s));
+    double sigma = std::sqrt(h.bb);
+    SEM_HIP_TRY(cg_replace<float>(m, ws.v32, ws.v64.r, ws.st32, 1.0 / sigma, 0.0, 1, h.tol2 / h.bb, s));
+    const double delta2 = o.inner_tol * o.inner_tol;
+    double rmax = 1.0, best = h.bb;
+    int updates = 0, stalls = 0;
+    CgState lo{};
+    for (;;) {
+        SEM_TRY(read_state(lo, ws.st32, s));
+        if (lo.done >= 2) { h.done = lo.done; break; }
+        rmax = std::max(rmax, lo.rr);
+        if (lo.done == 1 || lo.rr < delta2 * rmax) {
+            // reliable update: fold the low-precision solution into x64 and
+            // replace the residual by the FP64 true residual
+            SEM_HIP_TRY(cg_axpy<float>(m, ws.v64.x, ws.v32.x, sigma, s));
+            SEM_TRY(true_residual(m, o.h1, o.h2, ws, s, h));
+            ++updates;
+            if (h.true_rr <= h.tol2) { h.done = 1; break; }
+            if (!std::isfinite(h.true_rr)) { h.done = 2; break; }
+            if (h.true_rr < best) {
+                best = h.true_rr;
+                stalls = 0;
+            } else if (++stalls >= 3) {
+                h.done = 2;   // the true residual stopped decreasing
+                break;
+            }
+            if (lo.it >= o.max_iter) { h.done = 3; break; }
+            const double sn = std::sqrt(h.true_rr);
+            SEM_HIP_TRY(cg_replace<float>(m, ws.v32, ws.v64.r, ws.st32, 1.0 / sn, sigma / sn, 0, h.tol2 / h.true_rr, s));
+            sigma = sn;
+            rmax = 1.0;
+        }
+        for (int q = 0; q < check_every; ++q) {
+            if (bf16)
+                SEM_HIP_TRY(launch_ax_bf16s(m, (float)o.h1, (float)o.h2, ws.v32.p, ws.v32.w, ws.v32.part_e, s,
+                                            &ws.st32->done, true));
+            else
+                SEM_HIP_TRY(launch_ax_f32_gather(m, (float)o.h1, (float)o.h2, ws.v32.p, ws.v32.w, ws.v32.part_e, s,
+                                                 &ws.st32->done));
+            SEM_HIP_TRY(cg_step_after_ax<float>(m, ws.v32, ws.st32, nullptr, s));
+        }
+    }
+    if (h.done != 1) {
+        // report the FP64 true residual of what x64 holds
+        SEM_TRY(true_residual(m, o.h1, o.h2, ws, s, h));
+    }
+    h.rr = h.true_rr;
+    h.it = lo.it;
+    rep->iterations = lo.it;
+    rep->outer_iterations = updates;
+    return SEM_OK;
+}
+
 }  // namespace
 }  // namespace sem
 
@@ -295,6 +377,11 @@ sem_status sem_ax(const sem_mesh *mesh, double h1, double h2, sem_dtype in, cons
         if (!m.d_Gbf) return fail(SEM_ERR_INVALID_ARG, "mesh was created without SEM_PREP_BF16");
         if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "the bf16 operator needs order N = 7");
         SEM_HIP_TRY(launch_ax_bf16(m, (float)h1, (float)h2, (const uint16_t *)u, (float *)w, s));
+        return SEM_OK;
+    case SEM_BF16_SPLIT:
+        if (!m.d_Gbf) return fail(SEM_ERR_INVALID_ARG, "mesh was created without SEM_PREP_BF16");
+        if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "the bf16 operator needs order N = 7");
+        SEM_HIP_TRY(launch_ax_bf16s(m, (float)h1, (float)h2, (const float *)u, (float *)w, nullptr, s, nullptr, false));
         return SEM_OK;
     default:
         return fail(SEM_ERR_INVALID_ARG, "unknown dtype");
@@ -379,6 +466,8 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
         SEM_TRY(solve_fcg_nested(m, *opts, ws.v64, ws.v32, ws.b32, ws.b64, ws.z, ws.q, ws.st64, ws.st32, ws.hist,
                                  hist_len, std::max(1, std::min(check_every, 4)),
                                  opts->form == SEM_FORM_FCG_INNER_BF16, s, rep, h));
+    else if (opts->form == SEM_FORM_RELIABLE_FP32 || opts->form == SEM_FORM_RELIABLE_BF16)
+        SEM_TRY(solve_reliable(m, *opts, ws, hist_len, s, check_every, rep, h));
     else if (opts->form == SEM_FORM_FCG_LEARNED)
         SEM_TRY(solve_fcg(m, opts->smoother->s, *opts, ws.v64, ws.b64, ws.z, ws.q, ws.st64, ws.hist, hist_len,
                           check_every, s, rep, h));

@@ -19,10 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libsem.so")
 
 SEM_OK, SEM_ERR_INVALID_ARG, SEM_ERR_OUT_OF_MEMORY, SEM_ERR_HIP, SEM_ERR_NOT_CONVERGED, \
     SEM_ERR_BREAKDOWN, SEM_ERR_UNSUPPORTED = range(7)
-SEM_F64, SEM_F32, SEM_BF16 = 0, 1, 2
+SEM_F64, SEM_F32, SEM_BF16, SEM_BF16_SPLIT = 0, 1, 2, 3
 SEM_PREP_F32, SEM_PREP_BF16 = 1, 2
 FIELD_GLO_NUM, FIELD_MULT, FIELD_MASK, FIELD_G, FIELD_B, FIELD_XYZ, FIELD_GLL, FIELD_DERIV = range(8)
-FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED, FORM_FCG_INNER_FP32, FORM_FCG_INNER_BF16 = range(6)
+(FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED, FORM_FCG_INNER_FP32, FORM_FCG_INNER_BF16,
+ FORM_RELIABLE_FP32, FORM_RELIABLE_BF16) = range(8)
 SMOOTHER_PARAMS = 8208
 
 EXPORTED_SYMBOLS = [
@@ -241,7 +242,8 @@ class Mesh:
 
     # ------------------------------------------------------------ ops
     def ax(self, u, w, h1=1.0, h2=0.0, dtype=SEM_F64):
-        name = {SEM_F64: ("f64", "f64"), SEM_F32: ("f32", "f32"), SEM_BF16: ("bf16", "f32")}[dtype]
+        name = {SEM_F64: ("f64", "f64"), SEM_F32: ("f32", "f32"), SEM_BF16: ("bf16", "f32"),
+                SEM_BF16_SPLIT: ("f32", "f32")}[dtype]
         pu = _want(u, name[0], self.n_local, "u")
         pw = _want(w, name[1], self.n_local, "w")
         _check(lib().sem_ax(self._h, float(h1), float(h2), dtype, pu, pw, _stream()))

@@ -247,6 +247,28 @@ def test_ax_bf16_matrix_cores():
         assert np.linalg.norm(wg - we) <= np.linalg.norm(we - w64)
 
 
+@pytest.mark.parametrize("spec", [wl.deformed_cube(3, 7), wl.channel(3, 7)], ids=["deformed3_N7", "channel3_N7"])
+def test_ax_bf16_split_matrix_cores(spec):
+    # the split-BF16 operator against the exact operator with BF16-stored G
+    # and B: within a 2^-15-level bound (about 2^-8 tighter than the plain
+    # BF16 operator), and far closer to it than that operator is to FP64
+    import torch
+    from oracle import mixed
+    om, gm = pair(spec, prepare=sem.SEM_PREP_BF16)
+    rng = np.random.default_rng(26)
+    u32 = rng.standard_normal(om.shape).astype(np.float32)
+    u = u32.astype(np.float64)
+    for h2 in (0.0, 0.1):
+        w = torch.empty(gm.shape, dtype=torch.float32, device="cuda")
+        gm.ax(dev(u32, torch.float32), w, 1.0, h2, dtype=sem.SEM_BF16_SPLIT)
+        wg = host(w).astype(np.float64)
+        ref = mixed.ax_bf16_split_reference(om, u, 1.0, h2)
+        bound = (3 * (om.N + 1) + 6) * 2.0 ** -15 * om.ax_abs_bound(u, 1.0, h2)
+        assert np.all(np.abs(wg - ref) <= bound + 1e-30)
+        w64 = om.ax(u, 1.0, h2)
+        assert np.linalg.norm(wg - ref) <= 0.05 * np.linalg.norm(ref - w64)
+
+
 @pytest.mark.parametrize("spec", [wl.deformed_cube(4, 7), wl.channel(3, 7)], ids=["deformed4_N7", "channel3_N7"])
 def test_dc_bf16_solve_reaches_fp64_tolerance(spec):
     import torch
@@ -282,6 +304,32 @@ def test_nested_fcg_reaches_fp64_tolerance(spec, form, prep):
     _, info = om.pcg(b, 1.0, h2)
     print("nested %s %s: %d outer, %d inner; FP64 PCG %d" % (spec.name, form, rep.outer_iterations, rep.iterations,
                                                             info["iterations"]))
+
+
+@pytest.mark.parametrize("form,prep,delta", [(sem.FORM_RELIABLE_FP32, sem.SEM_PREP_F32, 1e-2),
+                                             (sem.FORM_RELIABLE_BF16, sem.SEM_PREP_BF16, 0.1)],
+                         ids=["reliable_fp32", "reliable_bf16split"])
+@pytest.mark.parametrize("spec", [wl.deformed_cube(4, 7), wl.channel(3, 7)], ids=["deformed4_N7", "channel3_N7"])
+def test_reliable_update_cg_reaches_fp64_tolerance(spec, form, prep, delta):
+    # the FP64 true residual (evaluated by the oracle) meets 1e-10; with the
+    # FP32 operator the kept search direction holds the iteration count near
+    # the FP64 PCG count (a restarted defect correction would not)
+    import torch
+    om, gm = pair(spec, prepare=prep)
+    h2 = 0.1 if spec.name.startswith("deformed") else 0.0
+    rng = np.random.default_rng(25)
+    b = om.rhs(rng.standard_normal(om.shape))
+    x = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
+    rep = gm.pcg_solve(dev(b), x, h1=1.0, h2=h2, rel_tol=1e-10, form=form, inner_tol=delta, check_every=4)
+    xg = host(x)
+    r = b - om.apply_S(xg, 1.0, h2)
+    assert np.sqrt(om.dot(r, r) / om.dot(b, b)) <= 1.05e-10
+    assert rep.outer_iterations >= 2
+    _, info = om.pcg(b, 1.0, h2)
+    if form == sem.FORM_RELIABLE_FP32:
+        assert rep.iterations <= 1.25 * info["iterations"] + 8
+    print("reliable %s %s: %d iterations, %d replacements; FP64 PCG %d" %
+          (spec.name, form, rep.iterations, rep.outer_iterations, info["iterations"]))
 
 
 @pytest.mark.parametrize("spec,h2", [(wl.deformed_cube(3, 7), 5.0), (wl.channel(3, 7), 0.0)],

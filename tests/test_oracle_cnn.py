@@ -154,3 +154,23 @@ def test_bf16_rounding_and_lowp_operator_bounds():
     e16 = np.linalg.norm(mixed.ax_lowp(m, u, 1.0, 0.1, "bf16") - w64)
     e32 = np.linalg.norm(mixed.ax_lowp(m, u, 1.0, 0.1, "f32") - w64)
     assert e16 > 100 * e32
+
+
+def test_bf16_storage_reference_operator():
+    # the split-BF16 operator's reference: the exact operator with G and B
+    # rounded to BF16.  Rounding is idempotent, the operator stays symmetric
+    # (G12, G13, G23 are shared by both of their uses), and it differs from
+    # the FP64 operator by at most the storage rounding of G and B
+    from oracle import mixed
+    m = _mesh(wl.deformed_cube(2, 7, amp=0.2))
+    Gb = mixed.bf16_storage(m.G)
+    assert np.array_equal(mixed.bf16_storage(Gb), Gb)
+    assert np.all(np.abs(Gb - m.G) <= 2.0 ** -8 * np.abs(m.G) + 1e-37)   # float32 underflow of ~0 entries
+    rng = np.random.default_rng(3)
+    u, v = rng.standard_normal(m.shape), rng.standard_normal(m.shape)
+    au = mixed.ax_bf16_split_reference(m, u, 1.0, 0.1)
+    av = mixed.ax_bf16_split_reference(m, v, 1.0, 0.1)
+    assert abs(np.sum(v * au) - np.sum(u * av)) <= 1e-12 * np.sum(np.abs(v * au))
+    w64 = m.ax(u, 1.0, 0.1)
+    assert np.all(np.abs(au - w64) <= 2.0 ** -8 * m.ax_abs_bound(u, 1.0, 0.1) + 1e-30)
+    assert np.linalg.norm(au - w64) > 0.0
