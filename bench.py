@@ -57,25 +57,36 @@ def parse():
 
 
 def profile_kernels():
-    """Short, fixed launch sequence for rocprofv3 counter runs: 5 x (sem_ax,
-    sem_dssum) on the 32^3 workload, one 300-iteration FP64 PCG solve, and
-    5 copies of a 1 GiB buffer (exactly 1 GiB read + 1 GiB written each)."""
+    """Short, fixed launch sequence for rocprofv3 counter runs on the 32^3
+    workload: 5 x (sem_ax, sem_dssum) in FP64, 5 x sem_ax in FP32 and split
+    BF16, a 300-iteration FP64 PCG solve and 300-iteration FP32 and BF16
+    reliable-update solves (the solvers' gather-mode kernels), and 5 copies of
+    a 1 GiB buffer (exactly 1 GiB read + 1 GiB written each)."""
     import torch
 
     from paper_2405_05640_amd import sem
     from paper_2405_05640_amd import workloads as wl
     torch.cuda.set_device(0)
     spec = wl.deformed_cube(32, 7)
-    mesh = sem.Mesh.from_spec(spec)
+    mesh = sem.Mesh.from_spec(spec, prepare=sem.SEM_PREP_F32 | sem.SEM_PREP_BF16)
     u = torch.rand(mesh.shape, dtype=torch.float64, device="cuda")
     w = torch.empty_like(u)
     for _ in range(5):
         mesh.ax(u, w, 1.0, 0.1)
         mesh.dssum(w, mask=True)
+    u32 = u.float()
+    w32 = torch.empty_like(u32)
+    for _ in range(5):
+        mesh.ax(u32, w32, 1.0, 0.1, dtype=sem.SEM_F32)
+    for _ in range(5):
+        mesh.ax(u32, w32, 1.0, 0.1, dtype=sem.SEM_BF16_SPLIT)
     b = torch.empty_like(u)
     mesh.rhs(u, b)
     x = torch.zeros_like(b)
     mesh.pcg_solve(b, x, h1=1.0, h2=0.1, max_iter=300, raise_on_error=False)
+    for form in (sem.FORM_RELIABLE_FP32, sem.FORM_RELIABLE_BF16):
+        x.zero_()
+        mesh.pcg_solve(b, x, h1=1.0, h2=0.1, max_iter=300, raise_on_error=False, form=form, inner_tol=0.1)
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(5):

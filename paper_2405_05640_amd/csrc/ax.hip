@@ -23,8 +23,10 @@
 namespace sem {
 namespace {
 
+
 // GATHER: u is an assembled vector (one value per global node) read through
-// the closed-form numbering; otherwise u is local [E][P].
+// the closed-form numbering and w is written in the row layout; otherwise u
+// and w are local [E][P].
 template <typename T, int NP, bool HELM, bool DOT, bool GATHER>
 __global__ void __launch_bounds__(NP * NP)
 ax_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G,
@@ -43,13 +45,14 @@ ax_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G,
     const int i = t % NP;
     const int j = t / NP;
     const int64_t e = xcd_block();
+    int ex = 0, ey = 0, ez = 0;   // element coordinates (gather mode)
+    if (GATHER) elem_coords(L, e, ex, ey, ez);
     const T *Ge = G + e * (6 * P3);
 
     sD[t] = Dg[t];
 
     T ru[NP], rw[NP];
     if (GATHER) {
-        const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);
         int64_t gi = ex * (NP - 1) + i, gj = ey * (NP - 1) + j;
         if (gi >= L.nx) gi -= L.nx;
         if (gj >= L.ny) gj -= L.ny;
@@ -118,13 +121,12 @@ ax_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G,
         }
     }
 
-    T *we = w + e * P3;
     double dot = 0.0;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         T v = h1 * rw[k];
         if (HELM) v += h2 * Bm[e * P3 + k * P2 + t] * ru[k];
-        we[k * P2 + t] = v;
+        w[GATHER ? rows_index(L, ex, ey, ez, i, j, k) : e * P3 + k * P2 + t] = v;
         if (DOT) dot += (double)ru[k] * (double)v;
     }
     if (DOT) {
@@ -160,9 +162,10 @@ ax_pt_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G
     __shared__ T sD[P2], su[P3], sr[P3], ss[P3], st[P3];
     const int t = threadIdx.x, i = t % NP, j = (t / NP) % NP, k = t / P2;
     const int64_t e = xcd_block();
+    int ex = 0, ey = 0, ez = 0;   // element coordinates (gather mode)
+    if (GATHER) elem_coords(L, e, ex, ey, ez);
     T uv;
     if (GATHER) {
-        const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);
         int64_t gi = ex * (NP - 1) + i, gj = ey * (NP - 1) + j, gk = ez * (NP - 1) + k;
         if (gi >= L.nx) gi -= L.nx;
         if (gj >= L.ny) gj -= L.ny;
@@ -197,8 +200,23 @@ ax_pt_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G
                sD[m * NP + k] * st[m * P2 + j * NP + i];
     T v = h1 * acc;
     if (HELM) v += h2 * bv * uv;
-    w[e * P3 + t] = v;
-    if (DOT) {
+    w[GATHER ? rows_index(L, ex, ey, ez, i, j, k) : e * P3 + t] = v;
+    if constexpr (DOT && P3 % 64 == 0) {
+        // full wavefronts: fixed butterfly within each wave, then the wave
+        // sums in wave order (deterministic)
+        __shared__ double wred[P3 / 64 > 0 ? P3 / 64 : 1];
+        double d = (double)uv * (double)v;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+        if ((t & 63) == 0) wred[t >> 6] = d;
+        __syncthreads();
+        if (t == 0) {
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < P3 / 64; ++q) sum += wred[q];
+            partial[e] = sum;
+        }
+    } else if (DOT) {
         // fixed-order tree over the (N+1)^3 threads (the last wavefront may be
         // partial, so no cross-lane shuffles)
         __shared__ double red[P3];
@@ -210,6 +228,94 @@ ax_pt_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G
             __syncthreads();
         }
         if (t == 0) partial[e] = red[0];
+    }
+}
+
+// Two points per thread (N = 7, FP32): a workgroup of 256 threads per
+// element, thread t owning points (i, j, k) and (i, j, k + 4).  Each thread
+// then keeps twice the bytes in flight (16 streaming loads), which the FP32
+// operator needs to approach the bandwidth the FP64 one reaches with one
+// point per thread; the derivative rows of i and j are shared by both points.
+template <typename T, bool HELM, bool DOT, bool GATHER>
+__global__ void __launch_bounds__(256)
+ax_pt2_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G, const T *__restrict__ Bm,
+              const T *__restrict__ Dg, T h1, T h2, double *__restrict__ partial, const int32_t *__restrict__ skip,
+              Lattice L)
+{
+    if (skip && *skip) return;
+    constexpr int NP = 8, P2 = 64, P3 = 512, H = 256;
+    __shared__ T sD[P2], su[P3], sr[P3], ss[P3], st[P3];
+    const int t = threadIdx.x, i = t & 7, j = (t >> 3) & 7, k0 = t >> 6;   // second point: k0 + 4
+    const int64_t e = xcd_block();
+    int ex = 0, ey = 0, ez = 0;
+    if (GATHER) elem_coords(L, e, ex, ey, ez);
+    T uv[2];
+    if (GATHER) {
+        int64_t gi = ex * 7 + i, gj = ey * 7 + j;
+        if (gi >= L.nx) gi -= L.nx;
+        if (gj >= L.ny) gj -= L.ny;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            int64_t gk = ez * 7 + k0 + 4 * q;
+            if (gk >= L.nz) gk -= L.nz;
+            uv[q] = u[gi + L.nx * (gj + L.ny * gk)];
+        }
+    } else {
+        uv[0] = ldnt(&u[e * P3 + t]);
+        uv[1] = ldnt(&u[e * P3 + H + t]);
+    }
+    const T *Ge = G + e * 6 * P3;
+    T g[2][6];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) g[q][c] = ldnt(&Ge[c * P3 + q * H + t]);
+    T bv[2] = {T(0), T(0)};
+    if (HELM) {
+        bv[0] = ldnt(&Bm[e * P3 + t]);
+        bv[1] = ldnt(&Bm[e * P3 + H + t]);
+    }
+    if (t < P2) sD[t] = Dg[t];
+    su[t] = uv[0];
+    su[H + t] = uv[1];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int k = k0 + 4 * q;
+        T ur = T(0), us = T(0), ut = T(0);
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+            ur += sD[i * NP + m] * su[k * P2 + j * NP + m];
+            us += sD[j * NP + m] * su[k * P2 + m * NP + i];
+            ut += sD[k * NP + m] * su[m * P2 + j * NP + i];
+        }
+        const int tq = q * H + t;
+        sr[tq] = g[q][0] * ur + g[q][1] * us + g[q][2] * ut;
+        ss[tq] = g[q][1] * ur + g[q][3] * us + g[q][4] * ut;
+        st[tq] = g[q][2] * ur + g[q][4] * us + g[q][5] * ut;
+    }
+    __syncthreads();
+    double dot = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int k = k0 + 4 * q;
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < NP; ++m)
+            acc += sD[m * NP + i] * sr[k * P2 + j * NP + m] + sD[m * NP + j] * ss[k * P2 + m * NP + i] +
+                   sD[m * NP + k] * st[m * P2 + j * NP + i];
+        T v = h1 * acc;
+        if (HELM) v += h2 * bv[q] * uv[q];
+        w[GATHER ? rows_index(L, ex, ey, ez, i, j, k) : e * P3 + q * H + t] = v;
+        dot += (double)uv[q] * (double)v;
+    }
+    if constexpr (DOT) {
+        __shared__ double wred[H / 64];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
+        if ((t & 63) == 0) wred[t >> 6] = dot;
+        __syncthreads();
+        if (t == 0) partial[e] = ((wred[0] + wred[1]) + wred[2]) + wred[3];
     }
 }
 
@@ -231,12 +337,13 @@ ax_pt_batched_kernel(const double *__restrict__ u, int64_t ustride, double *__re
     }
     constexpr int P2 = NP * NP, P3 = NP * NP * NP;
     __shared__ double sD[P2], su[P3], sr[P3], ss[P3], st[P3];
-    __shared__ double red[P3];
+    __shared__ double red[P3 / 64];
     const int t = threadIdx.x, i = t % NP, j = (t / NP) % NP, k = t / P2;
     const int64_t e = xcd_block();
+    int ex = 0, ey = 0, ez = 0;   // element coordinates (gather mode)
+    if (GATHER) elem_coords(L, e, ex, ey, ez);
     int64_t src;
     if (GATHER) {
-        const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);
         int64_t gi = ex * (NP - 1) + i, gj = ey * (NP - 1) + j, gk = ez * (NP - 1) + k;
         if (gi >= L.nx) gi -= L.nx;
         if (gj >= L.ny) gj -= L.ny;
@@ -277,16 +384,22 @@ ax_pt_batched_kernel(const double *__restrict__ u, int64_t ustride, double *__re
                    sD[m * NP + k] * st[m * P2 + j * NP + i];
         double v = h1 * acc;
         if (HELM) v += h2 * bv * uv[c];
-        w[c * nl + e * P3 + t] = v;
+        w[c * nl + (GATHER ? rows_index(L, ex, ey, ez, i, j, k) : e * P3 + t)] = v;
         if (partial) {
-            red[t] = uv[c] * v;
+            // same order as the single-field kernel: butterfly per wavefront,
+            // then the wave sums in wave order
+            static_assert(P3 % 64 == 0, "full wavefronts");
+            double d = uv[c] * v;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+            if ((t & 63) == 0) red[t >> 6] = d;
             __syncthreads();
-            constexpr int top = P3 <= 2 ? 1 : (P3 <= 4 ? 2 : (P3 <= 8 ? 4 : (P3 <= 16 ? 8 : (P3 <= 32 ? 16 : (P3 <= 64 ? 32 : (P3 <= 128 ? 64 : (P3 <= 256 ? 128 : 256)))))));
-            for (int h = top; h > 0; h >>= 1) {
-                if (t < h && t + h < P3) red[t] += red[t + h];
-                __syncthreads();
+            if (t == 0) {
+                double sum = 0.0;
+#pragma unroll
+                for (int q = 0; q < P3 / 64; ++q) sum += red[q];
+                partial[c * (int64_t)gridDim.x + e] = sum;
             }
-            if (t == 0) partial[c * (int64_t)gridDim.x + e] = red[0];
         }
     }
 }
@@ -327,6 +440,27 @@ hipError_t launch_pt(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, co
     return hipGetLastError();
 }
 
+template <typename T, bool GATHER>
+hipError_t launch_pt2(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, const T *B, const T *D,
+                      double *partial, const int32_t *skip, hipStream_t s)
+{
+    const dim3 grid((unsigned)m.E), block(256);
+    const bool helm = (h2 != T(0));
+    const Lattice &L = m.lat;
+    if (partial) {
+        if (helm)
+            hipLaunchKernelGGL((ax_pt2_kernel<T, true, true, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+        else
+            hipLaunchKernelGGL((ax_pt2_kernel<T, false, true, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+    } else {
+        if (helm)
+            hipLaunchKernelGGL((ax_pt2_kernel<T, true, false, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+        else
+            hipLaunchKernelGGL((ax_pt2_kernel<T, false, false, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int NP, bool GATHER>
 hipError_t launch_np(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, const T *B,
                      const T *D, double *partial, const int32_t *skip, hipStream_t s)
@@ -360,7 +494,9 @@ hipError_t launch_any(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, c
     case 5: return launch_pt<T, 5, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 6: return launch_pt<T, 6, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 7: return launch_pt<T, 7, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
-    case 8: return launch_pt<T, 8, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
+    case 8:
+        if constexpr (sizeof(T) == 4) return launch_pt2<T, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
+        else return launch_pt<T, 8, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 9: return launch_np<T, 9, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 10: return launch_np<T, 10, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 11: return launch_np<T, 11, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);

@@ -24,13 +24,8 @@ typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
 
-__device__ __forceinline__ unsigned short f2bf(float f)
-{
-    unsigned u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
+// FP32 -> BF16, round to nearest even (the gfx950 conversion instruction)
+__device__ __forceinline__ unsigned short f2bf(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
 // BF16 number q (0..7) of a 16-byte vector, widened to FP32
 __device__ __forceinline__ float bf_at(const u32x4 &v, int q)
@@ -97,6 +92,8 @@ ax_bf16_kernel(const void *__restrict__ uin, float *__restrict__ w, const unsign
     __shared__ unsigned short sD[64];
     const int lane = threadIdx.x;
     const int64_t e = xcd_block();
+    int ex = 0, ey = 0, ez = 0;   // element coordinates (gather mode)
+    if (GATHER) elem_coords(L, e, ex, ey, ez);
     // Issue every streaming load of the element first (G: six 16-byte
     // vectors per lane, each lane owning the contiguous 8-point row 8 lane ..
     // 8 lane + 7; B likewise) so that their latency overlaps the u gather and
@@ -111,7 +108,6 @@ ax_bf16_kernel(const void *__restrict__ uin, float *__restrict__ w, const unsign
     // u tile (BF16) into LDS: each lane 8 consecutive points
     if (GATHER) {
         const float *ug = (const float *)uin;
-        const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int p = lane * 8 + q, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
@@ -171,7 +167,7 @@ ax_bf16_kernel(const void *__restrict__ uin, float *__restrict__ w, const unsign
         out[q] = v;
         if (partial) dot += (double)uu * (double)v;
     }
-    float4 *wo = (float4 *)(w + e * 512) + 2 * lane;
+    float4 *wo = (float4 *)(w + (GATHER ? rows_index(L, ex, ey, ez, 0, lane & 7, lane >> 3) : e * 512 + 8 * lane));
     wo[0] = make_float4(out[0], out[1], out[2], out[3]);
     wo[1] = make_float4(out[4], out[5], out[6], out[7]);
     if (partial) {
@@ -202,22 +198,22 @@ __device__ __forceinline__ void contract_split(int dir, const float *src, float 
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int L = 16 * t + m;
-        s16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (g < 3) {
-            float v[8];
-            if (dir == 0) {
-                const float4 v0 = *(const float4 *)&src[L * 8], v1 = *(const float4 *)&src[L * 8 + 4];
-                v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
-                v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
-            } else {
+        // every lane reads its line (branch-free); group 3 contributes zeros
+        float v[8];
+        if (dir == 0) {
+            const float4 v0 = *(const float4 *)&src[L * 8], v1 = *(const float4 *)&src[L * 8 + 4];
+            v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+            v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+        } else {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) v[q] = src[line_point(dir, L, q)];
-            }
+            for (int q = 0; q < 8; ++q) v[q] = src[line_point(dir, L, q)];
+        }
+        s16x8 a;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const unsigned short h = f2bf(v[q]);
-                a[q] = (short)(g == 1 ? f2bf(v[q] - bf2f(h)) : h);
-            }
+        for (int q = 0; q < 8; ++q) {
+            const float x = g == 3 ? 0.f : v[q];
+            const float h = bf2f(f2bf(x));
+            a[q] = (short)f2bf(g == 1 ? x - h : x);
         }
         f4 c = {0.f, 0.f, 0.f, 0.f};
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), bop, c, 0, 0, 0);
@@ -247,6 +243,8 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
     __shared__ unsigned short sD[128];                           // D hi | D lo
     const int lane = threadIdx.x;
     const int64_t e = xcd_block();
+    int ex = 0, ey = 0, ez = 0;   // element coordinates (gather mode)
+    if (GATHER) elem_coords(L, e, ex, ey, ez);
     const unsigned short *Ge = G + e * 6 * 512;
     u32x4 gq[6];
 #pragma unroll
@@ -258,7 +256,6 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
     // lane owns the 8-point row p = 8 lane + q: i = q, j = lane & 7, k = lane >> 3
     float uu[8];
     if (GATHER) {
-        const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);
         int64_t gj = ey * 7 + (lane & 7), gk = ez * 7 + (lane >> 3);
         if (gj >= L.ny) gj -= L.ny;
         if (gk >= L.nz) gk -= L.nz;
@@ -329,7 +326,7 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
         out[q] = v;
         if (partial) dot += (double)uu[q] * (double)v;
     }
-    float4 *wo = (float4 *)(w + e * 512) + 2 * lane;
+    float4 *wo = (float4 *)(w + (GATHER ? rows_index(L, ex, ey, ez, 0, lane & 7, lane >> 3) : e * 512 + 8 * lane));
     wo[0] = make_float4(out[0], out[1], out[2], out[3]);
     wo[1] = make_float4(out[4], out[5], out[6], out[7]);
     if (partial) {

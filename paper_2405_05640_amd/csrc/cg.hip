@@ -28,12 +28,14 @@ __device__ __forceinline__ void g_to_ijk(const Lattice &L, int64_t g, int64_t &g
     gk = t / L.ny;
 }
 
-template <typename T>
+// ROWS: w is an operator output in the row layout (solver operator calls);
+// otherwise [E][k][j][i].
+template <bool ROWS, typename T>
 __device__ __forceinline__ double assemble_at(const Lattice &L, const T *__restrict__ w, int gi, int gj, int gk,
                                               bool &masked)
 {
     int loc[8];
-    const int n = node_locals(L, gi, gj, gk, loc, masked);
+    const int n = node_locals<ROWS>(L, gi, gj, gk, loc, masked);
     T s = T(0);
     for (int c = 0; c < n; ++c) s += w[loc[c]];
     return (double)s;
@@ -112,7 +114,7 @@ __global__ void __launch_bounds__(kBS) dinv_kernel(const double *__restrict__ dl
     SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
     {
         bool msk;
-        const double d = assemble_at(L, dl, gi, gj, gk, msk);
+        const double d = assemble_at<false>(L, dl, gi, gj, gk, msk);
         dinv[g] = msk ? T(0) : (T)(1.0 / d);
     }
 }
@@ -183,7 +185,7 @@ __global__ void __launch_bounds__(kBS) alpha_kernel(CgState *st, const double *_
     }
 }
 
-// wg = Q^T w; x += alpha p; r -= alpha wg; partials (r,r), (r, dinv r)
+// wg = Q^T w (w in the row layout); x += alpha p; r -= alpha wg; partials (r,r), (r, dinv r)
 template <typename T>
 __global__ void __launch_bounds__(kBS)
 update_kernel(const CgState *__restrict__ st, const T *__restrict__ w, T *__restrict__ x, T *__restrict__ r,
@@ -192,17 +194,34 @@ update_kernel(const CgState *__restrict__ st, const T *__restrict__ w, T *__rest
     if (st->done) return;
     const T alpha = (T)st->alpha;
     double acc[2] = {0.0, 0.0};
-    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
-    {
-        const T d = dinv[g];
-        if (d == T(0)) continue;   // Dirichlet node: r, p, x stay zero
-        bool msk;
-        const T wg = (T)assemble_at(L, w, gi, gj, gk, msk);
-        x[g] += alpha * p[g];
-        const T rg = r[g] - alpha * wg;
-        r[g] = rg;
-        acc[0] += (double)rg * (double)rg;
-        acc[1] += (double)rg * (double)(d * rg);
+    // RPB rows per workgroup, unrolled so that the loads of all of them are
+    // in flight together
+    constexpr int RPB = update_rpb<T>();
+    const int nrows = (int)(L.ny * L.nz), row0 = (int)blockIdx.x * RPB;
+    for (int gi = threadIdx.x; gi < L.nx; gi += kBS) {
+        T d[RPB], xg[RPB], pg[RPB], rg0[RPB], wg[RPB];
+        int64_t g[RPB];
+#pragma unroll
+        for (int q = 0; q < RPB; ++q) {
+            const int row = row0 + q < nrows ? row0 + q : nrows - 1;   // clamped rows are not stored
+            g[q] = gi + L.nx * (int64_t)row;
+            d[q] = dinv[g[q]];
+            xg[q] = x[g[q]];
+            pg[q] = p[g[q]];
+            rg0[q] = r[g[q]];
+            const RowCopies rc = row_copies(L, row % (int)L.ny, row / (int)L.ny);
+            bool msk;
+            wg[q] = row_assemble(L, w, rc, gi, msk);
+        }
+#pragma unroll
+        for (int q = 0; q < RPB; ++q) {
+            if (row0 + q >= nrows || d[q] == T(0)) continue;   // Dirichlet node: r, p, x stay zero
+            x[g[q]] = xg[q] + alpha * pg[q];
+            const T rg = rg0[q] - alpha * wg[q];
+            r[g[q]] = rg;
+            acc[0] += (double)rg * (double)rg;
+            acc[1] += (double)rg * (double)(d[q] * rg);
+        }
     }
     block_store<2>(acc, part, gridDim.x);
 }
@@ -240,20 +259,24 @@ p_kernel(const CgState *__restrict__ st, T *__restrict__ p, const T *__restrict_
     GRID_STRIDE(g, ng) p[g] = dinv[g] * r[g] + beta * p[g];
 }
 
-// r = b - Q^T w (0 on Dirichlet nodes); partial (r, r)
+// r = b - Q^T w (w in the row layout; 0 on Dirichlet nodes); partial (r, r)
 template <typename T>
 __global__ void __launch_bounds__(kBS)
 resid_kernel(const T *__restrict__ b, const T *__restrict__ w, T *__restrict__ r, const T *__restrict__ dinv, Lattice L,
              double *__restrict__ part)
 {
     double acc[1] = {0.0};
-    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
+    SEM_FOR_EACH_ROW(L, 1, gj, gk, row, rc)
     {
-        T rg = T(0);
-        bool msk;
-        if (dinv[g] != T(0)) rg = b[g] - (T)assemble_at(L, w, gi, gj, gk, msk);
-        r[g] = rg;
-        acc[0] += (double)rg * (double)rg;
+        for (int gi = threadIdx.x; gi < L.nx; gi += kBS) {
+            const int64_t g = gi + L.nx * (int64_t)row;
+            const T d = dinv[g], bg = b[g];
+            bool msk;
+            const T wg = row_assemble(L, w, rc, gi, msk);
+            const T rg = d != T(0) ? bg - wg : T(0);
+            r[g] = rg;
+            acc[0] += (double)rg * (double)rg;
+        }
     }
     block_store<1>(acc, part, gridDim.x);
 }
@@ -292,8 +315,12 @@ __global__ void __launch_bounds__(kBS) restart_finalize(CgState *st, const doubl
 }
 
 // Residual replacement (reliable update) of a low-precision CG: r = inv_sigma
-// * r64 (the FP64 true residual), x = 0, p = first ? dinv r : p_scale * p;
-// partials (r, r), (r, dinv r)
+// * r64 (the FP64 true residual), x = 0, and p = dinv r on the first call.
+// Later calls keep the search direction but swap its preconditioned-residual
+// part: the last direction update was p = dinv r_old + beta p_prev, so
+// p + dinv (r_new - r_old) is the direction the new residual would have
+// produced; p_scale = sigma_old / sigma_new converts to the new units.
+// Partials (r, r), (r, dinv r).
 template <typename T>
 __global__ void __launch_bounds__(kBS)
 replace_kernel(const double *__restrict__ r64, T *__restrict__ x, T *__restrict__ r, T *__restrict__ p,
@@ -307,8 +334,13 @@ replace_kernel(const double *__restrict__ r64, T *__restrict__ x, T *__restrict_
         const T rg = d == T(0) ? T(0) : (T)(inv_sigma * r64[g]);
         const T z = d * rg;
         x[g] = T(0);
+        if (first) {
+            p[g] = z;
+        } else {
+            const double r_old = (double)r[g];
+            p[g] = (T)(p_scale * (double)p[g] + (double)d * ((double)rg - p_scale * r_old));
+        }
         r[g] = rg;
-        p[g] = first ? z : (T)(p_scale * (double)p[g]);
         acc[0] += (double)rg * (double)rg;
         acc[1] += (double)rg * (double)z;
     }
@@ -397,7 +429,7 @@ hipError_t cg_init(const Mesh &m, const CgVecs<T> &v, const T *b, CgState *st, d
 template <typename T>
 hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, double *hist, hipStream_t s)
 {
-    const int64_t rows = node_grid(m.lat);
+    const int64_t rows = row_grid(m.lat, update_rpb<T>());
     hipError_t e = cg_alpha(m, v.part_e, v.stage, st, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((cg::update_kernel<T>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,

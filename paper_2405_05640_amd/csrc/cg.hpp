@@ -11,8 +11,13 @@ constexpr int kBS = 256;             // threads per block of the vector kernels
 constexpr int kMaxVecBlocks = 4096;  // grid cap of the flat vector kernels
 constexpr int kStage = 256;          // second-stage partial sums
 
-// Grid of the per-node kernels: one workgroup per rpb lattice rows (gj, gk).
-inline unsigned node_grid(const Lattice &L) { return (unsigned)((L.ny * L.nz + L.rpb - 1) / L.rpb); }
+// Grid of the per-node kernels: one workgroup per lattice row (gj, gk).
+inline unsigned node_grid(const Lattice &L) { return (unsigned)(L.ny * L.nz); }
+// Rows per workgroup of the CG update (a measured choice: the per-workgroup
+// prologue is a chain of scalar loads, and FP32 rows carry half the bytes, so
+// FP32 takes four rows per workgroup and FP64 two).
+template <typename T> constexpr int update_rpb() { return sizeof(T) == 4 ? 4 : 2; }
+inline unsigned row_grid(const Lattice &L, int rpb) { return (unsigned)((L.ny * L.nz + rpb - 1) / rpb); }
 // Partial-sum capacity per quantity for any kernel of a mesh.
 inline int64_t part_capacity(const Lattice &L, int64_t E)
 {

@@ -29,8 +29,7 @@ __global__ void __launch_bounds__(256)
 gs_rows_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip)
 {
     if (skip && *skip) return;
-    const int row = (int)xcd_block();   // one row per workgroup
-    const int gj = row % L.ny, gk = row / L.ny;
+    const int gj = (int)(blockIdx.x % L.ny), gk = (int)(blockIdx.x / L.ny);   // one row per workgroup
     const int2 ay = L.tab[1][gj], az = L.tab[2][gk];
     const bool full = axis_count(ay) > 1 || axis_count(az) > 1 || (MASK && (axis_masked(ay) || axis_masked(az)));
     if (!full) return;   // uniform over the block

@@ -27,7 +27,6 @@ struct Lattice {
     // so kernels enumerate copies with table reads instead of divisions.
     const int2 *tab[3];
     int unsorted;         // 1 if some axis is periodic with a single element
-    int rpb;              // lattice rows per workgroup of the per-node kernels
 };
 
 // Decode one axis entry.
@@ -36,8 +35,30 @@ __host__ __device__ inline int axis_elem(int2 a, int c) { return c ? (a.x >> 16)
 __host__ __device__ inline int axis_loc(int2 a, int c) { return c ? (a.y >> 8) & 0xff : a.y & 0xff; }
 __host__ __device__ inline bool axis_masked(int2 a) { return ((a.y >> 24) & 1) != 0; }
 
+// Coordinates of element e = ex + nelx (ey + nely ez), 32-bit arithmetic
+// (E < 2^31).
+__device__ __forceinline__ void elem_coords(const Lattice &L, int64_t e, int &ex, int &ey, int &ez)
+{
+    const int ei = (int)e, t = ei / L.nelx;
+    ex = ei - t * L.nelx;
+    ez = t / L.nely;
+    ey = t - ez * L.nely;
+}
+
+// Row layout of the solvers' unassembled operator output: the local points
+// of all elements form one (nelx NP) x (nely NP) x (nelz NP) lattice, x
+// fastest, so that the copies along one global lattice row -- including the
+// two copies of every x-face node -- are contiguous.  (The C ABI's local
+// fields use [E][k][j][i].)
+__host__ __device__ inline int64_t rows_index(const Lattice &L, int64_t ex, int64_t ey, int64_t ez, int i, int j, int k)
+{
+    return ((ez * L.NP + k) * ((int64_t)L.nely * L.NP) + ey * L.NP + j) * ((int64_t)L.nelx * L.NP) + ex * L.NP + i;
+}
+
 // All local indices (ascending) of global node (gi, gj, gk) from the axis
 // tables, 32-bit arithmetic (n_local < 2^31).  Returns the copy count.
+// ROWS: indices into the row layout, else into [E][k][j][i].
+template <bool ROWS = false>
 __device__ inline int node_locals(const Lattice &L, int gi, int gj, int gk, int loc[8], bool &masked)
 {
     const int2 ax = L.tab[0][gi], ay = L.tab[1][gj], az = L.tab[2][gk];
@@ -48,8 +69,15 @@ __device__ inline int node_locals(const Lattice &L, int gi, int gj, int gk, int 
     for (int c = 0; c < cz; ++c)
         for (int b = 0; b < cy; ++b)
             for (int a = 0; a < cx; ++a) {
-                const int e = axis_elem(ax, a) + L.nelx * (axis_elem(ay, b) + L.nely * axis_elem(az, c));
-                loc[n++] = e * P + axis_loc(ax, a) + NP * (axis_loc(ay, b) + NP * axis_loc(az, c));
+                if (ROWS) {
+                    const int X = axis_elem(ax, a) * NP + axis_loc(ax, a);
+                    const int Y = axis_elem(ay, b) * NP + axis_loc(ay, b);
+                    const int Z = axis_elem(az, c) * NP + axis_loc(az, c);
+                    loc[n++] = (Z * (L.nely * NP) + Y) * (L.nelx * NP) + X;
+                } else {
+                    const int e = axis_elem(ax, a) + L.nelx * (axis_elem(ay, b) + L.nely * axis_elem(az, c));
+                    loc[n++] = e * P + axis_loc(ax, a) + NP * (axis_loc(ay, b) + NP * axis_loc(az, c));
+                }
             }
     if (L.unsorted) {
         for (int q = 1; q < n; ++q) {
@@ -80,19 +108,122 @@ __device__ __forceinline__ int64_t xcd_block()
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-// Loop over the global nodes of lattice rows gj + ny gk in
-// [rpb xcd_block(), rpb xcd_block() + rpb) (threads over gi): no index is
-// divided per node, and a workgroup takes several consecutive rows so that
-// its partial-sum reduction and launch cost are spread over more nodes.
-// Launch with ceil(ny nz / rpb) blocks.  Binds gi, gj, gk (int) and g (int64
-// lexicographic id) for the body; `continue` skips one node.
-#define SEM_FOR_EACH_NODE(L, gi, gj, gk, g)                                                              \
-    for (int row_ = (int)xcd_block() * (L).rpb,                                                          \
-             rend_ = row_ + (L).rpb < (int)((L).ny * (L).nz) ? row_ + (L).rpb : (int)((L).ny * (L).nz); \
-         row_ < rend_; ++row_)                                                                           \
-        for (int gj = row_ % (int)(L).ny, gk = row_ / (int)(L).ny, gi = (int)threadIdx.x; gi < (L).nx;   \
-             gi += (int)blockDim.x)                                                                      \
-            if (const int64_t g = gi + (L).nx * (int64_t)row_; true)
+// Copies of global index g along one axis, 32-bit arithmetic: returns the
+// count (1 or 2) and X[c] = element * (N+1) + local coordinate, ascending
+// (X[1] = X[0] for a single copy).  No table is read, so the addresses of a
+// node's copies do not wait on a load.
+__device__ __forceinline__ int axis_copies(int g, int nel, int N, bool per, int X[2])
+{
+    const int NP = N + 1;
+    const int m = g / N, r = g - m * N;
+    if (r != 0) {
+        X[0] = X[1] = m * NP + r;
+        return 1;
+    }
+    if (per) {
+        if (m == 0) {
+            X[0] = 0;
+            X[1] = (nel - 1) * NP + N;
+        } else {
+            X[0] = (m - 1) * NP + N;
+            X[1] = m * NP;
+        }
+        return 2;
+    }
+    if (m == 0) {
+        X[0] = X[1] = 0;
+        return 1;
+    }
+    if (m == nel) {
+        X[0] = X[1] = (nel - 1) * NP + N;
+        return 1;
+    }
+    X[0] = (m - 1) * NP + N;
+    X[1] = m * NP;
+    return 2;
+}
+
+// Dirichlet flag of global index g along axis d
+__device__ __forceinline__ bool axis_dirichlet(const Lattice &L, int d, int g, int nel)
+{
+    if (L.per[d]) return false;
+    return (g == 0 && ((L.dir >> (2 * d)) & 1)) || (g == nel * L.N && ((L.dir >> (2 * d + 1)) & 1));
+}
+
+// Copies of one lattice row (gj, gk) in the row layout: the offsets of the
+// (y, z) copies, ascending (uniform over the row's workgroup), and the
+// Dirichlet flag of the y and z axes.
+struct RowCopies {
+    int n;
+    int off[4];
+    bool masked;
+};
+
+__device__ __forceinline__ RowCopies row_copies(const Lattice &L, int gj, int gk)
+{
+    int Y[2], Z[2];
+    const int cy = axis_copies(gj, L.nely, L.N, L.per[1] != 0, Y);
+    const int cz = axis_copies(gk, L.nelz, L.N, L.per[2] != 0, Z);
+    const int nyl = L.nely * L.NP, nxl = L.nelx * L.NP;
+    RowCopies rc;
+    rc.n = 0;
+    rc.masked = axis_dirichlet(L, 1, gj, L.nely) || axis_dirichlet(L, 2, gk, L.nelz);
+    for (int c = 0; c < cz; ++c)
+        for (int b = 0; b < cy; ++b) rc.off[rc.n++] = (Z[c] * nyl + Y[b]) * nxl;
+    return rc;   // ascending: Z and Y are ascending and Y < nyl
+}
+
+// Q^T w at node gi of a row with copies rc (w in the row layout), summed in
+// ascending local index -- the order of node_locals<true>.  All loads are
+// issued before the first add.  masked: Dirichlet flag of the node.
+template <typename T>
+__device__ __forceinline__ T row_assemble(const Lattice &L, const T *__restrict__ w, const RowCopies &rc, int gi,
+                                          bool &masked)
+{
+    int X[2];
+    const bool two = axis_copies(gi, L.nelx, L.N, L.per[0] != 0, X) > 1;
+    masked = rc.masked || axis_dirichlet(L, 0, gi, L.nelx);
+    T v0[4], v1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v0[q] = T(0);
+        v1[q] = T(0);
+        if (q < rc.n) {
+            v0[q] = w[rc.off[q] + X[0]];
+            if (two) v1[q] = w[rc.off[q] + X[1]];
+        }
+    }
+    T s = T(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q < rc.n) {
+            s += v0[q];
+            if (two) s += v1[q];
+        }
+    }
+    return s;
+}
+
+// Workgroup loop over lattice rows [RPB blockIdx.x, RPB blockIdx.x + RPB)
+// with the row's copies: binds gj, gk, row (int) and rc for the body.  The
+// workgroups sweep the rows in launch order (no XCD remap: every stream of a
+// row kernel is sequential, and measured sweeps run faster when all XCDs
+// advance through memory together).  Launch with ceil(ny nz / RPB) blocks.
+#define SEM_FOR_EACH_ROW(L, RPB, gj, gk, row, rc)                                                        \
+    for (int row = (int)blockIdx.x * (RPB),                                                              \
+             rend_ = row + (RPB) < (int)((L).ny * (L).nz) ? row + (RPB) : (int)((L).ny * (L).nz);       \
+         row < rend_; ++row)                                                                             \
+        if (const int gj = row % (int)(L).ny, gk = row / (int)(L).ny; true)                              \
+            if (const RowCopies rc = row_copies(L, gj, gk); true)
+
+// Loop over the global nodes of lattice row blockIdx.x = gj + ny gk (one
+// workgroup per row, threads over gi): no index is divided per node and every
+// row is independent work for the scheduler.  Launch with ny * nz blocks.
+// Binds gi, gj, gk (int) and g (int64 lexicographic id); `continue` skips a node.
+#define SEM_FOR_EACH_NODE(L, gi, gj, gk, g)                                                            \
+    for (int gj = (int)(blockIdx.x % (L).ny), gk = (int)(blockIdx.x / (L).ny), gi = (int)threadIdx.x; \
+         gi < (L).nx; gi += (int)blockDim.x)                                                           \
+        if (const int64_t g = gi + (L).nx * (int64_t)blockIdx.x; true)
 
 // Copies of a global index g along one direction, ascending in (element, local).
 // Returns the count (1 or 2); ec = element coordinate, lc = local coordinate.

@@ -29,11 +29,12 @@ namespace lk {
 
 #define GRID_STRIDE(g, n) for (int64_t g = (int64_t)blockIdx.x * kBS + threadIdx.x; g < (n); g += (int64_t)gridDim.x * kBS)
 
+// Q^T w at one node for an operator output w in the row layout
 __device__ __forceinline__ double assemble_at(const Lattice &L, const double *__restrict__ w, int gi, int gj, int gk,
                                               bool &masked)
 {
     int loc[8];
-    const int n = node_locals(L, gi, gj, gk, loc, masked);
+    const int n = node_locals<true>(L, gi, gj, gk, loc, masked);
     double s = 0.0;
     for (int c = 0; c < n; ++c) s += w[loc[c]];
     return s;

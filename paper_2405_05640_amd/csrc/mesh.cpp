@@ -258,9 +258,7 @@ static sem_status build(const sem_mesh_desc &d, Mesh &m)
     const int64_t nx = ndir(m.nelx, N, px), ny = ndir(m.nely, N, py), nz = ndir(m.nelz, N, pz);
     m.ng = nx * ny * nz;
     m.lat = Lattice{m.nelx, m.nely, m.nelz, N, NP, nx, ny, nz, P, {m.periodic[0], m.periodic[1], m.periodic[2]},
-                    m.dirichlet, {nullptr, nullptr, nullptr}, 0, 1};
-    // rows per workgroup: keep at least ~8k workgroups (32 per CU), at most 8 rows each
-    m.lat.rpb = (int)std::max<int64_t>(1, std::min<int64_t>(8, ny * nz / 8192));
+                    m.dirichlet, {nullptr, nullptr, nullptr}, 0};
     std::vector<int2> tab(nx + ny + nz);
     {
         const int nel[3] = {m.nelx, m.nely, m.nelz};

@@ -240,7 +240,8 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
     fwd32(W1, W2, W3, Xs, Y1s, Bs);
     // output gradient
     {
-        const int64_t ex = e % L.nelx, ey = (e / L.nelx) % L.nely, ez = e / ((int64_t)L.nelx * L.nely);
+        int ex, ey, ez;
+        elem_coords(L, e, ex, ey, ez);
         int gi = (int)(ex * L.N + i), gj = (int)(ey * L.N + j), gk = (int)(ez * L.N + k);
         if (gi >= L.nx) gi -= (int)L.nx;
         if (gj >= L.ny) gj -= (int)L.ny;

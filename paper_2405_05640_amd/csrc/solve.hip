@@ -289,7 +289,8 @@ sem_status solve_dc32(const Mesh &m, const sem_solve_opts &o, const Workspace &w
 // its largest value since the last replacement (or meets the tolerance), the
 // host queues x64 += sigma x32, the FP64 true residual r64 = b - S x64, and
 // restarts the low-precision residual from r64 / |r64| while the search
-// direction is kept (rescaled), so the Krylov process is not restarted.
+// direction is kept (rescaled, its dinv r part swapped for the new
+// residual's), so the Krylov process is not restarted.
 sem_status solve_reliable(const Mesh &m, const sem_solve_opts &o, const Workspace &ws, int hist_len, hipStream_t s,
                           int check_every, sem_solve_report *rep, CgState &h)
 {
