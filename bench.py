@@ -349,7 +349,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": tr, "kernel": "ax_kernel<double,8,HELM> (local operator)",
+                     "traffic": tr, "kernel": "ax_pt_kernel<double,8,HELM> (sem_ax local operator)",
                      "alg_bytes_per_point": B_ALG_HELMHOLTZ_F64,
                      "mean_launch_us": round(ax_mean * 1e3, 2)},
         "dssum_mean_us": round(gs_mean * 1e3, 2),
