@@ -309,7 +309,13 @@ sem_status solve_reliable(const Mesh &m, const sem_solve_opts &o, const Workspac
     CgState lo{};
     for (;;) {
         SEM_TRY(read_state(lo, ws.st32, s));
-        if (lo.done >= 2) { h.done = lo.done; break; }
+        if (lo.done >= 2) {
+            h.done = lo.done;
+            // iteration cap: x64 takes the last iterate; after a breakdown the
+            // low-precision solution may be non-finite and is dropped
+            if (lo.done == 3) SEM_HIP_TRY(cg_axpy<float>(m, ws.v64.x, ws.v32.x, sigma, s));
+            break;
+        }
         rmax = std::max(rmax, lo.rr);
         if (lo.done == 1 || lo.rr < delta2 * rmax) {
             // reliable update: fold the low-precision solution into x64 and

@@ -181,6 +181,35 @@ def test_status_codes_and_argument_checks():
         sem.Mesh(2, 2, 2, 3, v)
 
 
+def test_reliable_and_split_status_codes():
+    # reliable-update forms: zero right-hand side, iteration cap, argument
+    # checks; the split-BF16 operator needs a BF16-prepared N = 7 mesh
+    import torch
+    om, gm = pair(wl.deformed_cube(2, 7), prepare=sem.SEM_PREP_F32 | sem.SEM_PREP_BF16)
+    rng = np.random.default_rng(2)
+    b = dev(om.rhs(rng.standard_normal(om.shape)))
+    x = torch.zeros_like(b)
+    for form in (sem.FORM_RELIABLE_FP32, sem.FORM_RELIABLE_BF16):
+        rep = gm.pcg_solve(torch.zeros_like(b), x, form=form, inner_tol=0.1)
+        assert rep.status == 0 and rep.iterations == 0 and torch.count_nonzero(x) == 0
+        rep = gm.pcg_solve(b, x, form=form, inner_tol=0.1, max_iter=5, check_every=1, raise_on_error=False)
+        assert rep.status == sem.SEM_ERR_NOT_CONVERGED and rep.iterations >= 5
+        r = host(b) - om.apply_S(host(x), 1.0, 0.0)   # x is the FP64 iterate the report describes
+        assert abs(np.sqrt(om.dot(r, r) / om.dot(host(b), host(b))) - rep.true_rel_res) <= 1e-6 * rep.true_rel_res
+        for bad in (0.0, 1.0):
+            with pytest.raises(sem.SemError):
+                gm.pcg_solve(b, x, form=form, inner_tol=bad)
+    plain = sem.Mesh.from_spec(wl.deformed_cube(2, 7))
+    with pytest.raises(sem.SemError):
+        plain.pcg_solve(b, x, form=sem.FORM_RELIABLE_FP32, inner_tol=0.1)
+    with pytest.raises(sem.SemError):
+        plain.ax(b.float(), x.float(), dtype=sem.SEM_BF16_SPLIT)
+    om5, gm5 = pair(wl.deformed_cube(2, 5), prepare=sem.SEM_PREP_BF16)
+    u5 = torch.zeros(gm5.shape, dtype=torch.float32, device="cuda")
+    with pytest.raises(sem.SemError):
+        gm5.ax(u5, torch.empty_like(u5), dtype=sem.SEM_BF16_SPLIT)
+
+
 def test_table1_unique_count_fully_periodic_64cube():
     # Table 1 (TGV row): E = 262,144 elements at N = 7 -> n = E N^3 = 89,915,392
     spec = wl.box(64, 64, 64, 7, periodic=(1, 1, 1), dirichlet=0)
