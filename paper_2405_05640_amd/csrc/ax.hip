@@ -494,7 +494,7 @@ hipError_t launch_any(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, c
     case 5: return launch_pt<T, 5, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 6: return launch_pt<T, 6, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 7: return launch_pt<T, 7, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
-    case 8:
+    case 8:   // two points per thread pays off in FP32 only (FP64: 225 against 207 us)
         if constexpr (sizeof(T) == 4) return launch_pt2<T, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
         else return launch_pt<T, 8, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 9: return launch_np<T, 9, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
