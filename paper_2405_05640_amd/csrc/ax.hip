@@ -126,7 +126,7 @@ ax_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G,
     for (int k = 0; k < NP; ++k) {
         T v = h1 * rw[k];
         if (HELM) v += h2 * Bm[e * P3 + k * P2 + t] * ru[k];
-        w[GATHER ? rows_index(L, ex, ey, ez, i, j, k) : e * P3 + k * P2 + t] = v;
+        w[GATHER ? (int64_t)rows_index32(L, ex, ey, ez, i, j, k) : e * P3 + k * P2 + t] = v;
         if (DOT) dot += (double)ru[k] * (double)v;
     }
     if (DOT) {
@@ -166,11 +166,7 @@ ax_pt_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G
     if (GATHER) elem_coords(L, e, ex, ey, ez);
     T uv;
     if (GATHER) {
-        int64_t gi = ex * (NP - 1) + i, gj = ey * (NP - 1) + j, gk = ez * (NP - 1) + k;
-        if (gi >= L.nx) gi -= L.nx;
-        if (gj >= L.ny) gj -= L.ny;
-        if (gk >= L.nz) gk -= L.nz;
-        uv = u[gi + L.nx * (gj + L.ny * gk)];
+        uv = u[gather_index32(L, ex, ey, ez, i, j, k)];
     } else {
         uv = ldnt(&u[e * P3 + t]);
     }
@@ -200,7 +196,7 @@ ax_pt_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G
                sD[m * NP + k] * st[m * P2 + j * NP + i];
     T v = h1 * acc;
     if (HELM) v += h2 * bv * uv;
-    w[GATHER ? rows_index(L, ex, ey, ez, i, j, k) : e * P3 + t] = v;
+    w[GATHER ? (int64_t)rows_index32(L, ex, ey, ez, i, j, k) : e * P3 + t] = v;
     if constexpr (DOT && P3 % 64 == 0) {
         // full wavefronts: fixed butterfly within each wave, then the wave
         // sums in wave order (deterministic)
@@ -251,15 +247,8 @@ ax_pt2_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ 
     if (GATHER) elem_coords(L, e, ex, ey, ez);
     T uv[2];
     if (GATHER) {
-        int64_t gi = ex * 7 + i, gj = ey * 7 + j;
-        if (gi >= L.nx) gi -= L.nx;
-        if (gj >= L.ny) gj -= L.ny;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            int64_t gk = ez * 7 + k0 + 4 * q;
-            if (gk >= L.nz) gk -= L.nz;
-            uv[q] = u[gi + L.nx * (gj + L.ny * gk)];
-        }
+        for (int q = 0; q < 2; ++q) uv[q] = u[gather_index32(L, ex, ey, ez, i, j, k0 + 4 * q)];
     } else {
         uv[0] = ldnt(&u[e * P3 + t]);
         uv[1] = ldnt(&u[e * P3 + H + t]);
@@ -306,7 +295,7 @@ ax_pt2_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ 
                    sD[m * NP + k] * st[m * P2 + j * NP + i];
         T v = h1 * acc;
         if (HELM) v += h2 * bv[q] * uv[q];
-        w[GATHER ? rows_index(L, ex, ey, ez, i, j, k) : e * P3 + q * H + t] = v;
+        w[GATHER ? (int64_t)rows_index32(L, ex, ey, ez, i, j, k) : e * P3 + q * H + t] = v;
         dot += (double)uv[q] * (double)v;
     }
     if constexpr (DOT) {
@@ -344,11 +333,7 @@ ax_pt_batched_kernel(const double *__restrict__ u, int64_t ustride, double *__re
     if (GATHER) elem_coords(L, e, ex, ey, ez);
     int64_t src;
     if (GATHER) {
-        int64_t gi = ex * (NP - 1) + i, gj = ey * (NP - 1) + j, gk = ez * (NP - 1) + k;
-        if (gi >= L.nx) gi -= L.nx;
-        if (gj >= L.ny) gj -= L.ny;
-        if (gk >= L.nz) gk -= L.nz;
-        src = gi + L.nx * (gj + L.ny * gk);
+        src = gather_index32(L, ex, ey, ez, i, j, k);
     } else {
         src = e * P3 + t;
     }
@@ -384,7 +369,7 @@ ax_pt_batched_kernel(const double *__restrict__ u, int64_t ustride, double *__re
                    sD[m * NP + k] * st[m * P2 + j * NP + i];
         double v = h1 * acc;
         if (HELM) v += h2 * bv * uv[c];
-        w[c * nl + (GATHER ? rows_index(L, ex, ey, ez, i, j, k) : e * P3 + t)] = v;
+        w[c * nl + (GATHER ? (int64_t)rows_index32(L, ex, ey, ez, i, j, k) : e * P3 + t)] = v;
         if (partial) {
             // same order as the single-field kernel: butterfly per wavefront,
             // then the wave sums in wave order

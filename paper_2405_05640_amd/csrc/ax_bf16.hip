@@ -111,11 +111,7 @@ ax_bf16_kernel(const void *__restrict__ uin, float *__restrict__ w, const unsign
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int p = lane * 8 + q, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
-            int64_t gi = ex * 7 + i, gj = ey * 7 + j, gk = ez * 7 + k;
-            if (gi >= L.nx) gi -= L.nx;
-            if (gj >= L.ny) gj -= L.ny;
-            if (gk >= L.nz) gk -= L.nz;
-            su[p] = f2bf(ug[gi + L.nx * (gj + L.ny * gk)]);
+            su[p] = f2bf(ug[gather_index32(L, ex, ey, ez, i, j, k)]);
         }
     } else {
         const uint4 v = ((const uint4 *)((const unsigned short *)uin + e * 512))[lane];
@@ -167,7 +163,7 @@ ax_bf16_kernel(const void *__restrict__ uin, float *__restrict__ w, const unsign
         out[q] = v;
         if (partial) dot += (double)uu * (double)v;
     }
-    float4 *wo = (float4 *)(w + (GATHER ? rows_index(L, ex, ey, ez, 0, lane & 7, lane >> 3) : e * 512 + 8 * lane));
+    float4 *wo = (float4 *)(w + (GATHER ? (int64_t)rows_index32(L, ex, ey, ez, 0, lane & 7, lane >> 3) : e * 512 + 8 * lane));
     wo[0] = make_float4(out[0], out[1], out[2], out[3]);
     wo[1] = make_float4(out[4], out[5], out[6], out[7]);
     if (partial) {
@@ -256,16 +252,8 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
     // lane owns the 8-point row p = 8 lane + q: i = q, j = lane & 7, k = lane >> 3
     float uu[8];
     if (GATHER) {
-        int64_t gj = ey * 7 + (lane & 7), gk = ez * 7 + (lane >> 3);
-        if (gj >= L.ny) gj -= L.ny;
-        if (gk >= L.nz) gk -= L.nz;
-        const float *row = uin + L.nx * (gj + L.ny * gk);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            int64_t gi = ex * 7 + q;
-            if (gi >= L.nx) gi -= L.nx;
-            uu[q] = row[gi];
-        }
+        for (int q = 0; q < 8; ++q) uu[q] = uin[gather_index32(L, ex, ey, ez, q, lane & 7, lane >> 3)];
     } else {
         const float4 v0 = ((const float4 *)(uin + e * 512))[2 * lane], v1 = ((const float4 *)(uin + e * 512))[2 * lane + 1];
         uu[0] = v0.x; uu[1] = v0.y; uu[2] = v0.z; uu[3] = v0.w;
@@ -326,7 +314,7 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
         out[q] = v;
         if (partial) dot += (double)uu[q] * (double)v;
     }
-    float4 *wo = (float4 *)(w + (GATHER ? rows_index(L, ex, ey, ez, 0, lane & 7, lane >> 3) : e * 512 + 8 * lane));
+    float4 *wo = (float4 *)(w + (GATHER ? (int64_t)rows_index32(L, ex, ey, ez, 0, lane & 7, lane >> 3) : e * 512 + 8 * lane));
     wo[0] = make_float4(out[0], out[1], out[2], out[3]);
     wo[1] = make_float4(out[4], out[5], out[6], out[7]);
     if (partial) {

@@ -185,8 +185,11 @@ __global__ void __launch_bounds__(kBS) alpha_kernel(CgState *st, const double *_
     }
 }
 
-// wg = Q^T w (w in the row layout); x += alpha p; r -= alpha wg; partials (r,r), (r, dinv r)
-template <typename T>
+// wg = Q^T w (w in the row layout); x += alpha p; r -= alpha wg; partials
+// (r,r), (r, dinv r).  RPB rows per workgroup, unrolled so that the loads of
+// all of them are in flight together; NPC = N + 1 fixed at compile time
+// (0: any order).
+template <typename T, int RPB, int NPC>
 __global__ void __launch_bounds__(kBS)
 update_kernel(const CgState *__restrict__ st, const T *__restrict__ w, T *__restrict__ x, T *__restrict__ r,
               const T *__restrict__ p, const T *__restrict__ dinv, Lattice L, double *__restrict__ part)
@@ -194,24 +197,19 @@ update_kernel(const CgState *__restrict__ st, const T *__restrict__ w, T *__rest
     if (st->done) return;
     const T alpha = (T)st->alpha;
     double acc[2] = {0.0, 0.0};
-    // RPB rows per workgroup, unrolled so that the loads of all of them are
-    // in flight together
-    constexpr int RPB = update_rpb<T>();
-    const int nrows = (int)(L.ny * L.nz), row0 = (int)blockIdx.x * RPB;
-    for (int gi = threadIdx.x; gi < L.nx; gi += kBS) {
+    const int nrows = (int)(L.ny * L.nz), row0 = (int)blockIdx.x * RPB, ny = (int)L.ny, nx = (int)L.nx;
+    for (int gi = threadIdx.x; gi < nx; gi += kBS) {
         T d[RPB], xg[RPB], pg[RPB], rg0[RPB], wg[RPB];
         int64_t g[RPB];
 #pragma unroll
         for (int q = 0; q < RPB; ++q) {
             const int row = row0 + q < nrows ? row0 + q : nrows - 1;   // clamped rows are not stored
-            g[q] = gi + L.nx * (int64_t)row;
+            g[q] = gi + (int64_t)nx * row;
             d[q] = dinv[g[q]];
             xg[q] = x[g[q]];
             pg[q] = p[g[q]];
             rg0[q] = r[g[q]];
-            const RowCopies rc = row_copies(L, row % (int)L.ny, row / (int)L.ny);
-            bool msk;
-            wg[q] = row_assemble(L, w, rc, gi, msk);
+            wg[q] = node_assemble_rows<NPC>(L, w, gi, row % ny, row / ny);
         }
 #pragma unroll
         for (int q = 0; q < RPB; ++q) {
@@ -432,8 +430,13 @@ hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, doub
     const int64_t rows = row_grid(m.lat, update_rpb<T>());
     hipError_t e = cg_alpha(m, v.part_e, v.stage, st, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((cg::update_kernel<T>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,
-                       m.lat, v.part_b);
+    constexpr int RPB = update_rpb<T>();
+    if (m.lat.NP == 8)
+        hipLaunchKernelGGL((cg::update_kernel<T, RPB, 8>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
+                           v.dinv, m.lat, v.part_b);
+    else
+        hipLaunchKernelGGL((cg::update_kernel<T, RPB, 0>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
+                           v.dinv, m.lat, v.part_b);
     e = cg_reduce(v.part_b, rows, 2, v.stage, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(cg::beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.stage, kStage, hist);

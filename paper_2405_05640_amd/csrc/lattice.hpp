@@ -54,6 +54,22 @@ __host__ __device__ inline int64_t rows_index(const Lattice &L, int64_t ex, int6
 {
     return ((ez * L.NP + k) * ((int64_t)L.nely * L.NP) + ey * L.NP + j) * ((int64_t)L.nelx * L.NP) + ex * L.NP + i;
 }
+// the same in 32-bit arithmetic (every local index is below 2^31)
+__device__ __forceinline__ int rows_index32(const Lattice &L, int ex, int ey, int ez, int i, int j, int k)
+{
+    return ((ez * L.NP + k) * (L.nely * L.NP) + ey * L.NP + j) * (L.nelx * L.NP) + ex * L.NP + i;
+}
+// global index of local point (i, j, k) of element (ex, ey, ez), 32-bit
+// (n_global <= n_local < 2^31); the periodic wrap is one compare per axis
+__device__ __forceinline__ int gather_index32(const Lattice &L, int ex, int ey, int ez, int i, int j, int k)
+{
+    const int nx = (int)L.nx, ny = (int)L.ny, nz = (int)L.nz;
+    int gi = ex * L.N + i, gj = ey * L.N + j, gk = ez * L.N + k;
+    if (gi >= nx) gi -= nx;
+    if (gj >= ny) gj -= ny;
+    if (gk >= nz) gk -= nz;
+    return gi + nx * (gj + ny * gk);
+}
 
 // All local indices (ascending) of global node (gi, gj, gk) from the axis
 // tables, 32-bit arithmetic (n_local < 2^31).  Returns the copy count.
@@ -141,6 +157,63 @@ __device__ __forceinline__ int axis_copies(int g, int nel, int N, bool per, int 
     X[0] = (m - 1) * NP + N;
     X[1] = m * NP;
     return 2;
+}
+
+// axis_copies with the order fixed at compile time when NPC = N + 1 > 0
+// (the divisions by N become multiply-shifts); NPC = 0 takes N at run time.
+template <int NPC>
+__device__ __forceinline__ int axis_copies_t(int g, int nel, int Nrt, bool per, int X[2])
+{
+    if constexpr (NPC > 0) {
+        constexpr int N = NPC - 1;
+        const int m = g / N, r = g - m * N;
+        if (r != 0) {
+            X[0] = X[1] = m * NPC + r;
+            return 1;
+        }
+        if (per) {
+            X[0] = m == 0 ? 0 : (m - 1) * NPC + N;
+            X[1] = m == 0 ? (nel - 1) * NPC + N : m * NPC;
+            return 2;
+        }
+        if (m == 0 || m == nel) {
+            X[0] = X[1] = m == 0 ? 0 : (nel - 1) * NPC + N;
+            return 1;
+        }
+        X[0] = (m - 1) * NPC + N;
+        X[1] = m * NPC;
+        return 2;
+    } else {
+        return axis_copies(g, nel, Nrt, per, X);
+    }
+}
+
+// Q^T w at node (gi, gj, gk) for w in the row layout, every copy computed per
+// thread and every load issued before the first add (missing copies load
+// nothing and add zero); summed in ascending local index.
+template <int NPC, typename T>
+__device__ __forceinline__ T node_assemble_rows(const Lattice &L, const T *__restrict__ w, int gi, int gj, int gk)
+{
+    const int NP = NPC > 0 ? NPC : L.NP;
+    int X[2], Y[2], Z[2];
+    const int cx = axis_copies_t<NPC>(gi, L.nelx, L.N, L.per[0] != 0, X);
+    const int cy = axis_copies_t<NPC>(gj, L.nely, L.N, L.per[1] != 0, Y);
+    const int cz = axis_copies_t<NPC>(gk, L.nelz, L.N, L.per[2] != 0, Z);
+    const int nxl = L.nelx * NP, nyl = L.nely * NP;
+    T v[8];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const bool ok = c < cz && b < cy && a < cx;
+                v[4 * c + 2 * b + a] = ok ? w[(Z[c] * nyl + Y[b]) * nxl + X[a]] : T(0);
+            }
+    T s = v[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) s += v[q];
+    return s;
 }
 
 // Dirichlet flag of global index g along axis d
