@@ -151,6 +151,8 @@ ax_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G,
 template <typename T>
 __device__ __forceinline__ T ldnt(const T *p) { return __builtin_nontemporal_load(p); }
 
+constexpr int kPptF32 = 2;   // points per thread of the FP32 operator at N = 7
+
 template <typename T, int NP, bool HELM, bool DOT, bool GATHER>
 __global__ void __launch_bounds__(NP * NP * NP)
 ax_pt_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G,
@@ -227,56 +229,58 @@ ax_pt_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G
     }
 }
 
-// Two points per thread (N = 7, FP32): a workgroup of 256 threads per
-// element, thread t owning points (i, j, k) and (i, j, k + 4).  Each thread
-// then keeps twice the bytes in flight (16 streaming loads), which the FP32
-// operator needs to approach the bandwidth the FP64 one reaches with one
-// point per thread; the derivative rows of i and j are shared by both points.
-template <typename T, bool HELM, bool DOT, bool GATHER>
-__global__ void __launch_bounds__(256)
-ax_pt2_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G, const T *__restrict__ Bm,
+// Several points per thread (N = 7, FP32): a workgroup of 512 / PPT threads
+// per element, thread t owning points (i, j, k0 + q 8/PPT), q < PPT.  Each
+// thread keeps PPT times the bytes in flight (which the FP32 operator needs
+// to approach the bandwidth the FP64 one reaches with one point per thread),
+// and its points share one (i, j) pencil: the t-direction contractions read
+// the pencil from LDS once for all of them.
+template <typename T, int PPT, bool HELM, bool DOT, bool GATHER>
+__global__ void __launch_bounds__(512 / PPT)
+ax_ptn_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G, const T *__restrict__ Bm,
               const T *__restrict__ Dg, T h1, T h2, double *__restrict__ partial, const int32_t *__restrict__ skip,
               Lattice L)
 {
     if (skip && *skip) return;
-    constexpr int NP = 8, P2 = 64, P3 = 512, H = 256;
+    constexpr int NP = 8, P2 = 64, P3 = 512, H = 512 / PPT, KS = 8 / PPT;
     __shared__ T sD[P2], su[P3], sr[P3], ss[P3], st[P3];
-    const int t = threadIdx.x, i = t & 7, j = (t >> 3) & 7, k0 = t >> 6;   // second point: k0 + 4
+    const int t = threadIdx.x, i = t & 7, j = (t >> 3) & 7, k0 = t >> 6;   // points k0 + q KS
     const int64_t e = xcd_block();
     int ex = 0, ey = 0, ez = 0;
     if (GATHER) elem_coords(L, e, ex, ey, ez);
-    T uv[2];
+    T uv[PPT];
     if (GATHER) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) uv[q] = u[gather_index32(L, ex, ey, ez, i, j, k0 + 4 * q)];
+        for (int q = 0; q < PPT; ++q) uv[q] = u[gather_index32(L, ex, ey, ez, i, j, k0 + q * KS)];
     } else {
-        uv[0] = ldnt(&u[e * P3 + t]);
-        uv[1] = ldnt(&u[e * P3 + H + t]);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) uv[q] = ldnt(&u[e * P3 + q * H + t]);
     }
     const T *Ge = G + e * 6 * P3;
-    T g[2][6];
+    T g[PPT][6];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < PPT; ++q)
 #pragma unroll
         for (int c = 0; c < 6; ++c) g[q][c] = ldnt(&Ge[c * P3 + q * H + t]);
-    T bv[2] = {T(0), T(0)};
-    if (HELM) {
-        bv[0] = ldnt(&Bm[e * P3 + t]);
-        bv[1] = ldnt(&Bm[e * P3 + H + t]);
-    }
-    if (t < P2) sD[t] = Dg[t];
-    su[t] = uv[0];
-    su[H + t] = uv[1];
-    __syncthreads();
+    T bv[PPT];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int k = k0 + 4 * q;
+    for (int q = 0; q < PPT; ++q) bv[q] = HELM ? ldnt(&Bm[e * P3 + q * H + t]) : T(0);
+    if (t < P2) sD[t] = Dg[t];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) su[q * H + t] = uv[q];
+    __syncthreads();
+    T pen[NP];   // the (i, j) pencil of u, shared by this thread's points
+#pragma unroll
+    for (int m = 0; m < NP; ++m) pen[m] = su[m * P2 + j * NP + i];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int k = k0 + q * KS;
         T ur = T(0), us = T(0), ut = T(0);
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
             ur += sD[i * NP + m] * su[k * P2 + j * NP + m];
             us += sD[j * NP + m] * su[k * P2 + m * NP + i];
-            ut += sD[k * NP + m] * su[m * P2 + j * NP + i];
+            ut += sD[k * NP + m] * pen[m];
         }
         const int tq = q * H + t;
         sr[tq] = g[q][0] * ur + g[q][1] * us + g[q][2] * ut;
@@ -284,15 +288,17 @@ ax_pt2_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ 
         st[tq] = g[q][2] * ur + g[q][4] * us + g[q][5] * ut;
     }
     __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NP; ++m) pen[m] = st[m * P2 + j * NP + i];
     double dot = 0.0;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int k = k0 + 4 * q;
+    for (int q = 0; q < PPT; ++q) {
+        const int k = k0 + q * KS;
         T acc = T(0);
 #pragma unroll
         for (int m = 0; m < NP; ++m)
             acc += sD[m * NP + i] * sr[k * P2 + j * NP + m] + sD[m * NP + j] * ss[k * P2 + m * NP + i] +
-                   sD[m * NP + k] * st[m * P2 + j * NP + i];
+                   sD[m * NP + k] * pen[m];
         T v = h1 * acc;
         if (HELM) v += h2 * bv[q] * uv[q];
         w[GATHER ? (int64_t)rows_index32(L, ex, ey, ez, i, j, k) : e * P3 + q * H + t] = v;
@@ -304,7 +310,12 @@ ax_pt2_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ 
         for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
         if ((t & 63) == 0) wred[t >> 6] = dot;
         __syncthreads();
-        if (t == 0) partial[e] = ((wred[0] + wred[1]) + wred[2]) + wred[3];
+        if (t == 0) {
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < H / 64; ++q) sum += wred[q];
+            partial[e] = sum;
+        }
     }
 }
 
@@ -425,23 +436,23 @@ hipError_t launch_pt(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, co
     return hipGetLastError();
 }
 
-template <typename T, bool GATHER>
-hipError_t launch_pt2(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, const T *B, const T *D,
+template <typename T, int PPT, bool GATHER>
+hipError_t launch_ptn(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, const T *B, const T *D,
                       double *partial, const int32_t *skip, hipStream_t s)
 {
-    const dim3 grid((unsigned)m.E), block(256);
+    const dim3 grid((unsigned)m.E), block(512 / PPT);
     const bool helm = (h2 != T(0));
     const Lattice &L = m.lat;
     if (partial) {
         if (helm)
-            hipLaunchKernelGGL((ax_pt2_kernel<T, true, true, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+            hipLaunchKernelGGL((ax_ptn_kernel<T, PPT, true, true, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
         else
-            hipLaunchKernelGGL((ax_pt2_kernel<T, false, true, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+            hipLaunchKernelGGL((ax_ptn_kernel<T, PPT, false, true, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
     } else {
         if (helm)
-            hipLaunchKernelGGL((ax_pt2_kernel<T, true, false, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+            hipLaunchKernelGGL((ax_ptn_kernel<T, PPT, true, false, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
         else
-            hipLaunchKernelGGL((ax_pt2_kernel<T, false, false, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
+            hipLaunchKernelGGL((ax_ptn_kernel<T, PPT, false, false, GATHER>), grid, block, 0, s, u, w, G, B, D, h1, h2, partial, skip, L);
     }
     return hipGetLastError();
 }
@@ -479,8 +490,8 @@ hipError_t launch_any(const Mesh &m, T h1, T h2, const T *u, T *w, const T *G, c
     case 5: return launch_pt<T, 5, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 6: return launch_pt<T, 6, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 7: return launch_pt<T, 7, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
-    case 8:   // two points per thread pays off in FP32 only (FP64: 225 against 207 us)
-        if constexpr (sizeof(T) == 4) return launch_pt2<T, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
+    case 8:   // several points per thread pay off in FP32 only (FP64, two: 225 against 207 us)
+        if constexpr (sizeof(T) == 4) return launch_ptn<T, kPptF32, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
         else return launch_pt<T, 8, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 9: return launch_np<T, 9, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
     case 10: return launch_np<T, 10, GATHER>(m, h1, h2, u, w, G, B, D, partial, skip, s);
