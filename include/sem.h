@@ -152,8 +152,11 @@ typedef enum {
                                     accumulated in FP64 and the residual is replaced by the FP64
                                     true residual whenever it has fallen by inner_tol (reliable
                                     updates); the search direction is kept */
-    SEM_FORM_RELIABLE_BF16 = 7   /* same with the split-BF16 matrix-core operator
+    SEM_FORM_RELIABLE_BF16 = 7,  /* same with the split-BF16 matrix-core operator
                                     (SEM_BF16_SPLIT) */
+    SEM_FORM_PCG_1RED = 8        /* FP64 Jacobi-PCG in the single-reduction form of
+                                    Chronopoulos & Gear (1989): one vector pass, the operator and
+                                    one reduction phase per iteration; same stopping test */
 } sem_form;
 
 typedef struct {

@@ -363,6 +363,147 @@ __global__ void __launch_bounds__(kBS) replace_finalize(CgState *st, const doubl
     }
 }
 
+// ---------------------------------------------------------------- single-reduction CG
+//
+// Chronopoulos & Gear (1989) form of preconditioned CG: with u = dinv r,
+// w = S u, gamma = (r, u) and delta = (u, w) from ONE reduction phase,
+//   beta = gamma / gamma_old, alpha = gamma / (delta - beta gamma / alpha_old),
+//   p = u + beta p, s = w + beta s (s = S p), x += alpha p, r -= alpha s.
+// One pass updates every vector (cg1_vec_kernel), the operator is applied to
+// u (its per-element partials give delta), and one finalize computes the
+// scalars: four launches per iteration instead of seven.
+
+// x = 0 (unless keep_x), r = b (or r as given when keep_x), u = dinv r,
+// p = s = 0; partials (r, u), (r, r)
+__global__ void __launch_bounds__(kBS)
+cg1_init_kernel(const double *__restrict__ b, double *__restrict__ x, double *__restrict__ r, double *__restrict__ u,
+                double *__restrict__ p, double *__restrict__ sv, const double *__restrict__ dinv, int keep_x,
+                int64_t ng, double *__restrict__ part)
+{
+    double acc[2] = {0.0, 0.0};
+    GRID_STRIDE(g, ng)
+    {
+        const double d = dinv[g];
+        const double rg = d == 0.0 ? 0.0 : (keep_x ? r[g] : b[g]);
+        if (!keep_x) x[g] = 0.0;
+        r[g] = rg;
+        const double ug = d * rg;
+        u[g] = ug;
+        p[g] = 0.0;
+        sv[g] = 0.0;
+        acc[0] += rg * ug;
+        acc[1] += rg * rg;
+    }
+    block_store<2>(acc, part, gridDim.x);
+}
+
+// after the operator on u: gamma, delta, (r, r); first = 1 starts a run
+// (alpha = gamma / delta, beta = 0, bb and tol2 when fresh = 1)
+__global__ void __launch_bounds__(kBS)
+cg1_finalize(CgState *st, const double *__restrict__ stage_v, const double *__restrict__ stage_e, int first, int fresh,
+             double tol, double *hist)
+{
+    if (st->done && !first) return;
+    const double gamma = block_sum(stage_v, kStage);
+    const double rr = block_sum(stage_v + kStage, kStage);
+    const double delta = block_sum(stage_e, kStage);
+    if (threadIdx.x != 0) return;
+    if (first) {
+        if (fresh) {
+            st->bb = rr;
+            st->tol2 = tol * tol * rr;
+            st->it = 0;
+            if (hist && st->hist_len > 0) hist[0] = 1.0;
+        }
+        st->status = 0;
+        st->rr = rr;
+        st->rz = gamma;
+        st->beta = 0.0;
+        st->done = rr == 0.0 || rr <= st->tol2 ? 1 : 0;
+        if (!st->done) {
+            if (!(delta > 0.0) || !isfinite(delta) || !isfinite(gamma)) {
+                st->done = 2;
+                st->status = SEM_ERR_BREAKDOWN;
+            } else {
+                st->alpha = gamma / delta;
+            }
+        }
+        return;
+    }
+    const int it = st->it + 1;
+    st->it = it;
+    st->rr = rr;
+    if (hist && it < st->hist_len) hist[it] = sqrt(rr / st->bb);
+    if (!isfinite(rr) || !isfinite(gamma) || !isfinite(delta)) {
+        st->done = 2;
+        st->status = SEM_ERR_BREAKDOWN;
+        return;
+    }
+    if (rr <= st->tol2) {
+        st->done = 1;
+        return;
+    }
+    if (it >= st->max_it) {
+        st->done = 3;
+        return;
+    }
+    const double beta = gamma / st->rz;
+    const double den = delta - beta * gamma / st->alpha;
+    if (!(den > 0.0)) {
+        st->done = 2;
+        st->status = SEM_ERR_BREAKDOWN;
+        return;
+    }
+    st->beta = beta;
+    st->alpha = gamma / den;
+    st->rz = gamma;
+}
+
+// s = Q^T w + beta s; p = dinv r + beta p; x += alpha p; r -= alpha s;
+// u = dinv r; partials (r, u), (r, r).  w in the row layout.
+template <int RPB, int NPC>
+__global__ void __launch_bounds__(kBS)
+cg1_vec_kernel(const CgState *__restrict__ st, const double *__restrict__ w, double *__restrict__ x,
+               double *__restrict__ r, double *__restrict__ p, double *__restrict__ sv, double *__restrict__ u,
+               const double *__restrict__ dinv, Lattice L, double *__restrict__ part)
+{
+    if (st->done) return;
+    const double alpha = st->alpha, beta = st->beta;
+    double acc[2] = {0.0, 0.0};
+    const int nrows = (int)(L.ny * L.nz), row0 = (int)blockIdx.x * RPB, ny = (int)L.ny, nx = (int)L.nx;
+    for (int gi = threadIdx.x; gi < nx; gi += kBS) {
+        double d[RPB], xg[RPB], pg[RPB], rg[RPB], sg[RPB], wg[RPB];
+        int64_t g[RPB];
+#pragma unroll
+        for (int q = 0; q < RPB; ++q) {
+            const int row = row0 + q < nrows ? row0 + q : nrows - 1;   // clamped rows are not stored
+            g[q] = gi + (int64_t)nx * row;
+            d[q] = dinv[g[q]];
+            xg[q] = x[g[q]];
+            pg[q] = p[g[q]];
+            rg[q] = r[g[q]];
+            sg[q] = sv[g[q]];
+            wg[q] = node_assemble_rows<NPC>(L, w, gi, row % ny, row / ny);
+        }
+#pragma unroll
+        for (int q = 0; q < RPB; ++q) {
+            if (row0 + q >= nrows || d[q] == 0.0) continue;   // Dirichlet node: every vector stays zero
+            const double sn = wg[q] + beta * sg[q];
+            const double pn = d[q] * rg[q] + beta * pg[q];
+            const double rn = rg[q] - alpha * sn;
+            const double un = d[q] * rn;
+            sv[g[q]] = sn;
+            p[g[q]] = pn;
+            x[g[q]] = xg[q] + alpha * pn;
+            r[g[q]] = rn;
+            u[g[q]] = un;
+            acc[0] += rn * un;
+            acc[1] += rn * rn;
+        }
+    }
+    block_store<2>(acc, part, gridDim.x);
+}
+
 // y += s * (double)d   (defect correction: x64 += scale * d32)
 template <typename T>
 __global__ void __launch_bounds__(kBS) axpy_kernel(double *__restrict__ y, const T *__restrict__ d, double s, int64_t ng)
@@ -471,6 +612,37 @@ hipError_t cg_replace(const Mesh &m, const CgVecs<T> &v, const double *r64, CgSt
     const int nb = cg_blocks(m.ng);
     L3((cg::replace_kernel<T>), m.ng) r64, v.x, v.r, v.p, v.dinv, inv_sigma, p_scale, first, m.ng, v.part_b);
     hipLaunchKernelGGL(cg::replace_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb, tol2, first);
+    return hipGetLastError();
+}
+
+hipError_t cg1_init(const Mesh &m, const CgVecs<double> &v, const double *b, double *u, double *sv, int keep_x,
+                    hipStream_t s)
+{
+    const int nb = cg_blocks(m.ng);
+    hipLaunchKernelGGL(cg::cg1_init_kernel, dim3(nb), dim3(kBS), 0, s, b, v.x, v.r, u, v.p, sv, v.dinv, keep_x, m.ng,
+                       v.part_b);
+    return cg_reduce(v.part_b, nb, 2, v.stage, s);
+}
+
+hipError_t cg1_vec(const Mesh &m, const CgVecs<double> &v, double *u, double *sv, CgState *st, hipStream_t s)
+{
+    const int64_t rows = row_grid(m.lat, 2);
+    if (m.lat.NP == 8)
+        hipLaunchKernelGGL((cg::cg1_vec_kernel<2, 8>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
+                           sv, u, v.dinv, m.lat, v.part_b);
+    else
+        hipLaunchKernelGGL((cg::cg1_vec_kernel<2, 0>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
+                           sv, u, v.dinv, m.lat, v.part_b);
+    return cg_reduce(v.part_b, rows, 2, v.stage, s);
+}
+
+hipError_t cg1_finalize(const Mesh &m, const CgVecs<double> &v, CgState *st, int first, int fresh, double tol,
+                        double *hist, hipStream_t s)
+{
+    hipError_t e = cg_reduce(v.part_e, m.E, 1, v.stage + 2 * kStage, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cg::cg1_finalize, dim3(1), dim3(kBS), 0, s, st, v.stage, v.stage + 2 * kStage, first, fresh,
+                       tol, hist);
     return hipGetLastError();
 }
 

@@ -74,6 +74,16 @@ hipError_t cg_rsub(const Mesh &m, const double *x, double *e, hipStream_t s);
 template <typename T>
 hipError_t cg_replace(const Mesh &m, const CgVecs<T> &v, const double *r64, CgState *st, double inv_sigma,
                       double p_scale, int first, double tol2, hipStream_t s);
+// single-reduction (Chronopoulos-Gear) CG on FP64 vectors, u and sv extra
+// assembled vectors: init (x = 0 unless keep_x; partials of (r,u), (r,r)
+// reduced into v.stage), vector pass (partials reduced into v.stage), and the
+// finalize after the operator on u has left its per-element partials in
+// v.part_e (first = 1 starts a run; fresh = 1 also sets bb and tol2)
+hipError_t cg1_init(const Mesh &m, const CgVecs<double> &v, const double *b, double *u, double *sv, int keep_x,
+                    hipStream_t s);
+hipError_t cg1_vec(const Mesh &m, const CgVecs<double> &v, double *u, double *sv, CgState *st, hipStream_t s);
+hipError_t cg1_finalize(const Mesh &m, const CgVecs<double> &v, CgState *st, int first, int fresh, double tol,
+                        double *hist, hipStream_t s);
 template <typename T> hipError_t cg_axpy(const Mesh &m, double *y, const T *d, double scale, hipStream_t s);
 template <typename T> hipError_t cg_scale(const Mesh &m, const double *in, T *out, double scale, hipStream_t s);
 

@@ -73,6 +73,8 @@ bool uses_fcg(int form)
 {
     return form == SEM_FORM_FCG_LEARNED || form == SEM_FORM_FCG_INNER_FP32 || form == SEM_FORM_FCG_INNER_BF16;
 }
+// forms that need the two extra assembled FP64 vectors z and q
+bool uses_zq(int form) { return uses_fcg(form) || form == SEM_FORM_PCG_1RED; }
 
 Workspace carve(const Mesh &m, int form, int hist_len, char *base)
 {
@@ -96,7 +98,7 @@ Workspace carve(const Mesh &m, int form, int hist_len, char *base)
     ws.st64 = (CgState *)take(sizeof(CgState));
     ws.st32 = (CgState *)take(sizeof(CgState));
     ws.hist = (double *)take((size_t)std::max(hist_len, 1) * 8);
-    if (uses_fcg(form)) {
+    if (uses_zq(form)) {
         ws.z = (double *)take(ng * 8);
         ws.q = (double *)take(ng * 8);
     }
@@ -126,6 +128,7 @@ sem_status check_opts(const Mesh &m, const sem_solve_opts *o)
     if (!std::isfinite(o->h1) || !std::isfinite(o->h2)) return fail(SEM_ERR_INVALID_ARG, "non-finite h1/h2");
     switch (o->form) {
     case SEM_FORM_JACOBI_PCG:
+    case SEM_FORM_PCG_1RED:
         return SEM_OK;
     case SEM_FORM_DC_FP32:
     case SEM_FORM_DC_BF16:
@@ -230,6 +233,44 @@ sem_status solve_pcg64(const Mesh &m, const sem_solve_opts &o, const Workspace &
         if (h.true_rr <= h.tol2 || restarts == 3 || h.it >= h.max_it) break;
         ++restarts;   // recursive residual drifted: restart CG from x
         SEM_HIP_TRY(cg_restart<double>(m, ws.v64, ws.st64, s));
+    }
+    if (h.done != 1 && h.bb > 0.0) SEM_TRY(true_residual(m, o.h1, o.h2, ws, s, h));
+    rep->iterations = h.it;
+    rep->restarts = restarts;
+    return SEM_OK;
+}
+
+// Single-reduction Jacobi-PCG (Chronopoulos & Gear 1989; the survey's
+// communication-reducing CG): per iteration one vector pass, the operator on
+// u = dinv r, and one finalize that forms alpha and beta from the three inner
+// products of the same reduction phase.  Same convergence test and
+// true-residual restarts as solve_pcg64.
+sem_status solve_pcg1(const Mesh &m, const sem_solve_opts &o, const Workspace &ws, int hist_len, hipStream_t s,
+                      int check_every, sem_solve_report *rep, CgState &h)
+{
+    double *u = ws.z, *sv = ws.q;
+    SEM_TRY(reset_state(ws.st64, o.max_iter, hist_len, s));
+    SEM_HIP_TRY(cg1_init(m, ws.v64, ws.b64, u, sv, 0, s));
+    SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, u, ws.v64.w, ws.v64.part_e, s));
+    SEM_HIP_TRY(cg1_finalize(m, ws.v64, ws.st64, 1, 1, o.rel_tol, ws.hist, s));
+    int restarts = 0;
+    for (;;) {
+        for (;;) {
+            SEM_TRY(read_state(h, ws.st64, s));
+            if (h.done) break;
+            for (int q = 0; q < check_every; ++q) {
+                SEM_HIP_TRY(cg1_vec(m, ws.v64, u, sv, ws.st64, s));
+                SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, u, ws.v64.w, ws.v64.part_e, s, &ws.st64->done));
+                SEM_HIP_TRY(cg1_finalize(m, ws.v64, ws.st64, 0, 0, o.rel_tol, ws.hist, s));
+            }
+        }
+        if (h.done != 1 || h.bb == 0.0) break;
+        SEM_TRY(true_residual(m, o.h1, o.h2, ws, s, h));
+        if (h.true_rr <= h.tol2 || restarts == 3 || h.it >= h.max_it) break;
+        ++restarts;   // recursive residual drifted: restart from x with the true residual
+        SEM_HIP_TRY(cg1_init(m, ws.v64, ws.b64, u, sv, 1, s));
+        SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, u, ws.v64.w, ws.v64.part_e, s));
+        SEM_HIP_TRY(cg1_finalize(m, ws.v64, ws.st64, 1, 0, o.rel_tol, ws.hist, s));
     }
     if (h.done != 1 && h.bb > 0.0) SEM_TRY(true_residual(m, o.h1, o.h2, ws, s, h));
     rep->iterations = h.it;
@@ -473,6 +514,8 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
         SEM_TRY(solve_fcg_nested(m, *opts, ws.v64, ws.v32, ws.b32, ws.b64, ws.z, ws.q, ws.st64, ws.st32, ws.hist,
                                  hist_len, std::max(1, std::min(check_every, 4)),
                                  opts->form == SEM_FORM_FCG_INNER_BF16, s, rep, h));
+    else if (opts->form == SEM_FORM_PCG_1RED)
+        SEM_TRY(solve_pcg1(m, *opts, ws, hist_len, s, check_every, rep, h));
     else if (opts->form == SEM_FORM_RELIABLE_FP32 || opts->form == SEM_FORM_RELIABLE_BF16)
         SEM_TRY(solve_reliable(m, *opts, ws, hist_len, s, check_every, rep, h));
     else if (opts->form == SEM_FORM_FCG_LEARNED)
@@ -484,7 +527,8 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
 
     rep->rel_res = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
     rep->true_rel_res = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
-    if (opts->history && opts->history_len > 0 && (opts->form == SEM_FORM_JACOBI_PCG || uses_fcg(opts->form))) {
+    if (opts->history && opts->history_len > 0 &&
+        (opts->form == SEM_FORM_JACOBI_PCG || opts->form == SEM_FORM_PCG_1RED || uses_fcg(opts->form))) {
         const int n = std::min(opts->history_len, std::min(h.it + 1, hist_len));
         SEM_HIP_TRY(hipMemcpyAsync(opts->history, ws.hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         SEM_HIP_TRY(hipStreamSynchronize(s));

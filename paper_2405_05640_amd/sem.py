@@ -23,7 +23,7 @@ SEM_F64, SEM_F32, SEM_BF16, SEM_BF16_SPLIT = 0, 1, 2, 3
 SEM_PREP_F32, SEM_PREP_BF16 = 1, 2
 FIELD_GLO_NUM, FIELD_MULT, FIELD_MASK, FIELD_G, FIELD_B, FIELD_XYZ, FIELD_GLL, FIELD_DERIV = range(8)
 (FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED, FORM_FCG_INNER_FP32, FORM_FCG_INNER_BF16,
- FORM_RELIABLE_FP32, FORM_RELIABLE_BF16) = range(8)
+ FORM_RELIABLE_FP32, FORM_RELIABLE_BF16, FORM_PCG_1RED) = range(9)
 SMOOTHER_PARAMS = 8208
 
 EXPORTED_SYMBOLS = [

@@ -127,6 +127,31 @@ def test_pcg_solve_parity(meshes, h2):
     assert rep.history[0] == 1.0 and rep.history[-1] <= 1e-10
 
 
+@pytest.mark.parametrize("h2", [0.0, 0.1])
+def test_single_reduction_pcg_parity(meshes, h2):
+    # the Chronopoulos-Gear form is the same Krylov method: same bars as the
+    # standard form against the oracle (true residual, S-norm error, counts)
+    import torch
+    om, gm = meshes
+    rng = np.random.default_rng(14)
+    b = om.rhs(rng.standard_normal(om.shape))
+    xo, info = om.pcg(b, 1.0, h2, tol=1e-10)
+    x = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
+    rep = gm.pcg_solve(dev(b), x, h1=1.0, h2=h2, rel_tol=1e-10, form=sem.FORM_PCG_1RED, history=True, check_every=8)
+    xg = host(x)
+    r = b - om.apply_S(xg, 1.0, h2)
+    true_rel = np.sqrt(om.dot(r, r) / om.dot(b, b))
+    assert true_rel <= 1.05e-10
+    assert abs(rep.true_rel_res - true_rel) <= 1e-3 * true_rel + 1e-14
+    e = xg - xo
+    en = np.sqrt(max(om.dot(e, om.apply_S(e, 1.0, h2)), 0.0))
+    assert en <= 1e-6 * np.sqrt(om.dot(xo, om.apply_S(xo, 1.0, h2))) + 1e-300
+    assert abs(rep.iterations - info["iterations"]) <= max(2, 0.03 * info["iterations"])
+    assert np.array_equal(xg, om.gather_global(xg)[om.glo])
+    assert np.all(xg[om.mask == 1] == 0.0)
+    assert rep.history[0] == 1.0 and rep.history[-1] <= 1e-10
+
+
 def test_deterministic_repeat():
     import torch
     om, gm = pair(wl.deformed_cube(4, 7))
