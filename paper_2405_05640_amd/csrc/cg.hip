@@ -626,12 +626,12 @@ hipError_t cg1_init(const Mesh &m, const CgVecs<double> &v, const double *b, dou
 
 hipError_t cg1_vec(const Mesh &m, const CgVecs<double> &v, double *u, double *sv, CgState *st, hipStream_t s)
 {
-    const int64_t rows = row_grid(m.lat, 2);
+    const int64_t rows = row_grid(m.lat, 1);
     if (m.lat.NP == 8)
-        hipLaunchKernelGGL((cg::cg1_vec_kernel<2, 8>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
+        hipLaunchKernelGGL((cg::cg1_vec_kernel<1, 8>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
                            sv, u, v.dinv, m.lat, v.part_b);
     else
-        hipLaunchKernelGGL((cg::cg1_vec_kernel<2, 0>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
+        hipLaunchKernelGGL((cg::cg1_vec_kernel<1, 0>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
                            sv, u, v.dinv, m.lat, v.part_b);
     return cg_reduce(v.part_b, rows, 2, v.stage, s);
 }
