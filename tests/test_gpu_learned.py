@@ -145,34 +145,54 @@ def test_pcg_snapshots_match_oracle(mp):
         assert np.linalg.norm(E[q] - ref) <= 1e-7 * np.linalg.norm(om.gather_global(xs))
 
 
-def test_training_reduces_loss_and_helps_fcg():
+def test_training_gain_over_jacobi():
+    # What the trained network gains over the method without it (the zero
+    # network, which is exactly Jacobi): on held-out error fields, the A-norm
+    # error left after one smoothing, |e - M(S e)|_S^2 / |e|_S^2, is lower.
+    # The flexible-CG solve with the trained network still meets the FP64
+    # true residual; its iteration count is reported, not asserted (no
+    # iteration gain is measured for this per-element smoother).
     import torch
     spec = wl.channel(4, 7)
     om, gm = pair(spec)
-    sm = sem.Smoother(gm, seed=0, lr=2e-3)
+    glo = torch.from_numpy(gm.export(sem.FIELD_GLO_NUM).ravel()).cuda()
     vm = wl.kolmogorov_velocity(2)
-    iters = [2, 8, 32]
-    pairs = []
-    for t in range(8):
-        f = wl.fourier_on_elements(wl.divergence_source(vm, t), om.xyz, (4, 4, 4))
-        b = torch.empty(gm.shape, dtype=torch.float64, device="cuda")
-        gm.rhs(dev(f), b)
-        e = torch.zeros(len(iters) * gm.n_global, dtype=torch.float64, device="cuda")
-        sem.pcg_snapshots(gm, b, iters, e)
-        for q in range(len(iters)):
-            pairs.append(e[q * gm.n_global:(q + 1) * gm.n_global].float().contiguous())
+    iters = [1, 2, 4, 8]
+
+    def errors(ts):
+        out = []
+        for t in ts:
+            f = wl.fourier_on_elements(wl.divergence_source(vm, t), om.xyz, (4, 4, 4))
+            b = torch.empty(gm.shape, dtype=torch.float64, device="cuda")
+            gm.rhs(dev(f), b)
+            e = torch.zeros(len(iters) * gm.n_global, dtype=torch.float64, device="cuda")
+            sem.pcg_snapshots(gm, b, iters, e)
+            out += [e[q * gm.n_global:(q + 1) * gm.n_global].contiguous() for q in range(len(iters))]
+        return out
+
+    train = errors(range(8))
+    held = errors(range(40, 42))
+    sm = sem.Smoother(gm, seed=0, lr=2e-3)
+
+    def held_loss():
+        return float(np.mean([sm.loss_grad(e[glo].reshape(gm.shape).contiguous())[0] for e in held]))
+
+    jacobi = held_loss()   # fresh smoother: last layer zero -> Jacobi
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     first, last = [], []
-    for epoch in range(6):
-        for k, ep in enumerate(pairs):
-            sm.train_step(ep, loss)
+    for epoch in range(8):
+        for k, ep in enumerate(train):
+            sm.train_step(ep.float().contiguous(), loss)
             if epoch == 0:
                 first.append(float(loss.item()))
-            if epoch == 5:
+            if epoch == 7:
                 last.append(float(loss.item()))
-    print("loss first epoch %.4f last epoch %.4f" % (np.mean(first), np.mean(last)))
+    trained = held_loss()
+    print("training loss %.4f -> %.4f; held-out one-step A-norm error: Jacobi %.4f, trained %.4f" %
+          (np.mean(first), np.mean(last), jacobi, trained))
     assert np.mean(last) < np.mean(first)
-    # held-out field: FCG with the trained smoother vs Jacobi-PCG
+    assert trained < 0.97 * jacobi
+    # held-out solve: FCG with the trained smoother vs Jacobi-PCG
     f = wl.fourier_on_elements(wl.divergence_source(vm, 50), om.xyz, (4, 4, 4))
     b = om.rhs(f)
     x = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
