@@ -136,17 +136,23 @@ def learned_section(args):
         mesh.rhs(f, b)
         return b
 
-    # training pairs: errors of Jacobi-PCG iterates
+    # training pairs: errors of early Jacobi-PCG iterates
     t0 = time.perf_counter()
-    iters = [2, 8, 32, 128]
-    pairs = []
+    iters = [1, 2, 4, 8]
     ws = mesh.workspace(mesh.solve_opts())
-    for t in range(args.train_fields):
-        b = rhs(t)
-        e = torch.zeros(len(iters) * mesh.n_global, dtype=torch.float64, device="cuda")
-        sem.pcg_snapshots(mesh, b, iters, e, workspace=ws)
-        for q in range(len(iters)):
-            pairs.append(e[q * mesh.n_global:(q + 1) * mesh.n_global].float().contiguous())
+
+    def snapshot_errors(ts):
+        out = []
+        for t in ts:
+            b = rhs(t)
+            e = torch.zeros(len(iters) * mesh.n_global, dtype=torch.float64, device="cuda")
+            sem.pcg_snapshots(mesh, b, iters, e, workspace=ws)
+            out += [e[q * mesh.n_global:(q + 1) * mesh.n_global].contiguous() for q in range(len(iters))]
+        return out
+
+    pairs = [e.float().contiguous() for e in snapshot_errors(range(args.train_fields))]
+    held_err = snapshot_errors(range(3000, 3002))
+    glo = torch.from_numpy(mesh.export(sem.FIELD_GLO_NUM).ravel()).cuda()
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     # Jacobi-PCG reference rate for the stall test
@@ -154,6 +160,11 @@ def learned_section(args):
     r0, _ = timed_solves(mesh, b0, 1)
     rate = (1e-10) ** (1.0 / max(r0["iterations"], 1))
     sm = sem.Smoother(mesh, seed=0, lr=1e-3, stall_window=25, stall_rate=rate)
+
+    def held_loss():
+        return float(np.mean([sm.loss_grad(e[glo].reshape(mesh.shape).contiguous())[0] for e in held_err]))
+
+    loss_jacobi = held_loss()   # fresh smoother: zero last layer, exactly Jacobi
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     losses = []
     t0 = time.perf_counter()
@@ -167,6 +178,7 @@ def learned_section(args):
         losses.append(float(torch.cat(acc).mean().item()))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    loss_trained = held_loss()
     del pairs
     # held-out fields (t beyond the training range)
     res_j, res_l = [], []
@@ -182,6 +194,9 @@ def learned_section(args):
             "train_fields": args.train_fields, "pairs": args.train_fields * len(iters),
             "snapshot_iters": iters, "epochs": args.train_epochs, "loss_per_epoch": [round(v, 5) for v in losses],
             "data_gen_s": round(t_data, 2), "train_s": round(t_train, 2),
+            "heldout_one_step_error": {"jacobi": round(loss_jacobi, 4), "trained": round(loss_trained, 4),
+                                       "what": "A-norm error energy left after one smoother application, "
+                                               "held-out Jacobi-PCG iterate errors"},
             "heldout": args.heldout,
             "jacobi_pcg": {"median_ms": round(tj, 2),
                            "iterations": [r["iterations"] for r in res_j]},
