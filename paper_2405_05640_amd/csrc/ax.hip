@@ -6,8 +6,10 @@
 // matrix-free operator of section 3.1, which the paper's section 4.2 notes is
 // memory bound).
 //
-// Two designs: a thread-per-point kernel for N <= 7 (below) and, for higher
-// orders, the k-pencil kernel (one (N+1)x(N+1) workgroup per element):
+// Three designs: thread-per-point kernels for N <= 7 (one point per thread in
+// FP64; in FP32 at N = 7, several points per thread sharing an (i, j) pencil),
+// and for higher orders the k-pencil kernel (one (N+1)x(N+1) workgroup per
+// element):
 //  - the workgroup is the (N+1)x(N+1) "i,j" plane of an element: lane (i,j)
 //    owns the k-pencil u(i,j,0..N) and w(i,j,0..N) in registers;
 //  - each k-slice of u is staged once in LDS; the r and s derivatives read

@@ -28,14 +28,13 @@ __device__ __forceinline__ void g_to_ijk(const Lattice &L, int64_t g, int64_t &g
     gk = t / L.ny;
 }
 
-// ROWS: w is an operator output in the row layout (solver operator calls);
-// otherwise [E][k][j][i].
-template <bool ROWS, typename T>
+// sum of the copies of node (gi, gj, gk) of a local [E][k][j][i] field
+template <typename T>
 __device__ __forceinline__ double assemble_at(const Lattice &L, const T *__restrict__ w, int gi, int gj, int gk,
                                               bool &masked)
 {
     int loc[8];
-    const int n = node_locals<ROWS>(L, gi, gj, gk, loc, masked);
+    const int n = node_locals(L, gi, gj, gk, loc, masked);
     T s = T(0);
     for (int c = 0; c < n; ++c) s += w[loc[c]];
     return (double)s;
@@ -114,7 +113,7 @@ __global__ void __launch_bounds__(kBS) dinv_kernel(const double *__restrict__ dl
     SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
     {
         bool msk;
-        const double d = assemble_at<false>(L, dl, gi, gj, gk, msk);
+        const double d = assemble_at(L, dl, gi, gj, gk, msk);
         dinv[g] = msk ? T(0) : (T)(1.0 / d);
     }
 }
@@ -264,17 +263,13 @@ resid_kernel(const T *__restrict__ b, const T *__restrict__ w, T *__restrict__ r
              double *__restrict__ part)
 {
     double acc[1] = {0.0};
-    SEM_FOR_EACH_ROW(L, 1, gj, gk, row, rc)
+    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
     {
-        for (int gi = threadIdx.x; gi < L.nx; gi += kBS) {
-            const int64_t g = gi + L.nx * (int64_t)row;
-            const T d = dinv[g], bg = b[g];
-            bool msk;
-            const T wg = row_assemble(L, w, rc, gi, msk);
-            const T rg = d != T(0) ? bg - wg : T(0);
-            r[g] = rg;
-            acc[0] += (double)rg * (double)rg;
-        }
+        const T d = dinv[g], bg = b[g];
+        const T wg = node_assemble_rows<0>(L, w, gi, gj, gk);
+        const T rg = d != T(0) ? bg - wg : T(0);
+        r[g] = rg;
+        acc[0] += (double)rg * (double)rg;
     }
     block_store<1>(acc, part, gridDim.x);
 }

@@ -71,10 +71,9 @@ __device__ __forceinline__ int gather_index32(const Lattice &L, int ex, int ey, 
     return gi + nx * (gj + ny * gk);
 }
 
-// All local indices (ascending) of global node (gi, gj, gk) from the axis
-// tables, 32-bit arithmetic (n_local < 2^31).  Returns the copy count.
-// ROWS: indices into the row layout, else into [E][k][j][i].
-template <bool ROWS = false>
+// All local indices (ascending) of global node (gi, gj, gk) of a local
+// [E][k][j][i] field, from the axis tables, 32-bit arithmetic (n_local <
+// 2^31).  Returns the copy count.
 __device__ inline int node_locals(const Lattice &L, int gi, int gj, int gk, int loc[8], bool &masked)
 {
     const int2 ax = L.tab[0][gi], ay = L.tab[1][gj], az = L.tab[2][gk];
@@ -85,15 +84,8 @@ __device__ inline int node_locals(const Lattice &L, int gi, int gj, int gk, int 
     for (int c = 0; c < cz; ++c)
         for (int b = 0; b < cy; ++b)
             for (int a = 0; a < cx; ++a) {
-                if (ROWS) {
-                    const int X = axis_elem(ax, a) * NP + axis_loc(ax, a);
-                    const int Y = axis_elem(ay, b) * NP + axis_loc(ay, b);
-                    const int Z = axis_elem(az, c) * NP + axis_loc(az, c);
-                    loc[n++] = (Z * (L.nely * NP) + Y) * (L.nelx * NP) + X;
-                } else {
-                    const int e = axis_elem(ax, a) + L.nelx * (axis_elem(ay, b) + L.nely * axis_elem(az, c));
-                    loc[n++] = e * P + axis_loc(ax, a) + NP * (axis_loc(ay, b) + NP * axis_loc(az, c));
-                }
+                const int e = axis_elem(ax, a) + L.nelx * (axis_elem(ay, b) + L.nely * axis_elem(az, c));
+                loc[n++] = e * P + axis_loc(ax, a) + NP * (axis_loc(ay, b) + NP * axis_loc(az, c));
             }
     if (L.unsorted) {
         for (int q = 1; q < n; ++q) {
@@ -222,72 +214,6 @@ __device__ __forceinline__ bool axis_dirichlet(const Lattice &L, int d, int g, i
     if (L.per[d]) return false;
     return (g == 0 && ((L.dir >> (2 * d)) & 1)) || (g == nel * L.N && ((L.dir >> (2 * d + 1)) & 1));
 }
-
-// Copies of one lattice row (gj, gk) in the row layout: the offsets of the
-// (y, z) copies, ascending (uniform over the row's workgroup), and the
-// Dirichlet flag of the y and z axes.
-struct RowCopies {
-    int n;
-    int off[4];
-    bool masked;
-};
-
-__device__ __forceinline__ RowCopies row_copies(const Lattice &L, int gj, int gk)
-{
-    int Y[2], Z[2];
-    const int cy = axis_copies(gj, L.nely, L.N, L.per[1] != 0, Y);
-    const int cz = axis_copies(gk, L.nelz, L.N, L.per[2] != 0, Z);
-    const int nyl = L.nely * L.NP, nxl = L.nelx * L.NP;
-    RowCopies rc;
-    rc.n = 0;
-    rc.masked = axis_dirichlet(L, 1, gj, L.nely) || axis_dirichlet(L, 2, gk, L.nelz);
-    for (int c = 0; c < cz; ++c)
-        for (int b = 0; b < cy; ++b) rc.off[rc.n++] = (Z[c] * nyl + Y[b]) * nxl;
-    return rc;   // ascending: Z and Y are ascending and Y < nyl
-}
-
-// Q^T w at node gi of a row with copies rc (w in the row layout), summed in
-// ascending local index -- the order of node_locals<true>.  All loads are
-// issued before the first add.  masked: Dirichlet flag of the node.
-template <typename T>
-__device__ __forceinline__ T row_assemble(const Lattice &L, const T *__restrict__ w, const RowCopies &rc, int gi,
-                                          bool &masked)
-{
-    int X[2];
-    const bool two = axis_copies(gi, L.nelx, L.N, L.per[0] != 0, X) > 1;
-    masked = rc.masked || axis_dirichlet(L, 0, gi, L.nelx);
-    T v0[4], v1[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        v0[q] = T(0);
-        v1[q] = T(0);
-        if (q < rc.n) {
-            v0[q] = w[rc.off[q] + X[0]];
-            if (two) v1[q] = w[rc.off[q] + X[1]];
-        }
-    }
-    T s = T(0);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        if (q < rc.n) {
-            s += v0[q];
-            if (two) s += v1[q];
-        }
-    }
-    return s;
-}
-
-// Workgroup loop over lattice rows [RPB blockIdx.x, RPB blockIdx.x + RPB)
-// with the row's copies: binds gj, gk, row (int) and rc for the body.  The
-// workgroups sweep the rows in launch order (no XCD remap: every stream of a
-// row kernel is sequential, and measured sweeps run faster when all XCDs
-// advance through memory together).  Launch with ceil(ny nz / RPB) blocks.
-#define SEM_FOR_EACH_ROW(L, RPB, gj, gk, row, rc)                                                        \
-    for (int row = (int)blockIdx.x * (RPB),                                                              \
-             rend_ = row + (RPB) < (int)((L).ny * (L).nz) ? row + (RPB) : (int)((L).ny * (L).nz);       \
-         row < rend_; ++row)                                                                             \
-        if (const int gj = row % (int)(L).ny, gk = row / (int)(L).ny; true)                              \
-            if (const RowCopies rc = row_copies(L, gj, gk); true)
 
 // Loop over the global nodes of lattice row blockIdx.x = gj + ny gk (one
 // workgroup per row, threads over gi): no index is divided per node and every

@@ -33,11 +33,8 @@ namespace lk {
 __device__ __forceinline__ double assemble_at(const Lattice &L, const double *__restrict__ w, int gi, int gj, int gk,
                                               bool &masked)
 {
-    int loc[8];
-    const int n = node_locals<true>(L, gi, gj, gk, loc, masked);
-    double s = 0.0;
-    for (int c = 0; c < n; ++c) s += w[loc[c]];
-    return s;
+    masked = lattice_masked(L, gi, gj, gk);
+    return node_assemble_rows<0>(L, w, gi, gj, gk);
 }
 
 template <int NV>

@@ -33,7 +33,9 @@
 // true residual r = b - S x is scaled to unit norm, rounded to FP32, an FP32
 // PCG on the FP32 operator solves S d = r to inner_tol, and x += |r| d in
 // FP64.  FP64 is kept for the outer residual, every inner product and the
-// convergence tests.
+// convergence tests.  The reliable-update forms keep one low-precision Krylov
+// process and replace its residual instead (solve_reliable); the
+// single-reduction form is solve_pcg1.
 #include <chrono>
 #include <cmath>
 #include <cstring>
