@@ -71,8 +71,8 @@ gs_xface_kernel(T *__restrict__ u, Lattice L, int mx, const int32_t *__restrict_
     for (int c = 0; c < n; ++c) u[loc[c]] = s;
 }
 
-// Whole-row pass (the default): whole wavefronts per global lattice row
-// (gj, gk); the kernel also takes several rows per workgroup.
+// Whole-row pass (the default): a workgroup of whole wavefronts per RPT
+// global lattice rows (gj, gk).
 // The row's copies in y and z are uniform over the workgroup (up to 2 x 2
 // element rows), and thread X = ex (N+1) + i reads local point i of element
 // ex in each of them.  Every 8-value element row of the field is read once, as
@@ -83,41 +83,45 @@ gs_xface_kernel(T *__restrict__ u, Lattice L, int mx, const int32_t *__restrict_
 // same ascending-local-index order as the copy enumeration.  Nodes with a
 // single copy are not written.  Needs nelx (N+1) <= 1024 and sorted axis
 // tables (no periodic single-element axis).
-template <typename T, int MASK>
+template <typename T, int MASK, int RPT>
 __global__ void __launch_bounds__(1024)
 gs_lattice_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip)
 {
     if (skip && *skip) return;
     extern __shared__ __attribute__((aligned(16))) unsigned char gs_smem[];
-    const int NP = L.NP, P = (int)L.P, nxl = L.nelx * NP;
-    const int nxp = (nxl + 63) / 64 * 64;          // threads per row (whole wavefronts)
-    const int rq = (int)threadIdx.x / nxp;         // row of this wavefront within the workgroup
-    const int row = (int)blockIdx.x * ((int)blockDim.x / nxp) + rq;
-    T *sv = (T *)gs_smem + (size_t)rq * 4 * nxl;   // [4][nelx (N+1)] per row
-    const bool row_ok = row < (int)(L.ny * L.nz);
-    const int gj = row_ok ? row % (int)L.ny : 0, gk = row_ok ? row / (int)L.ny : 0;
-    const int2 ay = L.tab[1][gj], az = L.tab[2][gk];
-    const int cy = axis_count(ay), cz = axis_count(az);
-    const bool msk_yz = MASK && (axis_masked(ay) || axis_masked(az));
-    const int X = (int)threadIdx.x - rq * nxp;
-    const bool live = row_ok && X < nxl;
+    const int NP = L.NP, P = (int)L.P, nxl = L.nelx * NP, nrows = (int)(L.ny * L.nz);
+    const int X = (int)threadIdx.x;
     const int ex = X / NP, i = X - ex * NP;
-    T own[4];
-    int loc[4];
+    // every load of the thread's RPT rows first, then one barrier
+    T own[RPT][4];
+    int loc[RPT][4], cyz[RPT][2];
+    bool mskyz[RPT];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int r = 0; r < RPT; ++r) {
+        const int row = (int)blockIdx.x * RPT + r;
+        const bool row_ok = row < nrows;
+        const int gj = row_ok ? row % (int)L.ny : 0, gk = row_ok ? row / (int)L.ny : 0;
+        const int2 ay = L.tab[1][gj], az = L.tab[2][gk];
+        const int cy = row_ok ? axis_count(ay) : 0, cz = row_ok ? axis_count(az) : 0;
+        cyz[r][0] = cy;
+        cyz[r][1] = cz;
+        mskyz[r] = MASK && (axis_masked(ay) || axis_masked(az));
+        T *sv = (T *)gs_smem + (size_t)r * 4 * nxl;   // [4][nelx (N+1)] per row
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int q = c * 2 + b;
-            if (live && c < cz && b < cy) {
-                const int e = ex + L.nelx * (axis_elem(ay, b) + L.nely * axis_elem(az, c));
-                loc[q] = e * P + i + NP * (axis_loc(ay, b) + NP * axis_loc(az, c));
-                own[q] = u[loc[q]];
-                sv[q * nxl + X] = own[q];
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int q = c * 2 + b;
+                if (X < nxl && c < cz && b < cy) {
+                    const int e = ex + L.nelx * (axis_elem(ay, b) + L.nely * axis_elem(az, c));
+                    loc[r][q] = e * P + i + NP * (axis_loc(ay, b) + NP * axis_loc(az, c));
+                    own[r][q] = u[loc[r][q]];
+                    sv[q * nxl + X] = own[r][q];
+                }
             }
-        }
+    }
     __syncthreads();
-    if (!live) return;
+    if (X >= nxl) return;
     // x partner of this node: the neighbouring element's end point
     int part = -1;
     bool part_first = false;
@@ -129,26 +133,32 @@ gs_lattice_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip
         part_first = ex == L.nelx - 1;
     }
     const int gi = ex * L.N + i;   // global x index (wrapped below when periodic)
-    const bool msk = MASK && (msk_yz || (!L.per[0] && ((gi == 0 && (L.dir & 1)) ||
-                                                      (gi == L.nelx * L.N && (L.dir & 2)))));
-    if (cy * cz == 1 && part < 0 && !msk) return;   // single copy: unchanged
-    T s = T(0);
-    if (!msk) {
+    const bool msk_x = MASK && !L.per[0] && ((gi == 0 && (L.dir & 1)) || (gi == L.nelx * L.N && (L.dir & 2)));
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+    for (int r = 0; r < RPT; ++r) {
+        const int cy = cyz[r][0], cz = cyz[r][1];
+        if (cy == 0) continue;   // past the last row
+        const bool msk = msk_x || mskyz[r];
+        if (cy * cz == 1 && part < 0 && !msk) continue;   // single copy: unchanged
+        const T *sv = (const T *)gs_smem + (size_t)r * 4 * nxl;
+        T s = T(0);
+        if (!msk) {
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int q = c * 2 + b;
-                if (c < cz && b < cy) {
-                    if (part >= 0 && part_first) s += sv[q * nxl + part];
-                    s += own[q];
-                    if (part >= 0 && !part_first) s += sv[q * nxl + part];
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int q = c * 2 + b;
+                    if (c < cz && b < cy) {
+                        if (part >= 0 && part_first) s += sv[q * nxl + part];
+                        s += own[r][q];
+                        if (part >= 0 && !part_first) s += sv[q * nxl + part];
+                    }
                 }
-            }
-    }
+        }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if ((q >> 1) < cz && (q & 1) < cy) u[loc[q]] = s;
+        for (int q = 0; q < 4; ++q)
+            if ((q >> 1) < cz && (q & 1) < cy) u[loc[r][q]] = s;
+    }
 }
 
 __global__ void scale_by_B_kernel(const double *__restrict__ f, const double *__restrict__ Bm,
@@ -213,16 +223,17 @@ hipError_t dssum_impl(const Mesh &m, T *u, int apply_mask, hipStream_t s, const 
     if (rows == 0) return hipSuccess;
     const int nxl = L.nelx * L.NP;
     if (!L.unsorted && nxl <= 1024) {
-        // whole wavefronts per row; one row per workgroup measured fastest on
-        // the 32^3 case (76 us, against 93 us with four rows per workgroup)
+        // one workgroup of whole wavefronts per RPT rows, each thread taking
+        // the same x position in every row with all its loads issued first
+        // (32^3 case: 79 us with one row, 69 us with two or three, 78 with four)
+        constexpr int RPT = 2;
         const int nxp = (nxl + 63) / 64 * 64;
-        const int rpb = 1;
-        const dim3 block((unsigned)(rpb * nxp)), grid((unsigned)((rows + rpb - 1) / rpb));
-        const size_t lds = (size_t)rpb * 4 * nxl * sizeof(T);
+        const dim3 block((unsigned)nxp), grid((unsigned)((rows + RPT - 1) / RPT));
+        const size_t lds = (size_t)RPT * 4 * nxl * sizeof(T);
         if (apply_mask)
-            hipLaunchKernelGGL((gs_lattice_kernel<T, 1>), grid, block, lds, s, u, L, skip);
+            hipLaunchKernelGGL((gs_lattice_kernel<T, 1, RPT>), grid, block, lds, s, u, L, skip);
         else
-            hipLaunchKernelGGL((gs_lattice_kernel<T, 0>), grid, block, lds, s, u, L, skip);
+            hipLaunchKernelGGL((gs_lattice_kernel<T, 0, RPT>), grid, block, lds, s, u, L, skip);
         return hipGetLastError();
     }
     const unsigned g1 = (unsigned)rows;
