@@ -301,7 +301,7 @@ def main():
         profile_kernels()
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no sharding or collectives); "
+        print("bench.py: the solver runs on one GPU only (no sharding or collectives); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np

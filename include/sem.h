@@ -46,7 +46,7 @@ typedef enum {
     SEM_ERR_HIP = 3,           /* a HIP runtime call failed */
     SEM_ERR_NOT_CONVERGED = 4, /* max_iter reached; x holds the last iterate */
     SEM_ERR_BREAKDOWN = 5,     /* non-finite value or (p, S p) <= 0 in CG */
-    SEM_ERR_UNSUPPORTED = 6    /* valid request this build does not provide */
+    SEM_ERR_UNSUPPORTED = 6    /* valid request the library does not provide */
 } sem_status;
 
 typedef enum { SEM_F64 = 0, SEM_F32 = 1, SEM_BF16 = 2, SEM_BF16_SPLIT = 3 } sem_dtype;

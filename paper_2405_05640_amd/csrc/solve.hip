@@ -242,7 +242,7 @@ sem_status solve_pcg64(const Mesh &m, const sem_solve_opts &o, const Workspace &
     return SEM_OK;
 }
 
-// Single-reduction Jacobi-PCG (Chronopoulos & Gear 1989; the survey's
+// Single-reduction Jacobi-PCG (Chronopoulos & Gear 1989; a
 // communication-reducing CG): per iteration one vector pass, the operator on
 // u = dinv r, and one finalize that forms alpha and beta from the three inner
 // products of the same reduction phase.  Same convergence test and
