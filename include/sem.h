@@ -109,10 +109,13 @@ sem_status sem_mesh_export(const sem_mesh *mesh, int field, void *host_dst, size
  * in = SEM_F64: u, w double.  in = SEM_F32: u, w float (needs SEM_PREP_F32).
  * in = SEM_BF16: u bf16 (uint16 bit patterns), w float, contractions on the
  * matrix cores with fp32 accumulation (needs SEM_PREP_BF16).
- * in = SEM_BF16_SPLIT: u, w float; G and B stored in bf16, every contraction
- * operand carried as a hi + lo bf16 pair on the matrix cores (hi.hi + lo.hi +
- * hi.lo, fp32 sums): the exact operator with bf16-rounded G and B to about
- * 2^-16 relative (needs SEM_PREP_BF16).  Both bf16 forms need N = 7. */
+ * in = SEM_BF16_SPLIT: u, w float; G and B stored in IEEE half with one
+ * power-of-two scale per element and array (the element's largest value in
+ * [2^14, 2^15) before rounding), every contraction operand carried as a hi +
+ * lo bf16 pair on the matrix cores (hi.hi + lo.hi + hi.lo, fp32 sums): the
+ * exact operator with those stored G and B to about 2^-16 relative (needs
+ * SEM_PREP_BF16, which builds both the bf16 and the half copies).  Both bf16
+ * forms need N = 7. */
 sem_status sem_ax(const sem_mesh *mesh, double h1, double h2, sem_dtype in,
                   const void *u, void *w, void *stream);
 

@@ -12,11 +12,12 @@ precisions so the GPU results can be bounded against them:
   G-combination is float32 and its three results are rounded to BF16; the
   transposed contractions sum in float32 and the r, s, t contributions are
   added in that order; the Helmholtz term h2 B u is float32.
-* BF16 split: G and B are stored in BF16 (rounded through float32); u, D and
+* BF16 split: G and B are stored in IEEE half precision with one
+  power-of-two scale per element and array (``f16_scaled_storage``); u, D and
   the intermediate fluxes enter the matrix cores as hi + lo BF16 pairs
   (three products per contraction, FP32 sums).  Its reference is the exact
-  operator with the BF16-rounded G and B (``ax_bf16_split_reference``); the
-  split reproduces that to about 2^-16 relative.
+  operator with the stored G and B (``ax_bf16_split_reference``); the split
+  reproduces that to about 2^-16 relative.
 """
 from __future__ import annotations
 
@@ -82,6 +83,34 @@ def bf16_storage(a):
     return bf16_round(np.asarray(a).astype(np.float32)).astype(np.float64)
 
 
+def f16_scale_exponents(a, elem_axis):
+    """Per-element exponent k of the half-precision storage: the largest
+    magnitude of the element's values divided by 2^k lies in [2^14, 2^15),
+    the top binade below the half-precision maximum (k = 0 for an element of
+    zeros)."""
+    a = np.asarray(a, dtype=np.float64)
+    axes = tuple(d for d in range(a.ndim) if d != elem_axis)
+    m = np.max(np.abs(a), axis=axes)
+    _, x = np.frexp(m)            # m = f 2^x with f in [0.5, 1)
+    return np.where(m > 0, x - 15, 0).astype(np.int64)
+
+
+def f16_scaled_storage(a, elem_axis):
+    """Values as the split-BF16 operator stores them: per element, a / 2^k
+    rounded to IEEE half (ties to even, straight from float64), times 2^k,
+    as float64.  The scaling by a power of two is exact, so the only error is
+    the half rounding, at most 2^-11 relative (or 2^-39 of the element's
+    largest magnitude for values that fall below the half normal range)."""
+    a = np.asarray(a, dtype=np.float64)
+    k = f16_scale_exponents(a, elem_axis)
+    shape = [1] * a.ndim
+    shape[elem_axis] = -1
+    k = k.reshape(shape)
+    h = np.ldexp(a, -k).astype(np.float16)
+    return np.ldexp(h.astype(np.float64), k)
+
+
 def ax_bf16_split_reference(mesh, u, h1, h2):
-    """Exact (FP64) local operator with BF16-stored G and B."""
-    return mesh.ax(u, h1, h2, G=bf16_storage(mesh.G), B=bf16_storage(mesh.B))
+    """Exact (FP64) local operator with G [6, E, ...] and B [E, ...] as the
+    split-BF16 operator stores them (half precision, per-element scale)."""
+    return mesh.ax(u, h1, h2, G=f16_scaled_storage(mesh.G, 1), B=f16_scaled_storage(mesh.B, 0))

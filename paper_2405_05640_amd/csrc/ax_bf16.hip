@@ -34,6 +34,13 @@ __device__ __forceinline__ float bf_at(const u32x4 &v, int q)
     return __uint_as_float((q & 1) ? (w & 0xffff0000u) : (w << 16));
 }
 
+// half-precision entry q (0..7) of a 16-byte vector, widened to float (exact)
+__device__ __forceinline__ float h_at(const u32x4 &v, int q)
+{
+    const unsigned w = v[q >> 1];
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)((q & 1) ? (w >> 16) : (w & 0xffffu)));
+}
+
 // point index of entry c (0..7) of line L along direction dir (0 = r, 1 = s, 2 = t)
 __device__ __forceinline__ int line_point(int dir, int L, int c)
 {
@@ -177,9 +184,12 @@ ax_bf16_kernel(const void *__restrict__ uin, float *__restrict__ w, const unsign
 // of a contraction (u, D, the fluxes, D^T) is carried as a pair of BF16
 // numbers x = hi + lo (hi = bf16(x), lo = bf16(x - hi): 16 significant bits),
 // and a contraction sums hi.Dhi + lo.Dhi + hi.Dlo in FP32 (the lo.lo product,
-// about 2^-18 relative, is dropped).  G and B are BF16 storage, so the
-// operator reproduces the exact operator with BF16-rounded G and B to about
-// 2^-16 relative while streaming 12 + 2 bytes of geometry per point.
+// about 2^-18 relative, is dropped).  The hi/lo split of u and of the
+// fluxes is made once per value, into LDS.  G and B are IEEE half storage
+// with one power-of-two scale per element and array (11 significant bits,
+// the largest value of an element in the top half binade), so the operator
+// reproduces the exact operator with those stored G and B to about 2^-16
+// relative while streaming 12 + 2 bytes of geometry per point.
 //
 // One 16x16x32 MFMA handles 16 lines of a direction: A row m = line
 // (K = [hi(8) | lo(8) | hi(8) | 0(8)]), B = [Dhi^T; Dhi^T; Dlo^T; 0] in output
@@ -187,30 +197,36 @@ ax_bf16_kernel(const void *__restrict__ uin, float *__restrict__ w, const unsign
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short s16x8;
 
-__device__ __forceinline__ void contract_split(int dir, const float *src, float *dst, bf16x8 bop, bool acc)
+// hi and lo BF16 parts of eight FP32 values
+__device__ __forceinline__ void split8(const float (&v)[8], s16x8 &h, s16x8 &l)
+{
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const unsigned short hb = f2bf(v[q]);
+        h[q] = (short)hb;
+        l[q] = (short)f2bf(v[q] - bf2f(hb));
+    }
+}
+
+// One directional contraction of a 512-point tile whose values were split
+// once into hi and lo BF16 arrays (LDS): four MFMAs, 16 lines each.
+__device__ __forceinline__ void contract_split(int dir, const unsigned short *hi, const unsigned short *lo, float *dst,
+                                               bf16x8 bop, bool acc)
 {
     const int lane = threadIdx.x & 63;
     const int m = lane & 15, g = lane >> 4, n = lane & 15;
+    const unsigned short *src = g == 1 ? lo : hi;   // K groups: hi | lo | hi | (zero)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int L = 16 * t + m;
-        // every lane reads its line (branch-free); group 3 contributes zeros
-        float v[8];
+        s16x8 a;
         if (dir == 0) {
-            const float4 v0 = *(const float4 *)&src[L * 8], v1 = *(const float4 *)&src[L * 8 + 4];
-            v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
-            v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+            a = *(const s16x8 *)&src[L * 8];
         } else {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = src[line_point(dir, L, q)];
+            for (int q = 0; q < 8; ++q) a[q] = (short)src[line_point(dir, L, q)];
         }
-        s16x8 a;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float x = g == 3 ? 0.f : v[q];
-            const float h = bf2f(f2bf(x));
-            a[q] = (short)f2bf(g == 1 ? x - h : x);
-        }
+        if (g == 3) a = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
         f4 c = {0.f, 0.f, 0.f, 0.f};
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), bop, c, 0, 0, 0);
         // C: column n = entry (n < 8), rows 4 g + q = lines 16 t + 4 g + q
@@ -230,13 +246,20 @@ __device__ __forceinline__ void contract_split(int dir, const float *src, float 
 template <bool GATHER, bool HELM>
 __global__ void __launch_bounds__(64)
 ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsigned short *__restrict__ G,
-                const unsigned short *__restrict__ Bm, const unsigned short *__restrict__ Dhl, float h1, float h2,
-                double *__restrict__ partial, const int32_t *__restrict__ skip, Lattice L)
+                const unsigned short *__restrict__ Bm, const float *__restrict__ scale,
+                const unsigned short *__restrict__ Dhl, float h1, float h2, double *__restrict__ partial,
+                const int32_t *__restrict__ skip, Lattice L)
 {
+    // G and B are half-precision values of one element, each array with its
+    // own power-of-two scale; the scales multiply h1 and h2 (exact).
     if (skip && *skip) return;
-    __shared__ __attribute__((aligned(16))) float su[512];      // u, then the accumulated output
-    __shared__ __attribute__((aligned(16))) float sd[3][512];   // derivatives, then the fluxes
-    __shared__ unsigned short sD[128];                           // D hi | D lo
+    // LDS: u as hi | lo BF16 (later the FP32 accumulator), the FP32
+    // derivatives (later the fluxes as hi | lo BF16), D hi | lo
+    __shared__ __attribute__((aligned(16))) unsigned short su[2][512];
+    __shared__ __attribute__((aligned(16))) float sd[3][512];
+    __shared__ unsigned short sD[128];
+    float *acc = (float *)&su[0][0];
+    unsigned short *sf = (unsigned short *)&sd[0][0];   // [3][2][512]
     const int lane = threadIdx.x;
     const int64_t e = xcd_block();
     int ex = 0, ey = 0, ez = 0;   // element coordinates (gather mode)
@@ -247,6 +270,7 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
     for (int c = 0; c < 6; ++c) gq[c] = __builtin_nontemporal_load((const u32x4 *)(Ge + c * 512) + lane);
     u32x4 bq = {0u, 0u, 0u, 0u};
     if (HELM) bq = __builtin_nontemporal_load((const u32x4 *)(Bm + e * 512) + lane);
+    const float2 sc = ((const float2 *)scale)[e];
     sD[lane] = Dhl[lane];
     sD[64 + lane] = Dhl[64 + lane];
     // lane owns the 8-point row p = 8 lane + q: i = q, j = lane & 7, k = lane >> 3
@@ -259,8 +283,12 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
         uu[0] = v0.x; uu[1] = v0.y; uu[2] = v0.z; uu[3] = v0.w;
         uu[4] = v1.x; uu[5] = v1.y; uu[6] = v1.z; uu[7] = v1.w;
     }
-    ((float4 *)su)[2 * lane] = make_float4(uu[0], uu[1], uu[2], uu[3]);
-    ((float4 *)su)[2 * lane + 1] = make_float4(uu[4], uu[5], uu[6], uu[7]);
+    {
+        s16x8 h, l;
+        split8(uu, h, l);
+        *(s16x8 *)&su[0][8 * lane] = h;
+        *(s16x8 *)&su[1][8 * lane] = l;
+    }
     __syncthreads();
     // B operands (lane: column n, K rows 8 g + q)
     const int n = lane & 15, g = lane >> 4;
@@ -274,43 +302,45 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
         }
     }
     const bf16x8 bF = __builtin_bit_cast(bf16x8, bFs), bT = __builtin_bit_cast(bf16x8, bTs);
-    contract_split(0, su, sd[0], bF, false);
-    contract_split(1, su, sd[1], bF, false);
-    contract_split(2, su, sd[2], bF, false);
+    contract_split(0, su[0], su[1], sd[0], bF, false);
+    contract_split(1, su[0], su[1], sd[1], bF, false);
+    contract_split(2, su[0], su[1], sd[2], bF, false);
     __syncthreads();
-    // G-combination in FP32 (fluxes kept in FP32)
-    float fr[8], fs[8], ft[8];
+    // G-combination in FP32; the fluxes are split once into hi | lo BF16
+    float fl[3][8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int p = 8 * lane + q;
         const float ur = sd[0][p], us = sd[1][p], ut = sd[2][p];
-        const float g11 = bf_at(gq[0], q), g12 = bf_at(gq[1], q), g13 = bf_at(gq[2], q);
-        const float g22 = bf_at(gq[3], q), g23 = bf_at(gq[4], q), g33 = bf_at(gq[5], q);
-        fr[q] = g11 * ur + g12 * us + g13 * ut;
-        fs[q] = g12 * ur + g22 * us + g23 * ut;
-        ft[q] = g13 * ur + g23 * us + g33 * ut;
+        const float g11 = h_at(gq[0], q), g12 = h_at(gq[1], q), g13 = h_at(gq[2], q);
+        const float g22 = h_at(gq[3], q), g23 = h_at(gq[4], q), g33 = h_at(gq[5], q);
+        fl[0][q] = g11 * ur + g12 * us + g13 * ut;
+        fl[1][q] = g12 * ur + g22 * us + g23 * ut;
+        fl[2][q] = g13 * ur + g23 * us + g33 * ut;
     }
     __syncthreads();
-    ((float4 *)sd[0])[2 * lane] = make_float4(fr[0], fr[1], fr[2], fr[3]);
-    ((float4 *)sd[0])[2 * lane + 1] = make_float4(fr[4], fr[5], fr[6], fr[7]);
-    ((float4 *)sd[1])[2 * lane] = make_float4(fs[0], fs[1], fs[2], fs[3]);
-    ((float4 *)sd[1])[2 * lane + 1] = make_float4(fs[4], fs[5], fs[6], fs[7]);
-    ((float4 *)sd[2])[2 * lane] = make_float4(ft[0], ft[1], ft[2], ft[3]);
-    ((float4 *)sd[2])[2 * lane + 1] = make_float4(ft[4], ft[5], ft[6], ft[7]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s16x8 h, l;
+        split8(fl[a], h, l);
+        *(s16x8 *)&sf[(2 * a) * 512 + 8 * lane] = h;
+        *(s16x8 *)&sf[(2 * a + 1) * 512 + 8 * lane] = l;
+    }
     __syncthreads();
-    // transposed contractions accumulated r, s, t into su (u is in registers)
-    contract_split(0, sd[0], su, bT, false);
+    // transposed contractions accumulated r, s, t (u itself is in registers)
+    contract_split(0, sf + 0 * 512, sf + 1 * 512, acc, bT, false);
     __syncthreads();
-    contract_split(1, sd[1], su, bT, true);
+    contract_split(1, sf + 2 * 512, sf + 3 * 512, acc, bT, true);
     __syncthreads();
-    contract_split(2, sd[2], su, bT, true);
+    contract_split(2, sf + 4 * 512, sf + 5 * 512, acc, bT, true);
     __syncthreads();
+    const float h1s = h1 * sc.x, h2s = h2 * sc.y;
     double dot = 0.0;
     float out[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        float v = h1 * su[8 * lane + q];
-        if (HELM) v += h2 * bf_at(bq, q) * uu[q];
+        float v = h1s * acc[8 * lane + q];
+        if (HELM) v += h2s * h_at(bq, q) * uu[q];
         out[q] = v;
         if (partial) dot += (double)uu[q] * (double)v;
     }
@@ -354,8 +384,8 @@ hipError_t launch_ax_bf16s(const Mesh &m, float h1, float h2, const float *u, fl
     const bool helm = h2 != 0.f;
     const dim3 grid((unsigned)m.E), block(64);
 #define SEM_BF16S(G_, H_)                                                                                     \
-    hipLaunchKernelGGL((ax_bf16s_kernel<G_, H_>), grid, block, 0, s, u, w, m.d_Gbf, m.d_Bbf, m.d_Dbf, h1, h2, \
-                       partial, skip, m.lat)
+    hipLaunchKernelGGL((ax_bf16s_kernel<G_, H_>), grid, block, 0, s, u, w, m.d_Gh, m.d_Bh, m.d_hscale, m.d_Dbf, \
+                       h1, h2, partial, skip, m.lat)
     if (gather) {
         if (helm) SEM_BF16S(true, true);
         else SEM_BF16S(true, false);

@@ -108,6 +108,38 @@ static uint16_t to_bf16(float f)
     return (uint16_t)(u >> 16);
 }
 
+// IEEE half bits of a double, rounded to nearest (ties to even) straight from
+// the double.  |v| must be below 65520 (no overflow handling: the callers
+// scale their values into [0, 2^15)).
+static uint16_t to_f16(double v)
+{
+    const uint16_t sign = std::signbit(v) ? 0x8000u : 0u;
+    const double a = std::fabs(v);
+    if (a == 0.0) return sign;
+    int x;
+    std::frexp(a, &x);                               // a in [2^(x-1), 2^x)
+    const int qexp = std::max(x - 11, -24);          // grid spacing 2^qexp (normal: 11 bits; subnormal: 2^-24)
+    const double r = std::nearbyint(std::ldexp(a, -qexp));   // exact scaling, then ties to even
+    const double val = std::ldexp(r, qexp);
+    if (val < 0x1p-14) return (uint16_t)(sign | (uint16_t)r);   // subnormal (r < 1024)
+    int y;
+    std::frexp(val, &y);                             // val in [2^(y-1), 2^y)
+    const uint32_t mant = (uint32_t)std::ldexp(val, 11 - y) - 1024u;
+    return (uint16_t)(sign | (uint16_t)((y - 1 + 15) << 10) | (uint16_t)mant);
+}
+
+// Per-element power-of-two scale of the half storage: exponent k with
+// max |a| / 2^k in [2^14, 2^15) (0 for an element of zeros).
+static int f16_exponent(const double *a, int64_t n)
+{
+    double mx = 0.0;
+    for (int64_t q = 0; q < n; ++q) mx = std::max(mx, std::fabs(a[q]));
+    if (mx == 0.0) return 0;
+    int x;
+    std::frexp(mx, &x);
+    return x - 15;
+}
+
 // ---------------------------------------------------------------------------
 // Structured numbering: gi = ex N + i (mod nx if periodic), glo = gi + nx (gj + ny gk).
 
@@ -152,7 +184,7 @@ static sem_status upload(T **dst, const T *src, size_t count, size_t &acc)
 static void release(Mesh &m)
 {
     void *ptrs[] = {m.d_D, m.d_D32, m.d_Dbf, m.d_G, m.d_B, m.d_xyz, m.d_wcode, m.d_mult,
-                    m.d_G32, m.d_B32, m.d_Gbf, m.d_Bbf, m.d_scratch, m.d_tab};
+                    m.d_G32, m.d_B32, m.d_Gbf, m.d_Bbf, m.d_Gh, m.d_Bh, m.d_hscale, m.d_scratch, m.d_tab};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -355,6 +387,22 @@ static sem_status build(const sem_mesh_desc &d, Mesh &m)
         for (int64_t q = 0; q < nl; ++q) bb[q] = to_bf16((float)B[q]);
         SEM_TRY(upload(&m.d_Gbf, gb.data(), gb.size(), acc));
         SEM_TRY(upload(&m.d_Bbf, bb.data(), bb.size(), acc));
+        // half storage with one power-of-two scale per element and array
+        // (the split-BF16 operator's G and B)
+        std::vector<uint16_t> gh((size_t)6 * nl), bh(nl);
+        std::vector<float> sc((size_t)2 * m.E);
+#pragma omp parallel for schedule(static)
+        for (int64_t e = 0; e < m.E; ++e) {
+            const double *Ge = G.get() + e * 6 * P, *Be = B.get() + e * P;
+            const int kg = f16_exponent(Ge, 6 * P), kb = f16_exponent(Be, P);
+            for (int64_t q = 0; q < 6 * P; ++q) gh[e * 6 * P + q] = to_f16(std::ldexp(Ge[q], -kg));
+            for (int64_t q = 0; q < P; ++q) bh[e * P + q] = to_f16(std::ldexp(Be[q], -kb));
+            sc[2 * e] = std::ldexp(1.0f, kg);
+            sc[2 * e + 1] = std::ldexp(1.0f, kb);
+        }
+        SEM_TRY(upload(&m.d_Gh, gh.data(), gh.size(), acc));
+        SEM_TRY(upload(&m.d_Bh, bh.data(), bh.size(), acc));
+        SEM_TRY(upload(&m.d_hscale, sc.data(), sc.size(), acc));
     }
     m.scratch_len = dot_blocks(m) + 1;
     {

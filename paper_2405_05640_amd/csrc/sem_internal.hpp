@@ -49,6 +49,10 @@ struct Mesh {
     int2 *d_tab = nullptr;       // axis copy tables (x, y, z concatenated)
     float *d_G32 = nullptr, *d_B32 = nullptr;          // [E][6][P], [E][P]
     uint16_t *d_Gbf = nullptr, *d_Bbf = nullptr;       // bf16 copies
+    // half copies for the split-BF16 operator: value = half(a / 2^k) 2^k with
+    // one k per element and array; d_hscale[2 e] = 2^k of G, [2 e + 1] of B
+    uint16_t *d_Gh = nullptr, *d_Bh = nullptr;
+    float *d_hscale = nullptr;
     double *d_scratch = nullptr;  // small device scratch for sem_dot partials
     int32_t scratch_len = 0;
     size_t device_bytes = 0;

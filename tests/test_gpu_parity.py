@@ -303,9 +303,10 @@ def test_ax_bf16_matrix_cores():
 
 @pytest.mark.parametrize("spec", [wl.deformed_cube(3, 7), wl.channel(3, 7)], ids=["deformed3_N7", "channel3_N7"])
 def test_ax_bf16_split_matrix_cores(spec):
-    # the split-BF16 operator against the exact operator with BF16-stored G
-    # and B: within a 2^-15-level bound (about 2^-8 tighter than the plain
-    # BF16 operator), and far closer to it than that operator is to FP64
+    # the split-BF16 operator against the exact operator with its stored G and
+    # B (half precision, per-element scale): within a 2^-15-level bound
+    # (about 2^-8 tighter than the plain BF16 operator), and well closer to
+    # it than that operator is to FP64 (storage 2^-11 against split 2^-16)
     import torch
     from oracle import mixed
     om, gm = pair(spec, prepare=sem.SEM_PREP_BF16)
@@ -320,7 +321,9 @@ def test_ax_bf16_split_matrix_cores(spec):
         bound = (3 * (om.N + 1) + 6) * 2.0 ** -15 * om.ax_abs_bound(u, 1.0, h2)
         assert np.all(np.abs(wg - ref) <= bound + 1e-30)
         w64 = om.ax(u, 1.0, h2)
-        assert np.linalg.norm(wg - ref) <= 0.05 * np.linalg.norm(ref - w64)
+        ratio = np.linalg.norm(wg - ref) / np.linalg.norm(ref - w64)
+        print("split-BF16 %s h2=%g: |gpu - ref| / |ref - fp64| = %.4f" % (spec.name, h2, ratio))
+        assert ratio <= 0.1
 
 
 @pytest.mark.parametrize("spec", [wl.deformed_cube(4, 7), wl.channel(3, 7)], ids=["deformed4_N7", "channel3_N7"])

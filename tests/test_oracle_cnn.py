@@ -156,20 +156,91 @@ def test_bf16_rounding_and_lowp_operator_bounds():
     assert e16 > 100 * e32
 
 
-def test_bf16_storage_reference_operator():
-    # the split-BF16 operator's reference: the exact operator with G and B
-    # rounded to BF16.  Rounding is idempotent, the operator stays symmetric
-    # (G12, G13, G23 are shared by both of their uses), and it differs from
-    # the FP64 operator by at most the storage rounding of G and B
+def _half_grid_neighbours(y):
+    """The two IEEE half grid points around each |y| (y below 65504), built
+    from the format's definition: spacing 2^(e-10) in the binade [2^e, 2^(e+1)),
+    2^-24 below 2^-14."""
+    a = np.abs(y)
+    _, x = np.frexp(a)
+    spacing = np.ldexp(1.0, np.maximum(x - 11, -24))
+    lo = np.floor(a / spacing) * spacing
+    return lo, lo + spacing, spacing
+
+
+def test_f16_scaled_storage_rounds_to_nearest_half():
+    # the split operator's G and B storage: per element a power-of-two scale
+    # that puts the largest magnitude in [2^14, 2^15), then round to nearest
+    # half (ties to even) straight from float64.  Checked against the two
+    # neighbouring grid points of every value (brute force over the format),
+    # including double-rounding cases that a float32 detour would get wrong
+    from oracle import mixed
+    rng = np.random.default_rng(11)
+    a = rng.standard_normal((5, 3, 40)) * np.logspace(-6, 2, 5)[:, None, None]
+    a[1, 0, 0] = 0.0
+    a[2, 1, :3] = [1e-12, -3e-13, 2e-9]           # below the element's half normal range
+    a[4] = 0.0                                    # an element of zeros
+    k = mixed.f16_scale_exponents(a, 0)
+    for e in range(5):
+        m = np.max(np.abs(a[e]))
+        if m == 0:
+            assert k[e] == 0
+        else:
+            assert 2.0 ** 14 <= m / 2.0 ** k[e] < 2.0 ** 15
+    st = mixed.f16_scaled_storage(a, 0)
+    y = a / 2.0 ** k[:, None, None]
+    ys = st / 2.0 ** k[:, None, None]
+    lo, hi, sp = _half_grid_neighbours(y)
+    ay = np.abs(y)
+    near = np.where(ay - lo < hi - ay, lo, np.where(ay - lo > hi - ay, hi,
+                    np.where(np.mod(lo / sp, 2) == 0, lo, hi)))   # ties to the even significand
+    assert np.array_equal(np.abs(ys), near)
+    assert np.all(np.sign(ys) * np.sign(y) >= 0)
+    # double rounding: 1 + 2^-11 + 2^-40 must go up; 1 + 2^-11 is a tie to 1
+    b = np.array([[1 + 2.0 ** -11 + 2.0 ** -40, 1 + 2.0 ** -11, 2.0 ** 14]])
+    sb = mixed.f16_scaled_storage(b, 0) / 2.0 ** mixed.f16_scale_exponents(b, 0)[0]
+    assert np.array_equal(sb, [[1 + 2.0 ** -10, 1.0, 2.0 ** 14]])
+    # relative error of a normal value: at most 2^-11
+    normal = ay >= 2.0 ** -14
+    assert np.all(np.abs(ys - y)[normal] <= 2.0 ** -11 * ay[normal])
+
+
+def test_f16_storage_reference_operator():
+    # the split-BF16 operator's reference: the exact operator with G and B in
+    # the scaled half storage.  The operator stays symmetric and differs from
+    # the FP64 one by at most the storage rounding (2^-11 relative, plus a
+    # 2^-39-of-the-largest floor for values below the half normal range)
     from oracle import mixed
     m = _mesh(wl.deformed_cube(2, 7, amp=0.2))
-    Gb = mixed.bf16_storage(m.G)
-    assert np.array_equal(mixed.bf16_storage(Gb), Gb)
-    assert np.all(np.abs(Gb - m.G) <= 2.0 ** -8 * np.abs(m.G) + 1e-37)   # float32 underflow of ~0 entries
+    Gh = mixed.f16_scaled_storage(m.G, 1)
+    Bh = mixed.f16_scaled_storage(m.B, 0)
+    gmax = np.max(np.abs(m.G), axis=(0, 2, 3, 4))[None, :, None, None, None]
+    assert np.all(np.abs(Gh - m.G) <= 2.0 ** -11 * np.abs(m.G) + 2.0 ** -39 * gmax)
+    assert np.all(np.abs(Bh - m.B) <= 2.0 ** -11 * m.B)
     rng = np.random.default_rng(3)
     u, v = rng.standard_normal(m.shape), rng.standard_normal(m.shape)
     au = mixed.ax_bf16_split_reference(m, u, 1.0, 0.1)
     av = mixed.ax_bf16_split_reference(m, v, 1.0, 0.1)
+    assert abs(np.sum(v * au) - np.sum(u * av)) <= 1e-12 * np.sum(np.abs(v * au))
+    w64 = m.ax(u, 1.0, 0.1)
+    assert np.all(np.abs(au - w64) <= 2.0 ** -11 * m.ax_abs_bound(u, 1.0, 0.1) + 1e-30)
+    assert np.linalg.norm(au - w64) > 0.0
+
+
+def test_bf16_storage_reference_operator():
+    # the exact operator with G and B rounded to BF16 (the plain BF16
+    # operator's storage).  Rounding is idempotent, the operator stays
+    # symmetric (G12, G13, G23 are shared by both of their uses), and it
+    # differs from the FP64 operator by at most the storage rounding
+    from oracle import mixed
+    m = _mesh(wl.deformed_cube(2, 7, amp=0.2))
+    Gb = mixed.bf16_storage(m.G)
+    Bb = mixed.bf16_storage(m.B)
+    assert np.array_equal(mixed.bf16_storage(Gb), Gb)
+    assert np.all(np.abs(Gb - m.G) <= 2.0 ** -8 * np.abs(m.G) + 1e-37)   # float32 underflow of ~0 entries
+    rng = np.random.default_rng(3)
+    u, v = rng.standard_normal(m.shape), rng.standard_normal(m.shape)
+    au = m.ax(u, 1.0, 0.1, G=Gb, B=Bb)
+    av = m.ax(v, 1.0, 0.1, G=Gb, B=Bb)
     assert abs(np.sum(v * au) - np.sum(u * av)) <= 1e-12 * np.sum(np.abs(v * au))
     w64 = m.ax(u, 1.0, 0.1)
     assert np.all(np.abs(au - w64) <= 2.0 ** -8 * m.ax_abs_bound(u, 1.0, 0.1) + 1e-30)
