@@ -3,18 +3,22 @@
 //
 // The gather-scatter is the only coupling between elements (paper section
 // 3.1) and the part the paper's section 4.2 identifies as the communication
-// bottleneck.  On one GPU it is an owner-computes pass over the unique nodes
-// that have more than one copy: one thread per such node enumerates its
-// copies in closed form (no index arrays are read), sums them in ascending
-// local index and writes the sum back to every copy.  Interior nodes (a
-// single copy) are never touched.
+// bottleneck.  Every global node receives the sum of its local copies, taken
+// in ascending local index, and the sum is written back to every copy; the
+// copies are found in closed form on the structured lattice (no index lists).
 //
-// Copies come from three small per-axis tables (no index lists, no integer
-// division per node).  Two passes that touch disjoint nodes: lattice rows
-// (gj, gk) lying on an element-face plane, walked node by node (contiguous
-// element rows per wave), and the x-face nodes of all other rows, one thread
-// per (x-face, row) so lanes m and m+1 hit the two ends of one 64-byte
-// element row.  Every element row is fetched once per pass.
+// Three implementations, chosen by shape:
+// * N = 7, nelx <= 64 (the default): one thread per element row segment in
+//   every y/z copy of a global lattice row, x-face partners by cross-lane
+//   shuffles (gs_seg_kernel);
+// * other orders with nelx (N+1) <= 1024: whole lattice rows per workgroup,
+//   x-face partners through LDS (gs_lattice_kernel);
+// * otherwise two passes over disjoint nodes: rows on an element-face plane,
+//   node by node, and the x-face nodes of all other rows (gs_rows_kernel,
+//   gs_xface_kernel), with copies from three small per-axis tables.
+// Every element row is fetched once per pass.
+#include <type_traits>
+
 #include "cg.hpp"
 #include "lattice.hpp"
 #include "sem_internal.hpp"
@@ -161,6 +165,169 @@ gs_lattice_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip
     }
 }
 
+// Segment pass (N = 7, the default where it applies): the 8 values i = 0..7
+// of one element row (j, k) form a 64-byte segment, and SPL lanes (1 or 2)
+// own one, VPL = 8 / SPL values each, in every y/z copy of a global lattice
+// row (gj, gk).  G lanes (a power of two >= SPL nelx) serve one row, lane
+// l = SPL ex + part owning points i = VPL part .. VPL part + VPL - 1 of
+// element ex.  Loads are 16-byte vectors, so a wavefront keeps 4 KB per copy
+// in flight, with neither LDS nor a barrier.  The x-face node between
+// elements ex and ex+1 (gi = (ex+1) N) is summed by the lane holding i = N
+// of ex from its own values and the next lane's i = 0 values (cross-lane
+// shuffles), in ascending local index: copies in (z, y) order, and within a
+// copy the lower element first (the partner's, across the periodic wrap).
+// The lane holding i = 0 of ex+1 takes that sum by one more shuffle.
+// Interior points sum their y/z copies; a node with a single copy keeps its
+// value.  Every segment is written back whole.  Needs sorted axis tables (no
+// periodic single-element axis) and SPL nelx <= 64.
+template <typename T, int MASK, int G, int SPL>
+__global__ void __launch_bounds__(256)
+gs_seg_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    constexpr int NP = 8, N = 7, VPL = NP / SPL;
+    typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type V;   // 16 bytes
+    constexpr int PV = 16 / (int)sizeof(T), NV = VPL / PV;
+    static_assert(NV >= 1 && VPL % PV == 0, "a lane's values are whole 16-byte vectors");
+    const int lane = (int)threadIdx.x & (G - 1);
+    const int row = (int)((blockIdx.x * blockDim.x + threadIdx.x) / G);
+    const int nelx = L.nelx, ny = (int)L.ny, nx = (int)L.nx, P = (int)L.P, nl = SPL * nelx;
+    const bool active = lane < nl && row < (int)(L.ny * L.nz);
+    const int ex = lane / SPL, i0 = (lane % SPL) * VPL;
+    const bool has_left = i0 == 0, has_right = i0 + VPL == NP;   // holds i = 0 / i = N
+    const int gj = active ? row % ny : 0, gk = active ? row / ny : 0;
+    // copies in y and z computed in closed form (element * 8 + local), so
+    // the segment loads wait on no table load
+    int Y[2], Z[2];
+    const int cy = active ? axis_copies_t<NP>(gj, L.nely, N, L.per[1] != 0, Y) : 0;
+    const int cz = active ? axis_copies_t<NP>(gk, L.nelz, N, L.per[2] != 0, Z) : 0;
+    const int n = cy * cz;
+    const bool myz = MASK && (axis_dirichlet(L, 1, gj, L.nely) || axis_dirichlet(L, 2, gk, L.nelz));
+    T v[4][VPL];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int m = 0; m < VPL; ++m) v[q][m] = T(0);   // absent copies (never summed)
+    int base[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = q >> 1, b = q & 1;
+        base[q] = -1;
+        if (c < cz && b < cy) {
+            const int e = ex + nelx * ((Y[b] >> 3) + L.nely * (Z[c] >> 3));
+            base[q] = e * P + NP * ((Y[b] & 7) + NP * (Z[c] & 7)) + i0;
+            const V *src = (const V *)(u + base[q]);
+#pragma unroll
+            for (int h = 0; h < NV; ++h) {
+                const V x = src[h];
+                const T *xs = (const T *)&x;
+#pragma unroll
+                for (int m = 0; m < PV; ++m) v[q][h * PV + m] = xs[m];
+            }
+        }
+    }
+    // the element's two end nodes along x: gi = (ex+1) N (wrapped) and ex N
+    int giR = ex * N + N;
+    if (giR >= nx) giR -= nx;
+    int XR[2], XL[2];
+    const int cxR = axis_copies_t<NP>(active ? giR : 0, nelx, N, L.per[0] != 0, XR);
+    const int cxL = axis_copies_t<NP>(active ? ex * N : 0, nelx, N, L.per[0] != 0, XL);
+    const bool mR = MASK && (myz || axis_dirichlet(L, 0, giR, nelx));
+    const bool mL = MASK && (myz || axis_dirichlet(L, 0, ex * N, nelx));
+    // the next lane's first values (i = 0 of element ex+1; lane 0 across the wrap)
+    const int srcR = lane + 1 == nl ? 0 : lane + 1, srcL = lane == 0 ? nl - 1 : lane - 1;
+    T pv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pv[q] = __shfl(v[q][0], srcR, G);
+    // node gi = (ex+1) N, on the lane holding i = N: masked, shared with the
+    // next element, or its own copies only
+    T sR = v[0][VPL - 1];
+    if (mR) {
+        sR = T(0);
+    } else if (cxR == 2) {
+        const bool pfirst = (XR[0] >> 3) != ex;   // the neighbour holds the lower element
+        sR = T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if ((q >> 1) < cz && (q & 1) < cy) {
+                if (pfirst) {
+                    sR += pv[q];
+                    sR += v[q][VPL - 1];
+                } else {
+                    sR += v[q][VPL - 1];
+                    sR += pv[q];
+                }
+            }
+    } else if (n > 1) {
+        sR = T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if ((q >> 1) < cz && (q & 1) < cy) sR += v[q][VPL - 1];
+    }
+    const T fromL = __shfl(sR, srcL, G);
+    if (!active) return;
+    T out[VPL];
+#pragma unroll
+    for (int m = 0; m < VPL; ++m) {
+        const bool left = has_left && m == 0, right = has_right && m == VPL - 1;
+        if (right) {
+            out[m] = sR;
+        } else if (left && cxL == 2) {
+            out[m] = fromL;   // the previous element's sum for the shared node
+        } else if (left ? mL : (MASK && myz)) {
+            out[m] = T(0);
+        } else if (n > 1) {
+            T s = T(0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if ((q >> 1) < cz && (q & 1) < cy) s += v[q][m];
+            out[m] = s;
+        } else {
+            out[m] = v[0][m];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (base[q] >= 0) {
+            V *dst = (V *)(u + base[q]);
+#pragma unroll
+            for (int h = 0; h < NV; ++h) {
+                V x;
+                T *xs = (T *)&x;
+#pragma unroll
+                for (int m = 0; m < PV; ++m) xs[m] = out[h * PV + m];
+                dst[h] = x;
+            }
+        }
+}
+
+template <typename T, int MASK, int SPL>
+hipError_t launch_seg_spl(const Lattice &L, T *u, hipStream_t s, const int32_t *skip)
+{
+    const int64_t rows = L.ny * L.nz;
+    int g = 4;
+    while (g < SPL * L.nelx) g *= 2;
+    const unsigned rpb = 256 / g;
+    const dim3 grid((unsigned)((rows + rpb - 1) / rpb)), block(256);
+    switch (g) {
+    case 4: hipLaunchKernelGGL((gs_seg_kernel<T, MASK, 4, SPL>), grid, block, 0, s, u, L, skip); break;
+    case 8: hipLaunchKernelGGL((gs_seg_kernel<T, MASK, 8, SPL>), grid, block, 0, s, u, L, skip); break;
+    case 16: hipLaunchKernelGGL((gs_seg_kernel<T, MASK, 16, SPL>), grid, block, 0, s, u, L, skip); break;
+    case 32: hipLaunchKernelGGL((gs_seg_kernel<T, MASK, 32, SPL>), grid, block, 0, s, u, L, skip); break;
+    case 64: hipLaunchKernelGGL((gs_seg_kernel<T, MASK, 64, SPL>), grid, block, 0, s, u, L, skip); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// two lanes per segment while a row fits one wavefront that way (fewer
+// registers per lane, more wavefronts in flight), else one
+template <typename T, int MASK>
+hipError_t launch_seg(const Lattice &L, T *u, hipStream_t s, const int32_t *skip)
+{
+    return 2 * L.nelx <= 64 ? launch_seg_spl<T, MASK, 2>(L, u, s, skip) : launch_seg_spl<T, MASK, 1>(L, u, s, skip);
+}
+
 __global__ void scale_by_B_kernel(const double *__restrict__ f, const double *__restrict__ Bm,
                                   double *__restrict__ b, int64_t nl)
 {
@@ -222,10 +389,13 @@ hipError_t dssum_impl(const Mesh &m, T *u, int apply_mask, hipStream_t s, const 
     const int64_t rows = L.ny * L.nz;
     if (rows == 0) return hipSuccess;
     const int nxl = L.nelx * L.NP;
+    if (!L.unsorted && L.NP == 8 && L.nelx <= 64)
+        return apply_mask ? launch_seg<T, 1>(L, u, s, skip) : launch_seg<T, 0>(L, u, s, skip);
     if (!L.unsorted && nxl <= 1024) {
         // one workgroup of whole wavefronts per RPT rows, each thread taking
         // the same x position in every row with all its loads issued first
-        // (32^3 case: 79 us with one row, 69 us with two or three, 78 with four)
+        // (measured at N = 7 on the 32^3 case, before the segment pass took
+        // over there: 79 us with one row, 69 us with two or three, 78 with four)
         constexpr int RPT = 2;
         const int nxp = (nxl + 63) / 64 * 64;
         const dim3 block((unsigned)nxp), grid((unsigned)((rows + RPT - 1) / RPT));
