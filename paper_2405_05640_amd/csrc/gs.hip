@@ -8,9 +8,10 @@
 // copies are found in closed form on the structured lattice (no index lists).
 //
 // Three implementations, chosen by shape:
-// * N = 7, nelx <= 64 (the default): one thread per element row segment in
-//   every y/z copy of a global lattice row, x-face partners by cross-lane
-//   shuffles (gs_seg_kernel);
+// * N = 7, nelx <= 256 (the default): one or two lanes per element row
+//   segment in every y/z copy of a global lattice row, x-face partners by
+//   cross-lane shuffles or, for rows wider than a wavefront, LDS
+//   (gs_seg_kernel);
 // * other orders with nelx (N+1) <= 1024: whole lattice rows per workgroup,
 //   x-face partners through LDS (gs_lattice_kernel);
 // * otherwise two passes over disjoint nodes: rows on an element-face plane,
@@ -168,10 +169,11 @@ gs_lattice_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip
 // Segment pass (N = 7, the default where it applies): the 8 values i = 0..7
 // of one element row (j, k) form a 64-byte segment, and SPL lanes (1 or 2)
 // own one, VPL = 8 / SPL values each, in every y/z copy of a global lattice
-// row (gj, gk).  G lanes (a power of two >= SPL nelx) serve one row, lane
-// l = SPL ex + part owning points i = VPL part .. VPL part + VPL - 1 of
-// element ex.  Loads are 16-byte vectors, so a wavefront keeps 4 KB per copy
-// in flight, with neither LDS nor a barrier.  The x-face node between
+// row (gj, gk).  G lanes (a power of two >= SPL nelx, at most 256) serve
+// one row, lane l = SPL ex + part owning points i = VPL part .. VPL part +
+// VPL - 1 of element ex.  Loads are 16-byte vectors, so a wavefront keeps
+// 4 KB per copy in flight; rows that fit a wavefront need neither LDS nor a
+// barrier (wider rows exchange the x-face values through LDS).  The x-face node between
 // elements ex and ex+1 (gi = (ex+1) N) is summed by the lane holding i = N
 // of ex from its own values and the next lane's i = 0 values (cross-lane
 // shuffles), in ascending local index: copies in (z, y) order, and within a
@@ -179,7 +181,7 @@ gs_lattice_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip
 // The lane holding i = 0 of ex+1 takes that sum by one more shuffle.
 // Interior points sum their y/z copies; a node with a single copy keeps its
 // value.  Every segment is written back whole.  Needs sorted axis tables (no
-// periodic single-element axis) and SPL nelx <= 64.
+// periodic single-element axis) and SPL nelx <= 256.
 template <typename T, int MASK, int G, int SPL>
 __global__ void __launch_bounds__(256)
 gs_seg_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip)
@@ -235,10 +237,22 @@ gs_seg_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip)
     const bool mR = MASK && (myz || axis_dirichlet(L, 0, giR, nelx));
     const bool mL = MASK && (myz || axis_dirichlet(L, 0, ex * N, nelx));
     // the next lane's first values (i = 0 of element ex+1; lane 0 across the wrap)
-    const int srcR = lane + 1 == nl ? 0 : lane + 1, srcL = lane == 0 ? nl - 1 : lane - 1;
+    const int srcR = lane + 1 >= nl ? 0 : lane + 1, srcL = lane == 0 ? nl - 1 : lane - 1;   // both < G
+    // rows wider than a wavefront exchange through LDS (two barriers)
+    constexpr bool kLds = G > 64;
+    __shared__ T xv[kLds ? 256 : 1][4], xs[kLds ? 256 : 1];
+    const int rb = (int)threadIdx.x - lane;   // first thread of this row
     T pv[4];
+    if constexpr (kLds) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) pv[q] = __shfl(v[q][0], srcR, G);
+        for (int q = 0; q < 4; ++q) xv[threadIdx.x][q] = v[q][0];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pv[q] = xv[rb + srcR][q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pv[q] = __shfl(v[q][0], srcR, G);
+    }
     // node gi = (ex+1) N, on the lane holding i = N: masked, shared with the
     // next element, or its own copies only
     T sR = v[0][VPL - 1];
@@ -264,7 +278,14 @@ gs_seg_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip)
         for (int q = 0; q < 4; ++q)
             if ((q >> 1) < cz && (q & 1) < cy) sR += v[q][VPL - 1];
     }
-    const T fromL = __shfl(sR, srcL, G);
+    T fromL;
+    if constexpr (kLds) {
+        xs[threadIdx.x] = sR;
+        __syncthreads();
+        fromL = xs[rb + srcL];
+    } else {
+        fromL = __shfl(sR, srcL, G);
+    }
     if (!active) return;
     T out[VPL];
 #pragma unroll
@@ -315,17 +336,19 @@ hipError_t launch_seg_spl(const Lattice &L, T *u, hipStream_t s, const int32_t *
     case 16: hipLaunchKernelGGL((gs_seg_kernel<T, MASK, 16, SPL>), grid, block, 0, s, u, L, skip); break;
     case 32: hipLaunchKernelGGL((gs_seg_kernel<T, MASK, 32, SPL>), grid, block, 0, s, u, L, skip); break;
     case 64: hipLaunchKernelGGL((gs_seg_kernel<T, MASK, 64, SPL>), grid, block, 0, s, u, L, skip); break;
+    case 128: hipLaunchKernelGGL((gs_seg_kernel<T, MASK, 128, SPL>), grid, block, 0, s, u, L, skip); break;
+    case 256: hipLaunchKernelGGL((gs_seg_kernel<T, MASK, 256, SPL>), grid, block, 0, s, u, L, skip); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-// two lanes per segment while a row fits one wavefront that way (fewer
-// registers per lane, more wavefronts in flight), else one
+// two lanes per segment while a row fits a workgroup that way (fewer
+// registers per lane, more wavefronts in flight), else one (nelx <= 256)
 template <typename T, int MASK>
 hipError_t launch_seg(const Lattice &L, T *u, hipStream_t s, const int32_t *skip)
 {
-    return 2 * L.nelx <= 64 ? launch_seg_spl<T, MASK, 2>(L, u, s, skip) : launch_seg_spl<T, MASK, 1>(L, u, s, skip);
+    return 2 * L.nelx <= 256 ? launch_seg_spl<T, MASK, 2>(L, u, s, skip) : launch_seg_spl<T, MASK, 1>(L, u, s, skip);
 }
 
 __global__ void scale_by_B_kernel(const double *__restrict__ f, const double *__restrict__ Bm,
@@ -389,7 +412,7 @@ hipError_t dssum_impl(const Mesh &m, T *u, int apply_mask, hipStream_t s, const 
     const int64_t rows = L.ny * L.nz;
     if (rows == 0) return hipSuccess;
     const int nxl = L.nelx * L.NP;
-    if (!L.unsorted && L.NP == 8 && L.nelx <= 64)
+    if (!L.unsorted && L.NP == 8 && L.nelx <= 256)
         return apply_mask ? launch_seg<T, 1>(L, u, s, skip) : launch_seg<T, 0>(L, u, s, skip);
     if (!L.unsorted && nxl <= 1024) {
         // one workgroup of whole wavefronts per RPT rows, each thread taking

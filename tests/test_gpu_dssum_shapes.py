@@ -1,7 +1,8 @@
 """Gather-scatter parity over the mesh shapes that select its implementation
-(N = 7: two lanes per element-row segment while 2 nelx <= 64, one lane for
-nelx up to 64; otherwise the whole-row LDS pass, or the two table-driven
-passes when an axis is periodic with a single element).  FP64 is bit-exact
+(N = 7: two lanes per element-row segment while 2 nelx <= 256, one lane up
+to nelx = 256, with x-face values exchanged by shuffles while a row fits a
+wavefront and through LDS beyond; the table-driven passes when an axis is
+periodic with a single element or the row is longer).  FP64 is bit-exact
 against the oracle; FP32 is bit-exact against the same ascending-local-index
 sum taken in float32 (numpy's unbuffered ufunc.at adds in index order)."""
 import numpy as np
@@ -18,13 +19,16 @@ SHAPES = [
     wl.random_deformed_box(2, 2, 3, 7, seed=5, amp=0.2, periodic=(1, 1, 0),
                            dirichlet=0x30),                                        # two-element wraps
     wl.random_deformed_box(32, 1, 2, 7, seed=6, amp=0.2, periodic=(1, 0, 0)),      # 2 nelx = 64 exactly
-    wl.random_deformed_box(33, 2, 1, 7, seed=7, amp=0.2),                          # one lane per segment
+    wl.random_deformed_box(33, 2, 1, 7, seed=7, amp=0.2),                          # two wavefronts per row
     wl.random_deformed_box(64, 1, 2, 7, seed=8, amp=0.2, periodic=(1, 0, 1),
                            dirichlet=wl.DIRICHLET_Y_WALLS),                        # nelx = 64, periodic
-    wl.random_deformed_box(65, 1, 1, 7, seed=9, amp=0.2),                          # whole-row LDS pass
+    wl.random_deformed_box(65, 1, 1, 7, seed=9, amp=0.2),                          # two lanes, LDS exchange
+    wl.random_deformed_box(130, 1, 1, 7, seed=10, amp=0.2, periodic=(1, 0, 0)),    # one lane, LDS exchange
+    wl.random_deformed_box(257, 1, 1, 7, seed=11, amp=0.2),                        # row too long: table passes
     wl.box(2, 1, 3, 7, periodic=(0, 1, 0)),                                        # table-driven passes
 ]
-IDS = ["nelx1", "wrap2", "nelx32_per", "nelx33", "nelx64_per", "nelx65", "per_single_y"]
+IDS = ["nelx1", "wrap2", "nelx32_per", "nelx33", "nelx64_per", "nelx65", "nelx130_per", "nelx257",
+       "per_single_y"]
 
 
 @pytest.fixture(scope="module", params=list(range(len(SHAPES))), ids=IDS)
