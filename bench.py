@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 B_ALG_HELMHOLTZ_F64 = 72.0
+B_ALG_DSSUM_F64 = 16.0      # every local value read once and written once
 
 
 def parse():
@@ -352,6 +353,7 @@ def main():
     gs_mean = statistics.mean(gs_ms)
     value = mesh.n_local * args.steps / wall / 1e9
     achieved = B_ALG_HELMHOLTZ_F64 * mesh.n_local / (ax_mean * 1e-3) / 1e9
+    gs_achieved = B_ALG_DSSUM_F64 * mesh.n_local / (gs_mean * 1e-3) / 1e9
     print("Ax %.1f us (%.0f GB/s alg), dssum %.1f us, step %.1f us" %
           (ax_mean * 1e3, achieved, gs_mean * 1e3, wall / args.steps * 1e6), flush=True)
     tr = traffic_record(os.path.join(ROOT, "paper_2405_05640_amd", "csrc", "ax.hip"))
@@ -379,8 +381,12 @@ def main():
                      "alg_bytes_per_point": B_ALG_HELMHOLTZ_F64,
                      "mean_launch_us": round(ax_mean * 1e3, 2)},
         "dssum_mean_us": round(gs_mean * 1e3, 2),
-        "ax_dssum_hbm_frac": round(B_ALG_HELMHOLTZ_F64 * mesh.n_local / (wall / args.steps) / 1e9
-                                   / PEAK_HBM_GBS, 4),
+        "dssum_roofline": {"bound": "hbm", "achieved": round(gs_achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": round(gs_achieved / PEAK_HBM_GBS, 4),
+                           "kernel": "gs_seg_kernel<double,MASK,G,SPL> (sem_dssum)",
+                           "alg_bytes_per_point": B_ALG_DSSUM_F64, "mean_launch_us": round(gs_mean * 1e3, 2)},
+        "ax_dssum_hbm_frac": round((B_ALG_HELMHOLTZ_F64 + B_ALG_DSSUM_F64) * mesh.n_local / (wall / args.steps)
+                                   / 1e9 / PEAK_HBM_GBS, 4),
     }
 
     if not args.no_solve:
