@@ -181,13 +181,25 @@ ax_pt_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G
     if (HELM) bv = ldnt(&Bm[e * P3 + t]);
     if (t < P2) sD[t] = Dg[t];
     su[t] = uv;
+    // With P2 = 64 a wavefront is one k-plane, so row k and column k of D are
+    // wave-uniform: they come through scalar loads into scalar registers and
+    // the t-direction contractions read only their u / flux operand from LDS.
+    T Dk[NP], DkT[NP];
+    if constexpr (P2 == 64) {
+        const int kw = __builtin_amdgcn_readfirstlane(k);
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+            Dk[m] = Dg[kw * NP + m];
+            DkT[m] = Dg[m * NP + kw];
+        }
+    }
     __syncthreads();
     T ur = T(0), us = T(0), ut = T(0);
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
         ur += sD[i * NP + m] * su[k * P2 + j * NP + m];
         us += sD[j * NP + m] * su[k * P2 + m * NP + i];
-        ut += sD[k * NP + m] * su[m * P2 + j * NP + i];
+        ut += (P2 == 64 ? Dk[m] : sD[k * NP + m]) * su[m * P2 + j * NP + i];
     }
     sr[t] = g0 * ur + g1 * us + g2 * ut;
     ss[t] = g1 * ur + g3 * us + g4 * ut;
@@ -197,7 +209,7 @@ ax_pt_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ G
 #pragma unroll
     for (int m = 0; m < NP; ++m)
         acc += sD[m * NP + i] * sr[k * P2 + j * NP + m] + sD[m * NP + j] * ss[k * P2 + m * NP + i] +
-               sD[m * NP + k] * st[m * P2 + j * NP + i];
+               (P2 == 64 ? DkT[m] : sD[m * NP + k]) * st[m * P2 + j * NP + i];
     T v = h1 * acc;
     if (HELM) v += h2 * bv * uv;
     w[GATHER ? (int64_t)rows_index32(L, ex, ey, ez, i, j, k) : e * P3 + t] = v;
