@@ -282,6 +282,19 @@ ax_ptn_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ 
     if (t < P2) sD[t] = Dg[t];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) su[q * H + t] = uv[q];
+    // k0 is the wavefront index, so the rows and columns k of D that this
+    // thread's points use are wave-uniform: scalar loads, scalar registers
+    T Dk[PPT][NP], DkT[PPT][NP];
+    {
+        const int k0w = __builtin_amdgcn_readfirstlane(k0);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+#pragma unroll
+            for (int m = 0; m < NP; ++m) {
+                Dk[q][m] = Dg[(k0w + q * KS) * NP + m];
+                DkT[q][m] = Dg[m * NP + k0w + q * KS];
+            }
+    }
     __syncthreads();
     T pen[NP];   // the (i, j) pencil of u, shared by this thread's points
 #pragma unroll
@@ -294,7 +307,7 @@ ax_ptn_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ 
         for (int m = 0; m < NP; ++m) {
             ur += sD[i * NP + m] * su[k * P2 + j * NP + m];
             us += sD[j * NP + m] * su[k * P2 + m * NP + i];
-            ut += sD[k * NP + m] * pen[m];
+            ut += Dk[q][m] * pen[m];
         }
         const int tq = q * H + t;
         sr[tq] = g[q][0] * ur + g[q][1] * us + g[q][2] * ut;
@@ -312,7 +325,7 @@ ax_ptn_kernel(const T *__restrict__ u, T *__restrict__ w, const T *__restrict__ 
 #pragma unroll
         for (int m = 0; m < NP; ++m)
             acc += sD[m * NP + i] * sr[k * P2 + j * NP + m] + sD[m * NP + j] * ss[k * P2 + m * NP + i] +
-                   sD[m * NP + k] * pen[m];
+                   DkT[q][m] * pen[m];
         T v = h1 * acc;
         if (HELM) v += h2 * bv[q] * uv[q];
         w[GATHER ? (int64_t)rows_index32(L, ex, ey, ez, i, j, k) : e * P3 + q * H + t] = v;
