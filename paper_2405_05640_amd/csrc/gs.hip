@@ -172,13 +172,14 @@ gs_lattice_kernel(T *__restrict__ u, Lattice L, const int32_t *__restrict__ skip
 // row (gj, gk).  G lanes (a power of two >= SPL nelx, at most 256) serve
 // one row, lane l = SPL ex + part owning points i = VPL part .. VPL part +
 // VPL - 1 of element ex.  Loads are 16-byte vectors, so a wavefront keeps
-// 4 KB per copy in flight; rows that fit a wavefront need neither LDS nor a
-// barrier (wider rows exchange the x-face values through LDS).  The x-face node between
-// elements ex and ex+1 (gi = (ex+1) N) is summed by the lane holding i = N
-// of ex from its own values and the next lane's i = 0 values (cross-lane
-// shuffles), in ascending local index: copies in (z, y) order, and within a
-// copy the lower element first (the partner's, across the periodic wrap).
-// The lane holding i = 0 of ex+1 takes that sum by one more shuffle.
+// 4 KB per copy in flight.  The x-face node between elements ex and ex+1
+// (gi = (ex+1) N) is summed by the lane holding i = N of ex from its own
+// values and the next lane's i = 0 values, in ascending local index: copies
+// in (z, y) order, and within a copy the lower element first (the
+// partner's, across the periodic wrap).  The lane holding i = 0 of ex+1
+// then takes that sum from its left neighbour.  Rows that fit a wavefront
+// exchange these values by cross-lane shuffles (no LDS, no barrier); wider
+// rows exchange them through LDS, with two barriers.
 // Interior points sum their y/z copies; a node with a single copy keeps its
 // value.  Every segment is written back whole.  Needs sorted axis tables (no
 // periodic single-element axis) and SPL nelx <= 256.
