@@ -208,8 +208,22 @@ __device__ __forceinline__ void split8(const float (&v)[8], s16x8 &h, s16x8 &l)
     }
 }
 
+// The BF16 hi and lo tiles in LDS are padded: point p = i + 8 j + 64 k sits
+// at halfword p + 8 k, so each k-plane (72 halfwords) starts 4 banks after the
+// previous one, and a lo tile starts kHalfTile halfwords (16 banks mod 32)
+// after its hi tile.  The s- and t-direction operand reads of hi and lo then
+// fall in distinct banks, and rows stay 16-byte aligned.
+constexpr int kHalfTile = 608;   // 512 + 8 * 8 padding + 32 bank offset
+__device__ __forceinline__ int hpad(int p) { return p + ((p >> 6) << 3); }
+// FP32 tiles (derivatives, accumulator): 4 floats of padding per 32, which
+// spreads the scattered MFMA result writes over more banks while each 8-value
+// row stays contiguous and 16-byte aligned; a tile spans kFloatTile floats.
+constexpr int kFloatTile = 608;
+__device__ __forceinline__ int fpad(int p) { return p + ((p >> 5) << 2); }
+
 // One directional contraction of a 512-point tile whose values were split
-// once into hi and lo BF16 arrays (LDS): four MFMAs, 16 lines each.
+// once into hi and lo BF16 tiles (LDS, padded as above): four MFMAs, 16
+// lines each.
 __device__ __forceinline__ void contract_split(int dir, const unsigned short *hi, const unsigned short *lo, float *dst,
                                                bf16x8 bop, bool acc)
 {
@@ -221,10 +235,10 @@ __device__ __forceinline__ void contract_split(int dir, const unsigned short *hi
         const int L = 16 * t + m;
         s16x8 a;
         if (dir == 0) {
-            a = *(const s16x8 *)&src[L * 8];
+            a = *(const s16x8 *)&src[hpad(L * 8)];
         } else {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[q] = (short)src[line_point(dir, L, q)];
+            for (int q = 0; q < 8; ++q) a[q] = (short)src[hpad(line_point(dir, L, q))];
         }
         if (g == 3) a = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
         f4 c = {0.f, 0.f, 0.f, 0.f};
@@ -233,7 +247,7 @@ __device__ __forceinline__ void contract_split(int dir, const unsigned short *hi
         if (n < 8) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int p = line_point(dir, 16 * t + 4 * g + q, n);
+                const int p = fpad(line_point(dir, 16 * t + 4 * g + q, n));
                 if (acc)
                     dst[p] += c[q];
                 else
@@ -253,13 +267,15 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
     // G and B are half-precision values of one element, each array with its
     // own power-of-two scale; the scales multiply h1 and h2 (exact).
     if (skip && *skip) return;
-    // LDS: u as hi | lo BF16 (later the FP32 accumulator), the FP32
-    // derivatives (later the fluxes as hi | lo BF16), D hi | lo
-    __shared__ __attribute__((aligned(16))) unsigned short su[2][512];
-    __shared__ __attribute__((aligned(16))) float sd[3][512];
+    // LDS: u as padded hi | lo BF16 tiles (later the FP32 accumulator), the
+    // FP32 derivatives (later the fluxes as padded hi | lo BF16 tiles), D hi | lo
+    __shared__ __attribute__((aligned(16))) unsigned short suh[2 * kHalfTile];
+    __shared__ __attribute__((aligned(16))) float sd[3 * kFloatTile];   // 3 FP32 tiles, or 6 BF16 tiles
     __shared__ unsigned short sD[128];
-    float *acc = (float *)&su[0][0];
-    unsigned short *sf = (unsigned short *)&sd[0][0];   // [3][2][512]
+    static_assert(2 * kHalfTile * 2 >= kFloatTile * 4, "the accumulator fits the u tiles");
+    static_assert(3 * kFloatTile * 4 >= 6 * kHalfTile * 2, "the flux tiles fit the derivative tiles");
+    float *acc = (float *)&suh[0];
+    unsigned short *sf = (unsigned short *)&sd[0];   // 6 tiles: flux a hi, lo at (2 a), (2 a + 1) kHalfTile
     const int lane = threadIdx.x;
     const int64_t e = xcd_block();
     int ex = 0, ey = 0, ez = 0;   // element coordinates (gather mode)
@@ -286,8 +302,8 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
     {
         s16x8 h, l;
         split8(uu, h, l);
-        *(s16x8 *)&su[0][8 * lane] = h;
-        *(s16x8 *)&su[1][8 * lane] = l;
+        *(s16x8 *)&suh[hpad(8 * lane)] = h;
+        *(s16x8 *)&suh[kHalfTile + hpad(8 * lane)] = l;
     }
     __syncthreads();
     // B operands (lane: column n, K rows 8 g + q)
@@ -302,16 +318,16 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
         }
     }
     const bf16x8 bF = __builtin_bit_cast(bf16x8, bFs), bT = __builtin_bit_cast(bf16x8, bTs);
-    contract_split(0, su[0], su[1], sd[0], bF, false);
-    contract_split(1, su[0], su[1], sd[1], bF, false);
-    contract_split(2, su[0], su[1], sd[2], bF, false);
+    contract_split(0, suh, suh + kHalfTile, sd, bF, false);
+    contract_split(1, suh, suh + kHalfTile, sd + kFloatTile, bF, false);
+    contract_split(2, suh, suh + kHalfTile, sd + 2 * kFloatTile, bF, false);
     __syncthreads();
     // G-combination in FP32; the fluxes are split once into hi | lo BF16
     float fl[3][8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int p = 8 * lane + q;
-        const float ur = sd[0][p], us = sd[1][p], ut = sd[2][p];
+        const float ur = sd[fpad(p)], us = sd[kFloatTile + fpad(p)], ut = sd[2 * kFloatTile + fpad(p)];
         const float g11 = h_at(gq[0], q), g12 = h_at(gq[1], q), g13 = h_at(gq[2], q);
         const float g22 = h_at(gq[3], q), g23 = h_at(gq[4], q), g33 = h_at(gq[5], q);
         fl[0][q] = g11 * ur + g12 * us + g13 * ut;
@@ -323,23 +339,23 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
     for (int a = 0; a < 3; ++a) {
         s16x8 h, l;
         split8(fl[a], h, l);
-        *(s16x8 *)&sf[(2 * a) * 512 + 8 * lane] = h;
-        *(s16x8 *)&sf[(2 * a + 1) * 512 + 8 * lane] = l;
+        *(s16x8 *)&sf[(2 * a) * kHalfTile + hpad(8 * lane)] = h;
+        *(s16x8 *)&sf[(2 * a + 1) * kHalfTile + hpad(8 * lane)] = l;
     }
     __syncthreads();
     // transposed contractions accumulated r, s, t (u itself is in registers)
-    contract_split(0, sf + 0 * 512, sf + 1 * 512, acc, bT, false);
+    contract_split(0, sf + 0 * kHalfTile, sf + 1 * kHalfTile, acc, bT, false);
     __syncthreads();
-    contract_split(1, sf + 2 * 512, sf + 3 * 512, acc, bT, true);
+    contract_split(1, sf + 2 * kHalfTile, sf + 3 * kHalfTile, acc, bT, true);
     __syncthreads();
-    contract_split(2, sf + 4 * 512, sf + 5 * 512, acc, bT, true);
+    contract_split(2, sf + 4 * kHalfTile, sf + 5 * kHalfTile, acc, bT, true);
     __syncthreads();
     const float h1s = h1 * sc.x, h2s = h2 * sc.y;
     double dot = 0.0;
     float out[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        float v = h1s * acc[8 * lane + q];
+        float v = h1s * acc[fpad(8 * lane + q)];
         if (HELM) v += h2s * h_at(bq, q) * uu[q];
         out[q] = v;
         if (partial) dot += (double)uu[q] * (double)v;
