@@ -292,8 +292,18 @@ ax_bf16s_kernel(const float *__restrict__ uin, float *__restrict__ w, const unsi
     // lane owns the 8-point row p = 8 lane + q: i = q, j = lane & 7, k = lane >> 3
     float uu[8];
     if (GATHER) {
+        // gathered in point order (lane = i + 8 j within k-plane q, so a load
+        // instruction spans 8 runs of 8 consecutive global nodes), then
+        // turned into rows through the (still unused) derivative tile
+        float ug[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) uu[q] = uin[gather_index32(L, ex, ey, ez, q, lane & 7, lane >> 3)];
+        for (int q = 0; q < 8; ++q) ug[q] = uin[gather_index32(L, ex, ey, ez, lane & 7, lane >> 3, q)];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sd[fpad(64 * q + lane)] = ug[q];
+        __syncthreads();
+        const float4 r0 = *(const float4 *)&sd[fpad(8 * lane)], r1 = *(const float4 *)&sd[fpad(8 * lane) + 4];
+        uu[0] = r0.x; uu[1] = r0.y; uu[2] = r0.z; uu[3] = r0.w;
+        uu[4] = r1.x; uu[5] = r1.y; uu[6] = r1.z; uu[7] = r1.w;
     } else {
         const float4 v0 = ((const float4 *)(uin + e * 512))[2 * lane], v1 = ((const float4 *)(uin + e * 512))[2 * lane + 1];
         uu[0] = v0.x; uu[1] = v0.y; uu[2] = v0.z; uu[3] = v0.w;
