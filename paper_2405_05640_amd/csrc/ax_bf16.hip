@@ -112,12 +112,14 @@ ax_bf16_kernel(const void *__restrict__ uin, float *__restrict__ w, const unsign
     u32x4 bq = {0u, 0u, 0u, 0u};
     if (HELM) bq = __builtin_nontemporal_load((const u32x4 *)(Bm + e * 512) + lane);
     sD[lane] = Dbf[lane];
-    // u tile (BF16) into LDS: each lane 8 consecutive points
+    // u tile (BF16) into LDS; gathered in point order (lane = i + 8 j within
+    // k-plane q), so a load instruction spans 8 runs of 8 consecutive global
+    // nodes
     if (GATHER) {
         const float *ug = (const float *)uin;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int p = lane * 8 + q, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
+            const int p = 64 * q + lane, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
             su[p] = f2bf(ug[gather_index32(L, ex, ey, ez, i, j, k)]);
         }
     } else {
