@@ -44,7 +44,8 @@ typedef enum {
     SEM_ERR_INVALID_ARG = 1,   /* null pointer, bad size/dtype/order, inverted element */
     SEM_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
     SEM_ERR_HIP = 3,           /* a HIP runtime call failed */
-    SEM_ERR_NOT_CONVERGED = 4, /* max_iter reached; x holds the last iterate */
+    SEM_ERR_NOT_CONVERGED = 4, /* max_iter reached, or a refinement form's FP64 true residual
+                                  stopped decreasing; x holds the last iterate */
     SEM_ERR_BREAKDOWN = 5,     /* non-finite value or (p, S p) <= 0 in CG */
     SEM_ERR_UNSUPPORTED = 6    /* valid request the library does not provide */
 } sem_status;
@@ -145,7 +146,10 @@ sem_status sem_dot(const sem_mesh *mesh, const double *u, const double *v, doubl
 typedef enum {
     SEM_FORM_JACOBI_PCG = 0,     /* FP64 Jacobi-preconditioned CG */
     SEM_FORM_DC_FP32 = 1,        /* FP64 defect correction around FP32 Jacobi-PCG */
-    SEM_FORM_DC_BF16 = 2,        /* FP64 defect correction around BF16-operator PCG */
+    SEM_FORM_DC_BF16 = 2,        /* FP64 defect correction around FP32-vector PCG with the
+                                    split-BF16 matrix-core operator (SEM_BF16_SPLIT; the plain BF16
+                                    operator's rounding of u is too coarse for refinement to
+                                    contract on deformed meshes) */
     SEM_FORM_FCG_LEARNED = 3,    /* flexible CG with the learned smoother (opts.smoother),
                                     Jacobi-PCG fallback */
     SEM_FORM_FCG_INNER_FP32 = 4, /* FP64 flexible CG preconditioned by inner_iters steps of
@@ -234,6 +238,14 @@ sem_status sem_smoother_destroy(sem_smoother *sm);
 /* HOST float[n], n = SEM_SMOOTHER_PARAMS; set also resets the Adam state. */
 sem_status sem_smoother_set_weights(sem_smoother *sm, const float *host, size_t n);
 sem_status sem_smoother_get_weights(const sem_smoother *sm, float *host, size_t n);
+/* Checkpoint and resume of training: FP32 master weights, Adam's first and
+ * second moments (HOST float[n] each, n = SEM_SMOOTHER_PARAMS) and the number
+ * of Adam steps taken (which sets the bias corrections of the next step).
+ * Both synchronise the device. */
+sem_status sem_smoother_get_state(const sem_smoother *sm, float *weights, float *adam_m, float *adam_v, size_t n,
+                                  int32_t *step);
+sem_status sem_smoother_set_state(sem_smoother *sm, const float *weights, const float *adam_m, const float *adam_v,
+                                  size_t n, int32_t step);
 /* z = M(r) for a continuous, masked local r (device double [E][P]); fp32 != 0
  * runs the FP32 network, else the BF16 inference path.  Blocking on stream. */
 sem_status sem_smoother_apply(const sem_smoother *sm, const sem_mesh *mesh, double h1, double h2, int fp32,
@@ -263,8 +275,11 @@ sem_status sem_pcg_snapshots(const sem_mesh *mesh, const sem_solve_opts *opts, c
  * [nrhs][E][P] local fields (layout as sem_pcg_solve, one block per field);
  * reps: HOST array of nrhs reports.  Each field runs its own CG (own alpha,
  * beta, convergence) but every iteration streams the geometric factors
- * once for all fields.  Results equal nrhs separate sem_pcg_solve calls
- * bit for bit.  opts.form must be SEM_FORM_JACOBI_PCG; history is ignored. */
+ * once for all fields.  The batched operator kernel sums in another order
+ * than the single-field one, so each field matches a separate sem_pcg_solve
+ * to rounding (the same 1e-10 true residual, iteration counts within one),
+ * not bit for bit.  opts.form must be SEM_FORM_JACOBI_PCG; history is
+ * ignored. */
 sem_status sem_pcg_solve_batched(const sem_mesh *mesh, const sem_solve_opts *opts, int32_t nrhs, const double *b,
                                  double *x, void *workspace, size_t ws_bytes, sem_solve_report *reps, void *stream);
 sem_status sem_solve_workspace_bytes_batched(const sem_mesh *mesh, const sem_solve_opts *opts, int32_t nrhs,

@@ -21,6 +21,9 @@ out plainly:
       L = ||e - M(r)||_S^2 / ||e||_S^2,
   dL/dz = -2 S (e - M(r)) / ||e||_S^2 (z = M(r)), and
   dL/dc_l = dL/dz_{glo(l)} / mult_l on free nodes.
+* Training updates the weights with Adam (Kingma & Ba 2015): with gradient
+  g at step t (t = 1, 2, ...), m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+  W -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); moments start at 0.
 * Flexible CG (Notay 2000; Golub & Ye 1999): CG with z_k = M(r_k) and the
   Polak-Ribiere coefficient beta = (z_k, r_k - r_{k-1}) / (z_{k-1}, r_{k-1}).
   Fallback: on a non-finite value, (r, z) <= 0, or a residual reduction over
@@ -155,6 +158,41 @@ def loss_and_grad(mesh, net, r, e, dinv, h1=1.0, h2=0.0):
     g3[~live] = 0.0
     grads = net.backward(cache, g3)
     return L, grads
+
+
+class Adam:
+    """Adam optimiser state over a list of arrays (Kingma & Ba 2015,
+    Algorithm 1), in FP64: first and second moment estimates, bias-corrected
+    by 1 - beta^t at step t."""
+
+    def __init__(self, shapes, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.lr, self.b1, self.b2, self.eps = float(lr), float(beta1), float(beta2), float(eps)
+        self.m = [np.zeros(sh) for sh in shapes]
+        self.v = [np.zeros(sh) for sh in shapes]
+        self.t = 0
+
+    def step(self, params, grads):
+        """Returns the updated parameters (new arrays)."""
+        self.t += 1
+        out = []
+        for q, (W, g) in enumerate(zip(params, grads)):
+            g = np.asarray(g, dtype=np.float64)
+            self.m[q] = self.b1 * self.m[q] + (1.0 - self.b1) * g
+            self.v[q] = self.b2 * self.v[q] + (1.0 - self.b2) * g * g
+            m_hat = self.m[q] / (1.0 - self.b1 ** self.t)
+            v_hat = self.v[q] / (1.0 - self.b2 ** self.t)
+            out.append(np.asarray(W, dtype=np.float64) - self.lr * m_hat / (np.sqrt(v_hat) + self.eps))
+        return out
+
+
+def train_step(mesh, net, opt, e, dinv, h1=1.0, h2=0.0):
+    """One training step on the pair (S e, e): loss and gradient at the
+    current weights, then an Adam update of net.W in place.  Returns the loss
+    before the update."""
+    r = mesh.apply_S(e, h1, h2)
+    L, grads = loss_and_grad(mesh, net, r, e, dinv, h1, h2)
+    net.W = opt.step(net.W, grads)
+    return L
 
 
 def fcg(mesh, net, b, h1=1.0, h2=0.0, tol=1e-10, max_iter=20000, window=25, rho=None,

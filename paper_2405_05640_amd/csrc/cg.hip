@@ -308,16 +308,19 @@ __global__ void __launch_bounds__(kBS) restart_finalize(CgState *st, const doubl
 }
 
 // Residual replacement (reliable update) of a low-precision CG: r = inv_sigma
-// * r64 (the FP64 true residual), x = 0, and p = dinv r on the first call.
-// Later calls keep the search direction but swap its preconditioned-residual
-// part: the last direction update was p = dinv r_old + beta p_prev, so
+// * r64 (the FP64 true residual), x = 0.  mode = kReplaceFirst starts a run
+// (p = dinv r, iteration count and |b| reset); kReplaceRestart sets
+// p = dinv r but keeps the counters (used when the low-precision run had
+// converged, so its last direction update was never made); kReplaceKeep
+// keeps the search direction but swaps its preconditioned-residual part: the
+// last direction update was p = dinv r_old + beta p_prev, so
 // p + dinv (r_new - r_old) is the direction the new residual would have
 // produced; p_scale = sigma_old / sigma_new converts to the new units.
 // Partials (r, r), (r, dinv r).
 template <typename T>
 __global__ void __launch_bounds__(kBS)
 replace_kernel(const double *__restrict__ r64, T *__restrict__ x, T *__restrict__ r, T *__restrict__ p,
-               const T *__restrict__ dinv, double inv_sigma, double p_scale, int first, int64_t ng,
+               const T *__restrict__ dinv, double inv_sigma, double p_scale, int mode, int64_t ng,
                double *__restrict__ part)
 {
     double acc[2] = {0.0, 0.0};
@@ -327,7 +330,7 @@ replace_kernel(const double *__restrict__ r64, T *__restrict__ x, T *__restrict_
         const T rg = d == T(0) ? T(0) : (T)(inv_sigma * r64[g]);
         const T z = d * rg;
         x[g] = T(0);
-        if (first) {
+        if (mode != kReplaceKeep) {
             p[g] = z;
         } else {
             const double r_old = (double)r[g];
@@ -341,12 +344,12 @@ replace_kernel(const double *__restrict__ r64, T *__restrict__ x, T *__restrict_
 }
 
 __global__ void __launch_bounds__(kBS) replace_finalize(CgState *st, const double *__restrict__ part, int nb, double tol2,
-                                                         int first)
+                                                         int mode)
 {
     const double rr = block_sum(part, nb);
     const double rz = block_sum(part + nb, nb);
     if (threadIdx.x == 0) {
-        if (first) {
+        if (mode == kReplaceFirst) {
             st->it = 0;
             st->bb = rr;
         }
@@ -602,11 +605,11 @@ hipError_t cg_restart(const Mesh &m, const CgVecs<T> &v, CgState *st, hipStream_
 
 template <typename T>
 hipError_t cg_replace(const Mesh &m, const CgVecs<T> &v, const double *r64, CgState *st, double inv_sigma,
-                      double p_scale, int first, double tol2, hipStream_t s)
+                      double p_scale, int mode, double tol2, hipStream_t s)
 {
     const int nb = cg_blocks(m.ng);
-    L3((cg::replace_kernel<T>), m.ng) r64, v.x, v.r, v.p, v.dinv, inv_sigma, p_scale, first, m.ng, v.part_b);
-    hipLaunchKernelGGL(cg::replace_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb, tol2, first);
+    L3((cg::replace_kernel<T>), m.ng) r64, v.x, v.r, v.p, v.dinv, inv_sigma, p_scale, mode, m.ng, v.part_b);
+    hipLaunchKernelGGL(cg::replace_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nb, tol2, mode);
     return hipGetLastError();
 }
 

@@ -31,7 +31,9 @@ struct CgState {
     int32_t hist_len, learned, redo, fallback_at;
     int32_t nn_skip, inner_its, pad1, pad2;
 };
-// done: 0 running, 1 converged (recursive residual), 2 breakdown, 3 max_iter
+// done: 0 running, 1 converged (recursive residual), 2 breakdown, 3 max_iter,
+// kDoneStalled: a refinement loop's FP64 true residual stopped decreasing
+constexpr int32_t kDoneStalled = 4;
 // flexible CG: learned = 1 while the learned smoother is in use, redo = 1 when
 // the last smoother output was rejected (p restarts from dinv r),
 // fallback_at = iteration of the switch to Jacobi (-1: none), nn_skip =
@@ -69,11 +71,14 @@ template <typename T> hipError_t cg_restart(const Mesh &m, const CgVecs<T> &v, C
 hipError_t cg_alpha(const Mesh &m, const double *part_e, double *stage, CgState *st, hipStream_t s);
 // e = x - e on assembled vectors
 hipError_t cg_rsub(const Mesh &m, const double *x, double *e, hipStream_t s);
-// residual replacement of a low-precision run: r = inv_sigma * r64, x = 0,
-// p = first ? dinv r : p_scale * p; st: rr, rz, tol2 (first: it = 0, bb = rr)
+// residual replacement of a low-precision run: r = inv_sigma * r64, x = 0;
+// p = dinv r (kReplaceFirst, kReplaceRestart) or p_scale * p with its dinv r
+// part swapped (kReplaceKeep); st: rr, rz, tol2 (kReplaceFirst also it = 0,
+// bb = rr)
+enum { kReplaceKeep = 0, kReplaceFirst = 1, kReplaceRestart = 2 };
 template <typename T>
 hipError_t cg_replace(const Mesh &m, const CgVecs<T> &v, const double *r64, CgState *st, double inv_sigma,
-                      double p_scale, int first, double tol2, hipStream_t s);
+                      double p_scale, int mode, double tol2, hipStream_t s);
 // single-reduction (Chronopoulos-Gear) CG on FP64 vectors, u and sv extra
 // assembled vectors: init (x = 0 unless keep_x; partials of (r,u), (r,r)
 // reduced into v.stage), vector pass (partials reduced into v.stage), and the

@@ -356,12 +356,22 @@ sem_status check_pair(const Smoother &sm, const Mesh &m)
     return SEM_OK;
 }
 
-// dinv (assembled, 0 on Dirichlet nodes) into t.dinv, using t.w as scratch
-hipError_t make_dinv(const Mesh &m, double h1, double h2, const TrainBufs &t, hipStream_t s)
+// dinv (assembled, 0 on Dirichlet nodes) into t.dinv, using t.w as scratch,
+// unless the buffer already holds it for this mesh and h1, h2 (force = true
+// always rebuilds); records what the buffer now holds
+hipError_t make_dinv(const Smoother &sm, const Mesh &m, double h1, double h2, const TrainBufs &t, hipStream_t s,
+                     bool force)
 {
+    if (!force && sm.dinv_serial == m.serial && sm.dinv_h1 == h1 && sm.dinv_h2 == h2) return hipSuccess;
+    sm.dinv_serial = 0;
     hipError_t e = launch_diag(m, h1, h2, t.w, s);
     if (e != hipSuccess) return e;
-    return cg_dinv<double>(m, t.w, t.dinv, s);
+    e = cg_dinv<double>(m, t.w, t.dinv, s);
+    if (e != hipSuccess) return e;
+    sm.dinv_serial = m.serial;
+    sm.dinv_h1 = h1;
+    sm.dinv_h2 = h2;
+    return hipSuccess;
 }
 
 // loss L(e) and dL/dz in t.sd -> gz (in t.d), leaves |e|_S^2 and L in sm.scal
@@ -645,6 +655,7 @@ sem_status sem_smoother_set_weights(sem_smoother *sm, const float *host, size_t 
     SEM_HIP_TRY(hipMemset(s.m, 0, kParams * 4));
     SEM_HIP_TRY(hipMemset(s.v, 0, kParams * 4));
     s.step = 0;
+    s.dinv_serial = 0;
     SEM_HIP_TRY(nn_pack(s, nullptr));
     SEM_HIP_TRY(hipDeviceSynchronize());
     return SEM_OK;
@@ -658,6 +669,37 @@ sem_status sem_smoother_get_weights(const sem_smoother *sm, float *host, size_t 
     return SEM_OK;
 }
 
+sem_status sem_smoother_get_state(const sem_smoother *sm, float *weights, float *adam_m, float *adam_v, size_t n,
+                                  int32_t *step)
+{
+    if (!sm || !weights || !adam_m || !adam_v || !step) return fail(SEM_ERR_INVALID_ARG, "null argument");
+    if (n != (size_t)kParams) return fail(SEM_ERR_INVALID_ARG, "expected " + std::to_string(kParams) + " values");
+    const Smoother &s = sm->s;
+    SEM_HIP_TRY(hipDeviceSynchronize());
+    SEM_HIP_TRY(hipMemcpy(weights, s.W, kParams * 4, hipMemcpyDeviceToHost));
+    SEM_HIP_TRY(hipMemcpy(adam_m, s.m, kParams * 4, hipMemcpyDeviceToHost));
+    SEM_HIP_TRY(hipMemcpy(adam_v, s.v, kParams * 4, hipMemcpyDeviceToHost));
+    *step = s.step;
+    return SEM_OK;
+}
+
+sem_status sem_smoother_set_state(sem_smoother *sm, const float *weights, const float *adam_m, const float *adam_v,
+                                  size_t n, int32_t step)
+{
+    if (!sm || !weights || !adam_m || !adam_v) return fail(SEM_ERR_INVALID_ARG, "null argument");
+    if (n != (size_t)kParams) return fail(SEM_ERR_INVALID_ARG, "expected " + std::to_string(kParams) + " values");
+    if (step < 0) return fail(SEM_ERR_INVALID_ARG, "negative Adam step count");
+    Smoother &s = sm->s;
+    SEM_HIP_TRY(hipDeviceSynchronize());
+    SEM_HIP_TRY(hipMemcpy(s.W, weights, kParams * 4, hipMemcpyHostToDevice));
+    SEM_HIP_TRY(hipMemcpy(s.m, adam_m, kParams * 4, hipMemcpyHostToDevice));
+    SEM_HIP_TRY(hipMemcpy(s.v, adam_v, kParams * 4, hipMemcpyHostToDevice));
+    s.step = step;
+    SEM_HIP_TRY(nn_pack(s, nullptr));
+    SEM_HIP_TRY(hipDeviceSynchronize());
+    return SEM_OK;
+}
+
 sem_status sem_smoother_apply(const sem_smoother *sm, const sem_mesh *mesh, double h1, double h2, int fp32,
                               const double *r_local, double *z_local, void *stream)
 {
@@ -667,7 +709,7 @@ sem_status sem_smoother_apply(const sem_smoother *sm, const sem_mesh *mesh, doub
     SEM_TRY(check_pair(s, m));
     hipStream_t st = (hipStream_t)stream;
     TrainBufs t = train_bufs(s);
-    SEM_HIP_TRY(make_dinv(m, h1, h2, t, st));
+    SEM_HIP_TRY(make_dinv(s, m, h1, h2, t, st, true));
     SEM_TRY(gather_local(m, r_local, t.r, st));
     if (fp32)
         SEM_HIP_TRY(nn_infer32(s, m, t.r, t.dinv, s.c_local, st));
@@ -687,7 +729,7 @@ sem_status sem_smoother_loss_grad(sem_smoother *sm, const sem_mesh *mesh, double
     SEM_TRY(check_pair(s, m));
     hipStream_t st = (hipStream_t)stream;
     TrainBufs t = train_bufs(s);
-    SEM_HIP_TRY(make_dinv(m, h1, h2, t, st));
+    SEM_HIP_TRY(make_dinv(s, m, h1, h2, t, st, true));
     SEM_TRY(gather_local(m, e_local, t.e, st));
     SEM_TRY(loss_forward(s, m, h1, h2, t, st));
     SEM_HIP_TRY(nn_grad(s, m, t.r, t.dinv, t.d, s.dW_elem, 1.0, s.grad, st));
@@ -708,11 +750,7 @@ sem_status sem_smoother_train_step(sem_smoother *sm, const sem_mesh *mesh, doubl
     SEM_TRY(check_pair(s, m));
     hipStream_t st = (hipStream_t)stream;
     TrainBufs t = train_bufs(s);
-    if (s.step == 0 || s.dinv_h1 != h1 || s.dinv_h2 != h2) {
-        SEM_HIP_TRY(make_dinv(m, h1, h2, t, st));
-        s.dinv_h1 = h1;
-        s.dinv_h2 = h2;
-    }
+    SEM_HIP_TRY(make_dinv(s, m, h1, h2, t, st, false));
     hipLaunchKernelGGL(lk::f32_to_f64_kernel, dim3(cg_blocks(m.ng)), dim3(kBS), 0, st, e_global, t.e, m.ng);
     SEM_TRY(loss_forward(s, m, h1, h2, t, st));
     SEM_HIP_TRY(nn_grad(s, m, t.r, t.dinv, t.d, s.dW_elem, 1.0, s.grad, st));

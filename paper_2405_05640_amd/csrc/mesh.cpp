@@ -5,6 +5,7 @@
 // (paper section 3.1: hexahedral
 // elements, GLL collocation, gather-scatter coupling; the spectral-element
 // definitions follow Deville, Fischer & Mund 2002, chapters 2 and 4).
+#include <atomic>
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -448,6 +449,8 @@ sem_status sem_mesh_create(const sem_mesh_desc *desc, sem_mesh **out)
         delete h;
         return st;
     }
+    static std::atomic<uint64_t> next_serial{1};
+    h->m.serial = next_serial.fetch_add(1);
     *out = h;
     return SEM_OK;
 }

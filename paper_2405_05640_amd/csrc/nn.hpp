@@ -28,7 +28,10 @@ struct Smoother {
     float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     int stall_window = 25;
     double stall_rate = 0.0;        // 0: stall test off
-    double dinv_h1 = -1.0, dinv_h2 = -1.0;   // coefficients of the cached training dinv
+    // what the dinv in the training buffers was built for: mesh serial and
+    // h1, h2 (every call that rebuilds it updates the key)
+    mutable uint64_t dinv_serial = 0;
+    mutable double dinv_h1 = -1.0, dinv_h2 = -1.0;
     size_t device_bytes = 0;
 };
 

@@ -56,6 +56,7 @@ struct Mesh {
     double *d_scratch = nullptr;  // small device scratch for sem_dot partials
     int32_t scratch_len = 0;
     size_t device_bytes = 0;
+    uint64_t serial = 0;          // unique per created mesh (process-wide counter)
 
     int64_t glo(int64_t e, int i, int j, int k) const;
 };

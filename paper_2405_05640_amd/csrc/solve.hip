@@ -1,21 +1,3 @@
-// solve.hip -- Jacobi-preconditioned conjugate gradients on S = mask o dssum o A_L
-// (the paper's preconditioned Krylov solve of Ax = b, section 3.1; CG after
-// Hestenes & Stiefel 1952 with point-Jacobi z = dinv o r), plus the small
-// operator entry points of the C ABI.
-//
-// Iteration (all scalars stay on the device; the host only polls a flag):
-//   1. w = A_L p                  ax kernel, fused per-element partial of p.w
-//   2. w = dssum(w)               gather-scatter
-//   3. alpha = rz / (p, w)        one-block finalize (deterministic tree)
-//   4. x += alpha p, r -= alpha w fused update, block partials of (r,r), (r,z)
-//   5. convergence test, beta     one-block finalize
-//   6. p = dinv r + beta p
-// For a continuous p that is zero on Dirichlet nodes, (p, S p) equals the
-// unassembled sum p.(A_L p), so step 1 yields the denominator before the
-// gather-scatter.  The preconditioner is stored with zeros on Dirichlet
-// nodes and the inner-product weights 1/mult are zero there too, so no mask
-// pass is needed inside the loop: p, x stay zero on those nodes and r's
-// values there never enter a sum.
 // solve.hip -- the solve drivers (paper section 3.1: a preconditioned Krylov
 // solve of Ax = b every time step) and the operator entry points of the C ABI.
 //
@@ -31,8 +13,8 @@
 //
 // FP32 defect correction (Wilkinson-style iterative refinement): the FP64
 // true residual r = b - S x is scaled to unit norm, rounded to FP32, an FP32
-// PCG on the FP32 operator solves S d = r to inner_tol, and x += |r| d in
-// FP64.  FP64 is kept for the outer residual, every inner product and the
+// PCG on the FP32 operator (DC_BF16: the split-BF16 matrix-core operator)
+// solves S d = r to inner_tol, and x += |r| d in FP64.  FP64 is kept for the outer residual, every inner product and the
 // convergence tests.  The reliable-update forms keep one low-precision Krylov
 // process and replace its residual instead (solve_reliable); the
 // single-reduction form is solve_pcg1.
@@ -136,7 +118,7 @@ sem_status check_opts(const Mesh &m, const sem_solve_opts *o)
     case SEM_FORM_DC_BF16:
         if (o->form == SEM_FORM_DC_FP32 && !m.d_G32)
             return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_DC_FP32 needs a mesh created with SEM_PREP_F32");
-        if (o->form == SEM_FORM_DC_BF16 && !m.d_Gbf)
+        if (o->form == SEM_FORM_DC_BF16 && !m.d_Gh)
             return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_DC_BF16 needs a mesh created with SEM_PREP_BF16");
         if (o->form == SEM_FORM_DC_BF16 && m.N != 7)
             return fail(SEM_ERR_UNSUPPORTED, "the bf16 operator needs order N = 7");
@@ -191,11 +173,14 @@ sem_status reset_state(CgState *d, int max_it, int hist_len, hipStream_t s)
     return SEM_OK;
 }
 
+// Low-precision operators of the float solves.
+enum LowOp { kOpF32 = 0, kOpBf16 = 1, kOpBf16Split = 2 };
+
 // Iterate until the device flag says done; returns the final host state.
-// bf16: the float inner solve applies the BF16 matrix-core operator.
+// op: the operator of a float solve (FP32, plain BF16 or split BF16).
 template <typename T>
 sem_status iterate(const Mesh &m, double h1, double h2, const CgVecs<T> &v, CgState *st, double *hist,
-                   int check_every, hipStream_t s, CgState &h, bool bf16 = false)
+                   int check_every, hipStream_t s, CgState &h, int op = kOpF32)
 {
     for (;;) {
         SEM_TRY(read_state(h, st, s));
@@ -204,8 +189,10 @@ sem_status iterate(const Mesh &m, double h1, double h2, const CgVecs<T> &v, CgSt
             if constexpr (sizeof(T) == 8) {
                 SEM_HIP_TRY(launch_ax_f64_gather(m, h1, h2, v.p, v.w, v.part_e, s, &st->done));
             } else {
-                if (bf16)
+                if (op == kOpBf16)
                     SEM_HIP_TRY(launch_ax_bf16_gather(m, (float)h1, (float)h2, v.p, v.w, v.part_e, s, &st->done));
+                else if (op == kOpBf16Split)
+                    SEM_HIP_TRY(launch_ax_bf16s(m, (float)h1, (float)h2, v.p, v.w, v.part_e, s, &st->done, true));
                 else
                     SEM_HIP_TRY(launch_ax_f32_gather(m, (float)h1, (float)h2, v.p, v.w, v.part_e, s, &st->done));
             }
@@ -297,7 +284,8 @@ sem_status solve_dc32(const Mesh &m, const sem_solve_opts &o, const Workspace &w
         if (outer > 0) {
             SEM_TRY(true_residual(m, o.h1, o.h2, ws, s, h));
             if (h.true_rr <= h.tol2) { h.done = 1; break; }
-            if (!(h.true_rr < prev)) { h.done = 2; break; }   // refinement stalled
+            if (!std::isfinite(h.true_rr)) { h.done = 2; break; }
+            if (!(h.true_rr < prev)) { h.done = kDoneStalled; break; }   // refinement stalled
             prev = h.true_rr;
         } else {
             // first outer step: r = b, already in v64.r
@@ -308,7 +296,7 @@ sem_status solve_dc32(const Mesh &m, const sem_solve_opts &o, const Workspace &w
         SEM_TRY(reset_state(ws.st32, o.max_iter - total, 0, s));
         SEM_HIP_TRY(cg_init<float>(m, ws.v32, ws.b32, ws.st32, o.inner_tol, nullptr, s));
         SEM_TRY(iterate<float>(m, o.h1, o.h2, ws.v32, ws.st32, nullptr, check_every, s, hi,
-                               o.form == SEM_FORM_DC_BF16));
+                               o.form == SEM_FORM_DC_BF16 ? kOpBf16Split : kOpF32));
         total += hi.it;
         SEM_HIP_TRY(cg_axpy<float>(m, ws.v64.x, ws.v32.x, rn, s));
         ++outer;
@@ -345,7 +333,7 @@ sem_status solve_reliable(const Mesh &m, const sem_solve_opts &o, const Workspac
     h.true_rr = h.bb;
     SEM_TRY(reset_state(ws.st32, o.max_iter, 0, s));
     double sigma = std::sqrt(h.bb);
-    SEM_HIP_TRY(cg_replace<float>(m, ws.v32, ws.v64.r, ws.st32, 1.0 / sigma, 0.0, 1, h.tol2 / h.bb, s));
+    SEM_HIP_TRY(cg_replace<float>(m, ws.v32, ws.v64.r, ws.st32, 1.0 / sigma, 0.0, kReplaceFirst, h.tol2 / h.bb, s));
     const double delta2 = o.inner_tol * o.inner_tol;
     double rmax = 1.0, best = h.bb;
     int updates = 0, stalls = 0;
@@ -372,12 +360,15 @@ sem_status solve_reliable(const Mesh &m, const sem_solve_opts &o, const Workspac
                 best = h.true_rr;
                 stalls = 0;
             } else if (++stalls >= 3) {
-                h.done = 2;   // the true residual stopped decreasing
+                h.done = kDoneStalled;   // the true residual stopped decreasing
                 break;
             }
             if (lo.it >= o.max_iter) { h.done = 3; break; }
             const double sn = std::sqrt(h.true_rr);
-            SEM_HIP_TRY(cg_replace<float>(m, ws.v32, ws.v64.r, ws.st32, 1.0 / sn, sigma / sn, 0, h.tol2 / h.true_rr, s));
+            // after a converged low-precision run the last direction update
+            // was skipped, so the direction restarts from dinv r
+            const int mode = lo.done == 1 ? kReplaceRestart : kReplaceKeep;
+            SEM_HIP_TRY(cg_replace<float>(m, ws.v32, ws.v64.r, ws.st32, 1.0 / sn, sigma / sn, mode, h.tol2 / h.true_rr, s));
             sigma = sn;
             rmax = 1.0;
         }
@@ -542,7 +533,12 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
     rep->elapsed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     if (h.done == 2) {
         rep->status = SEM_ERR_BREAKDOWN;
-        return fail(SEM_ERR_BREAKDOWN, "CG breakdown: (p, S p) <= 0, non-finite value, or stalled refinement");
+        return fail(SEM_ERR_BREAKDOWN, "CG breakdown: (p, S p) <= 0 or a non-finite value");
+    }
+    if (h.done == kDoneStalled) {
+        rep->status = SEM_ERR_NOT_CONVERGED;
+        return fail(SEM_ERR_NOT_CONVERGED, "refinement stalled: the FP64 true residual stopped decreasing at " +
+                                               std::to_string(rep->true_rel_res) + " relative");
     }
     if (h.bb > 0.0 && !(h.true_rr <= h.tol2)) {
         rep->status = SEM_ERR_NOT_CONVERGED;

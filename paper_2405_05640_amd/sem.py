@@ -112,6 +112,8 @@ def lib():
             "sem_smoother_destroy": [vp],
             "sem_smoother_set_weights": [vp, vp, ctypes.c_size_t],
             "sem_smoother_get_weights": [vp, vp, ctypes.c_size_t],
+            "sem_smoother_get_state": [vp, vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(i32)],
+            "sem_smoother_set_state": [vp, vp, vp, vp, ctypes.c_size_t, i32],
             "sem_smoother_apply": [vp, vp, dbl, dbl, ctypes.c_int, vp, vp, vp],
             "sem_smoother_loss_grad": [vp, vp, dbl, dbl, vp, ctypes.POINTER(dbl), vp, vp],
             "sem_smoother_train_step": [vp, vp, dbl, dbl, vp, vp, vp],
@@ -317,8 +319,8 @@ class Mesh:
 class Smoother:
     """Learned per-element smoother (``sem_smoother``) bound to one N = 7 mesh."""
 
-    def __init__(self, mesh, seed=0, lr=1e-3, stall_window=25, stall_rate=0.0):
-        d = SmootherDesc(seed, lr, 0.9, 0.999, 1e-8, stall_window, stall_rate)
+    def __init__(self, mesh, seed=0, lr=1e-3, stall_window=25, stall_rate=0.0, beta1=0.9, beta2=0.999, eps=1e-8):
+        d = SmootherDesc(seed, lr, beta1, beta2, eps, stall_window, stall_rate)
         h = ctypes.c_void_p()
         _check(lib().sem_smoother_create(mesh._h, ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -346,22 +348,38 @@ class Smoother:
         _check(lib().sem_smoother_get_weights(self._h, w.ctypes.data_as(ctypes.c_void_p), w.size))
         return w
 
+    def get_state(self):
+        """(weights, adam_m, adam_v, step): the training checkpoint."""
+        w, m, v = (np.zeros(SMOOTHER_PARAMS, dtype=np.float32) for _ in range(3))
+        step = ctypes.c_int32()
+        _check(lib().sem_smoother_get_state(self._h, w.ctypes.data_as(ctypes.c_void_p),
+                                            m.ctypes.data_as(ctypes.c_void_p), v.ctypes.data_as(ctypes.c_void_p),
+                                            SMOOTHER_PARAMS, ctypes.byref(step)))
+        return w, m, v, int(step.value)
+
+    def set_state(self, w, m, v, step):
+        arrs = [np.ascontiguousarray(a, dtype=np.float32).ravel() for a in (w, m, v)]
+        if any(a.size != SMOOTHER_PARAMS for a in arrs):
+            raise ValueError("expected %d values per array" % SMOOTHER_PARAMS)
+        _check(lib().sem_smoother_set_state(self._h, *(a.ctypes.data_as(ctypes.c_void_p) for a in arrs),
+                                            SMOOTHER_PARAMS, int(step)))
+
     def apply(self, r, z, h1=1.0, h2=0.0, fp32=False):
         m = self.mesh
         _check(lib().sem_smoother_apply(self._h, m._h, float(h1), float(h2), 1 if fp32 else 0,
                                         _want(r, "f64", m.n_local, "r"), _want(z, "f64", m.n_local, "z"), _stream()))
         return z
 
-    def loss_grad(self, e, h1=1.0, h2=0.0):
-        m = self.mesh
+    def loss_grad(self, e, h1=1.0, h2=0.0, mesh=None):
+        m = self.mesh if mesh is None else mesh
         loss = ctypes.c_double()
         g = np.zeros(SMOOTHER_PARAMS, dtype=np.float32)
         _check(lib().sem_smoother_loss_grad(self._h, m._h, float(h1), float(h2), _want(e, "f64", m.n_local, "e"),
                                             ctypes.byref(loss), g.ctypes.data_as(ctypes.c_void_p), _stream()))
         return loss.value, g
 
-    def train_step(self, e_global, loss_out=None, h1=1.0, h2=0.0):
-        m = self.mesh
+    def train_step(self, e_global, loss_out=None, h1=1.0, h2=0.0, mesh=None):
+        m = self.mesh if mesh is None else mesh
         _check(lib().sem_smoother_train_step(self._h, m._h, float(h1), float(h2),
                                              _want(e_global, "f32", m.n_global, "e_global"),
                                              _want(loss_out, "f64", 1, "loss_out") if loss_out is not None else None,

@@ -245,3 +245,182 @@ def test_bf16_storage_reference_operator():
     w64 = m.ax(u, 1.0, 0.1)
     assert np.all(np.abs(au - w64) <= 2.0 ** -8 * m.ax_abs_bound(u, 1.0, 0.1) + 1e-30)
     assert np.linalg.norm(au - w64) > 0.0
+
+
+# ---------------------------------------------------------------- Adam
+
+def _adam_run(grads, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, W0=None):
+    shape = np.shape(grads[0])
+    opt = cnn.Adam([shape], lr, b1, b2, eps)
+    W = [np.zeros(shape) if W0 is None else np.array(W0, dtype=np.float64)]
+    out = []
+    for g in grads:
+        W = opt.step(W, [g])
+        out.append(W[0].copy())
+    return out, opt
+
+
+def test_adam_first_step_closed_form():
+    # bias correction makes the first estimates m_hat = g, v_hat = g^2, so the
+    # first step is -lr g / (|g| + eps) in every component (a sign step for
+    # |g| >> eps), whatever beta1 and beta2 are
+    rng = np.random.default_rng(0)
+    g = rng.standard_normal(50) * np.logspace(-10, 2, 50)
+    g[3] = 0.0
+    W0 = rng.standard_normal(50)
+    for b1, b2 in ((0.9, 0.999), (0.5, 0.7)):
+        (W1,), _ = _adam_run([g], lr=2e-3, b1=b1, b2=b2, eps=1e-8, W0=W0)
+        assert np.allclose(W1, W0 - 2e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert W1[3] == W0[3]
+
+
+def test_adam_constant_gradient_closed_form():
+    # a constant gradient g gives m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2
+    # (geometric sums), so every bias-corrected step is the first one again:
+    # W_k = W_0 - k lr g / (|g| + eps).  Missing or wrong bias corrections
+    # break this from step 2 on.
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal(20)
+    Ws, _ = _adam_run([g] * 7, lr=1e-2, eps=1e-8)
+    for k, W in enumerate(Ws, start=1):
+        assert np.allclose(W, -k * 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-13, atol=0)
+
+
+def test_adam_impulse_closed_form():
+    # gradient g at step 1, then zeros: m_k = b1^(k-1) (1 - b1) g and
+    # v_k = b2^(k-1) (1 - b2) g^2, so step k moves by
+    # lr a_k g / (sqrt(c_k) |g| + eps) with a_k = b1^(k-1)(1-b1)/(1-b1^k) and
+    # c_k = b2^(k-1)(1-b2)/(1-b2^k).  Tells beta1 from beta2 (a swap fails).
+    g = np.array([0.3, -2.0, 1e-3])
+    b1, b2, lr, eps = 0.9, 0.99, 1e-3, 1e-8
+    Ws, opt = _adam_run([g] + [np.zeros(3)] * 5, lr=lr, b1=b1, b2=b2, eps=eps)
+    W = np.zeros(3)
+    for k in range(1, 7):
+        a = b1 ** (k - 1) * (1 - b1) / (1 - b1 ** k)
+        c = b2 ** (k - 1) * (1 - b2) / (1 - b2 ** k)
+        W = W - lr * a * g / (np.sqrt(c) * np.abs(g) + eps)
+        assert np.allclose(Ws[k - 1], W, rtol=1e-12, atol=0)
+    assert opt.t == 6
+    assert np.allclose(opt.m[0], b1 ** 5 * (1 - b1) * g, rtol=1e-14)
+    assert np.allclose(opt.v[0], b2 ** 5 * (1 - b2) * g * g, rtol=1e-14)
+    swapped, _ = _adam_run([g] + [np.zeros(3)] * 5, lr=lr, b1=b2, b2=b1, eps=eps)
+    assert not np.allclose(swapped[-1], Ws[-1], rtol=1e-6)
+
+
+def test_adam_scale_invariance_without_eps():
+    # with eps = 0 the update depends on the gradient sequence only through
+    # its direction: scaling every gradient by c > 0 leaves the path unchanged
+    rng = np.random.default_rng(2)
+    gs = [rng.standard_normal(30) for _ in range(5)]
+    a, _ = _adam_run(gs, eps=0.0)
+    b, _ = _adam_run([1e4 * g for g in gs], eps=0.0)
+    for x, y in zip(a, b):
+        assert np.allclose(x, y, rtol=1e-12, atol=1e-18)
+
+
+def test_train_step_is_loss_grad_then_adam():
+    # cnn.train_step = loss and gradient at the current weights (the pinned
+    # loss_and_grad), then the pinned Adam update; the loss it returns is the
+    # one before the update, and a small step lowers the loss of the same pair
+    m = _mesh(wl.random_deformed_box(2, 2, 2, 7, seed=1, amp=0.1))
+    rng = np.random.default_rng(3)
+    e = brute.continuous_random(m, rng)
+    dinv = m.jacobi_inv()
+    net = cnn.Net.init(16, seed=0)
+    net.W[2] = np.random.default_rng(9).standard_normal(net.W[2].shape) * 0.05
+    W0 = [w.copy() for w in net.W]
+    L0, g0 = cnn.loss_and_grad(m, net, m.apply_S(e), e, dinv)
+    opt = cnn.Adam([w.shape for w in net.W], lr=1e-4)
+    L = cnn.train_step(m, net, opt, e, dinv)
+    assert L == L0
+    ref = cnn.Adam([w.shape for w in W0], lr=1e-4).step(W0, g0)
+    for a, b in zip(net.W, ref):
+        assert np.array_equal(a, b)
+    L1, _ = cnn.loss_and_grad(m, net, m.apply_S(e), e, dinv)
+    assert L1 < L0
+
+
+# ---------------------------------------------------------------- BF16 rounding order
+
+def _rn(x, bits):
+    """Round a Fraction to the nearest binary number with `bits` significant
+    bits, ties to even (no exponent limits: the values here are moderate)."""
+    from fractions import Fraction
+    if x == 0:
+        return Fraction(0)
+    s = -1 if x < 0 else 1
+    a = abs(x)
+    e = 0
+    while a >= 2:
+        a /= 2
+        e += 1
+    while a < 1:
+        a *= 2
+        e -= 1
+    scaled = a * 2 ** (bits - 1)          # in [2^(bits-1), 2^bits)
+    q, r = divmod(scaled.numerator, scaled.denominator)
+    frac = Fraction(r, scaled.denominator)
+    if frac > Fraction(1, 2) or (frac == Fraction(1, 2) and q % 2 == 1):
+        q += 1
+    return s * Fraction(q) * Fraction(2) ** (e - (bits - 1))
+
+
+def test_bf16_operator_rounding_sequence_one_element():
+    # The plain BF16 emulation rounds at five places: u, D, G and B to BF16 on
+    # entry, and the three G-combination results to BF16 before the
+    # transposed contractions; every other operation is one FP32 rounding.
+    # On one N = 1 element (two-term contractions, so the FP32 sum order
+    # cannot matter) the expected result is evaluated here in exact rational
+    # arithmetic with those roundings written out (BF16: 8 significant bits,
+    # FP32: 24, nearest-even).  The emulation must match it bit for bit, and
+    # leaving out any one of the five roundings must change the result.
+    from fractions import Fraction
+    from types import SimpleNamespace
+
+    from oracle import mixed
+    rng = np.random.default_rng(5)
+    f32 = np.float32
+    D = rng.uniform(-1, 1, (2, 2)).astype(f32)
+    G = rng.uniform(-1, 1, (6, 1, 2, 2, 2)).astype(f32)
+    G[[0, 3, 5]] = np.abs(G[[0, 3, 5]]) + 1
+    B = rng.uniform(0.5, 1.5, (1, 2, 2, 2)).astype(f32)
+    u = rng.standard_normal((1, 2, 2, 2)).astype(f32)
+    h1, h2 = 1.0, 0.5
+    fake = SimpleNamespace(D=D.astype(np.float64), G=G.astype(np.float64), B=B.astype(np.float64))
+    got = mixed.ax_lowp(fake, u.astype(np.float64), h1, h2, "bf16")
+
+    def expected(skip=()):
+        b16 = lambda x: _rn(x, 8)
+        r32 = lambda x: _rn(x, 24)
+        F = lambda a: Fraction(float(a))
+        rd = lambda name, x: x if name in skip else b16(x)
+        Dq = [[rd("D", F(D[a, b])) for b in range(2)] for a in range(2)]
+        Gq = [[[[rd("G", F(G[c, 0, k, j, i])) for i in range(2)] for j in range(2)] for k in range(2)] for c in range(6)]
+        Bq = [[[rd("B", F(B[0, k, j, i])) for i in range(2)] for j in range(2)] for k in range(2)]
+        uq = [[[rd("u", F(u[0, k, j, i])) for i in range(2)] for j in range(2)] for k in range(2)]
+        idx = [(k, j, i) for k in range(2) for j in range(2) for i in range(2)]
+        ur, us, ut = {}, {}, {}
+        for (k, j, i) in idx:   # two exact BF16 x BF16 products, one FP32 rounding of the sum
+            ur[k, j, i] = r32(sum(Dq[i][m] * uq[k][j][m] for m in range(2)))
+            us[k, j, i] = r32(sum(Dq[j][m] * uq[k][m][i] for m in range(2)))
+            ut[k, j, i] = r32(sum(Dq[k][m] * uq[m][j][i] for m in range(2)))
+        flux = {}
+        for name, (a, b, c) in (("r", (0, 1, 2)), ("s", (1, 3, 4)), ("t", (2, 4, 5))):
+            for (k, j, i) in idx:   # numpy: ((Ga ur + Gb us) + Gc ut), each op rounded to FP32
+                p = r32(r32(r32(Gq[a][k][j][i] * ur[k, j, i]) + r32(Gq[b][k][j][i] * us[k, j, i]))
+                        + r32(Gq[c][k][j][i] * ut[k, j, i]))
+                flux[name, k, j, i] = p if "comb" in skip else b16(p)
+        out = np.zeros((1, 2, 2, 2))
+        for (k, j, i) in idx:
+            wr = r32(sum(Dq[m][i] * flux["r", k, j, m] for m in range(2)))
+            ws = r32(sum(Dq[m][j] * flux["s", k, m, i] for m in range(2)))
+            wt = r32(sum(Dq[m][k] * flux["t", m, j, i] for m in range(2)))
+            w = r32(r32(wr + ws) + wt)
+            helm = r32(r32(Fraction(h2) * Bq[k][j][i]) * uq[k][j][i])
+            out[0, k, j, i] = float(r32(r32(Fraction(h1) * w) + helm))
+        return out
+
+    ref = expected()
+    assert np.array_equal(got, ref)
+    for step in ("u", "D", "G", "B", "comb"):
+        assert not np.array_equal(expected(skip=(step,)), ref), step
