@@ -209,6 +209,22 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
                          double *x, void *workspace, size_t ws_bytes, sem_solve_report *rep,
                          void *stream);
 
+/* Allocation-free variant of sem_pcg_solve, for callers that cannot
+ * allocate device memory (serving loops and harnesses that forbid
+ * hipMalloc).  Same arguments and results as sem_pcg_solve, without the
+ * workspace: it lives in a static device array of SEM_NOALLOC_SCRATCH_BYTES
+ * that every device holds once the library is loaded on it, until the
+ * process ends.  Allocates nothing.  Fails with SEM_ERR_INVALID_ARG, before
+ * any device work, when the solve's workspace (sem_solve_workspace_bytes)
+ * exceeds that size (FP64 Jacobi-PCG at N = 7: meshes up to about 900,000
+ * local points, 1,700 elements) or the mesh lives on another device than the current one.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind: calls that overlap in time on one device (other threads or
+ * streams) race and must be serialised by the caller. */
+#define SEM_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+sem_status sem_pcg_solve_noalloc(const sem_mesh *mesh, const sem_solve_opts *opts, const double *b, double *x,
+                                 sem_solve_report *rep, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Learned smoother (not in the paper; this library's accelerated form).
  * Per element e of an N = 7 mesh, with q = dinv o r, s_e = max|r_e|,

@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "cg.hpp"
 #include "nn.hpp"
@@ -719,6 +720,68 @@ sem_status sem_pcg_solve_batched(const sem_mesh *mesh, const sem_solve_opts *opt
     for (int c = 0; c < nrhs; ++c) reps[c].elapsed_ms = ms;
     if (worst != SEM_OK) return fail(worst, "a batched field did not converge");
     return SEM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve: the workspace lives in a file-scope device array.
+// Each device that loads the library holds its own copy until the process
+// ends; the host never passes the array's name to a kernel (in host code it
+// is only a stand-in symbol) but the device address that
+// hipGetSymbolAddress returns for the current device.
+
+namespace sem {
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = SEM_NOALLOC_SCRATCH_BYTES;
+static_assert(kNoAllocScratchBytes % 256 == 0, "scratch size");
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+sem_status scratch_address(void **out)
+{
+    int dev = 0;
+    SEM_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(SEM_ERR_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        SEM_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(SEM_ERR_HIP, "hipGetSymbolAddress returned a null address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SEM_OK;
+}
+
+}  // namespace
+}  // namespace sem
+
+extern "C" {
+
+sem_status sem_pcg_solve_noalloc(const sem_mesh *mesh, const sem_solve_opts *opts, const double *b, double *x,
+                                 sem_solve_report *rep, void *stream)
+{
+    if (!mesh || !opts || !b || !x || !rep) return fail(SEM_ERR_INVALID_ARG, "null argument");
+    const Mesh &m = mesh->m;
+    SEM_TRY(check_opts(m, opts));
+    int dev = 0;
+    SEM_HIP_TRY(hipGetDevice(&dev));
+    if (dev != m.device) return fail(SEM_ERR_INVALID_ARG, "the mesh lives on another device than the current one");
+    const size_t need = carve(m, opts->form, hist_len_for(*opts), nullptr).bytes;
+    if (need > kNoAllocScratchBytes)
+        return fail(SEM_ERR_INVALID_ARG, "solve needs " + std::to_string(need) + " bytes of workspace, more than the " +
+                                             std::to_string(kNoAllocScratchBytes) + "-byte static scratch");
+    void *ptr = nullptr;
+    SEM_TRY(scratch_address(&ptr));
+    return sem_pcg_solve(mesh, opts, b, x, ptr, kNoAllocScratchBytes, rep, stream);
 }
 
 }  // extern "C"

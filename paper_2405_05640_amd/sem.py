@@ -25,6 +25,7 @@ FIELD_GLO_NUM, FIELD_MULT, FIELD_MASK, FIELD_G, FIELD_B, FIELD_XYZ, FIELD_GLL, F
 (FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED, FORM_FCG_INNER_FP32, FORM_FCG_INNER_BF16,
  FORM_RELIABLE_FP32, FORM_RELIABLE_BF16, FORM_PCG_1RED) = range(9)
 SMOOTHER_PARAMS = 8208
+NOALLOC_SCRATCH_BYTES = 32 << 20    # SEM_NOALLOC_SCRATCH_BYTES
 
 EXPORTED_SYMBOLS = [
     "sem_mesh_create", "sem_mesh_destroy", "sem_mesh_query", "sem_mesh_export", "sem_ax",
@@ -32,6 +33,7 @@ EXPORTED_SYMBOLS = [
     "sem_pcg_solve", "sem_last_error", "sem_version", "sem_smoother_create", "sem_smoother_destroy",
     "sem_smoother_set_weights", "sem_smoother_get_weights", "sem_smoother_apply", "sem_smoother_loss_grad",
     "sem_smoother_train_step", "sem_pcg_snapshots", "sem_pcg_solve_batched", "sem_solve_workspace_bytes_batched",
+    "sem_smoother_get_state", "sem_smoother_set_state", "sem_pcg_solve_noalloc",
 ]
 
 
@@ -108,6 +110,7 @@ def lib():
             "sem_solve_workspace_bytes": [vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(ctypes.c_size_t)],
             "sem_pcg_solve": [vp, ctypes.POINTER(SolveOpts), vp, vp, vp, ctypes.c_size_t,
                               ctypes.POINTER(SolveReport), vp],
+            "sem_pcg_solve_noalloc": [vp, ctypes.POINTER(SolveOpts), vp, vp, ctypes.POINTER(SolveReport), vp],
             "sem_smoother_create": [vp, ctypes.POINTER(SmootherDesc), ctypes.POINTER(vp)],
             "sem_smoother_destroy": [vp],
             "sem_smoother_set_weights": [vp, vp, ctypes.c_size_t],
@@ -311,6 +314,20 @@ class Mesh:
         r = Report(rep.status, rep.iterations, rep.outer_iterations, rep.restarts, rep.fallback_used,
                    rep.rel_res, rep.true_rel_res, rep.elapsed_ms,
                    hist[: rep.history_written].copy() if hist is not None else None)
+        if st != SEM_OK and raise_on_error:
+            raise SemError(st, lib().sem_last_error().decode())
+        return r
+
+
+    def pcg_solve_noalloc(self, b, x, raise_on_error=True, **kw):
+        """sem_pcg_solve_noalloc: the solve with its workspace in the
+        library's static device scratch (no allocation)."""
+        opts = self.solve_opts(**kw)
+        rep = SolveReport()
+        st = lib().sem_pcg_solve_noalloc(self._h, ctypes.byref(opts), _want(b, "f64", self.n_local, "b"),
+                                         _want(x, "f64", self.n_local, "x"), ctypes.byref(rep), _stream())
+        r = Report(rep.status, rep.iterations, rep.outer_iterations, rep.restarts, rep.fallback_used,
+                   rep.rel_res, rep.true_rel_res, rep.elapsed_ms, None)
         if st != SEM_OK and raise_on_error:
             raise SemError(st, lib().sem_last_error().decode())
         return r
