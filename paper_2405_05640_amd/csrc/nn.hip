@@ -431,7 +431,10 @@ hipError_t nn_grad(const Smoother &sm, const Mesh &m, const double *rg, const do
 hipError_t nn_adam(Smoother &sm, const float *grad, hipStream_t s)
 {
     sm.step += 1;
-    const float c1 = 1.f - std::pow(sm.b1, (float)sm.step), c2 = 1.f - std::pow(sm.b2, (float)sm.step);
+    // bias corrections 1 - beta^t in FP64 (in FP32, 1 - 0.999^t loses about
+    // 15 bits to cancellation at small t), then rounded once
+    const float c1 = (float)(1.0 - std::pow((double)sm.b1, (double)sm.step));
+    const float c2 = (float)(1.0 - std::pow((double)sm.b2, (double)sm.step));
     hipLaunchKernelGGL(nn::adam_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, sm.W, sm.m, sm.v, grad, sm.lr,
                        sm.b1, sm.b2, sm.eps, c1, c2);
     return nn_pack(sm, s);
