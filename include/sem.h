@@ -58,6 +58,11 @@ typedef struct sem_smoother sem_smoother;   /* opaque learned smoother */
 /* Low-precision copies of the geometric factors built at mesh creation. */
 #define SEM_PREP_F32 1u
 #define SEM_PREP_BF16 2u
+/* The hybrid Schwarz multigrid preconditioner's data (per-element separable
+ * local solvers at orders N and 3, interpolation matrices, the separable
+ * order-1 coarse solver); needed by SEM_FORM_GMRES_HSMG and
+ * SEM_FORM_PCG_BLOCK_JACOBI. */
+#define SEM_PREP_HSMG 4u
 
 typedef struct {
     int32_t nelx, nely, nelz;   /* elements per direction, each >= 1 */
@@ -142,6 +147,22 @@ sem_status sem_jacobi(const sem_mesh *mesh, double h1, double h2, double *dinv, 
 sem_status sem_dot(const sem_mesh *mesh, const double *u, const double *v, double *result,
                    void *stream);
 
+/* Preconditioners of the paper's solves, applied to a continuous, masked
+ * local residual r (device double [E][P]); z (device double [E][P])
+ * receives the continuous, masked result (async).  Needs SEM_PREP_HSMG,
+ * h1 > 0, h2 >= 0.  kind:
+ *   SEM_PRECOND_HSMG          the three-level hybrid Schwarz multigrid of
+ *                             SEM_FORM_GMRES_HSMG (defined below);
+ *   SEM_PRECOND_SCHWARZ       its fine level alone: W0 K0 r;
+ *   SEM_PRECOND_BLOCK_JACOBI  K0 r without the averaging (the velocity
+ *                             solves' block-Jacobi, symmetric positive
+ *                             definite).
+ * workspace: device, >= sem_precond_workspace_bytes. */
+enum { SEM_PRECOND_HSMG = 0, SEM_PRECOND_SCHWARZ = 1, SEM_PRECOND_BLOCK_JACOBI = 2 };
+sem_status sem_precond_workspace_bytes(const sem_mesh *mesh, size_t *bytes);
+sem_status sem_precond_apply(const sem_mesh *mesh, int kind, double h1, double h2, const double *r_local,
+                             double *z_local, void *workspace, size_t ws_bytes, void *stream);
+
 /* Solver forms. */
 typedef enum {
     SEM_FORM_JACOBI_PCG = 0,     /* FP64 Jacobi-preconditioned CG */
@@ -161,10 +182,40 @@ typedef enum {
                                     updates); the search direction is kept */
     SEM_FORM_RELIABLE_BF16 = 7,  /* same with the split-BF16 matrix-core operator
                                     (SEM_BF16_SPLIT) */
-    SEM_FORM_PCG_1RED = 8        /* FP64 Jacobi-PCG in the single-reduction form of
+    SEM_FORM_PCG_1RED = 8,       /* FP64 Jacobi-PCG in the single-reduction form of
                                     Chronopoulos & Gear (1989): one vector pass, the operator and
                                     one reduction phase per iteration; same stopping test */
+    SEM_FORM_GMRES_HSMG = 9,     /* the paper's pressure solver (section 3.1): restarted flexible
+                                    GMRES(m) (right preconditioning, Saad 2003 Alg. 9.6; classical
+                                    Gram-Schmidt with a second pass when a new direction loses
+                                    more than half its norm) with the three-level hybrid Schwarz
+                                    multigrid preconditioner below; FP64 throughout.  m =
+                                    opts.restart; iterations = preconditioned operator
+                                    applications.  Needs SEM_PREP_HSMG, h1 > 0, and at least two
+                                    elements along every periodic direction. */
+    SEM_FORM_PCG_BLOCK_JACOBI = 10 /* FP64 CG with the block-Jacobi preconditioner of the paper's
+                                    velocity solves (section 3.1): z = sum over elements of the
+                                    element's separable local solve (the fine level of
+                                    SEM_FORM_GMRES_HSMG, unweighted, so symmetric positive
+                                    definite).  Needs SEM_PREP_HSMG and h1 > 0. */
 } sem_form;
+
+/* Hybrid Schwarz multigrid (SEM_FORM_GMRES_HSMG), for an assembled fine
+ * residual r, with levels at orders N, 3 and 1 on the same vertices:
+ *   z = W0 K0 r + P01 [ W1 K1 R10 r + P12 C^-1 R21 R10 r ]
+ * P: tensor-product GLL interpolation between levels; R = P^T (on assembled
+ * vectors: the residual divided by its multiplicity, J^T per element, summed
+ * over copies).  K_l: additive Schwarz whose subdomains are the elements' own
+ * node sets (one GLL point of overlap into each neighbour, Dirichlet there);
+ * each local matrix is the separable approximation built from one length per
+ * element and axis (mean edge length) with the neighbours' end-interval
+ * terms, inverted by fast diagonalisation (Lynch, Rice & Thomas 1964) -- the
+ * exact principal submatrix inverse on rectilinear meshes.  W_l: the average
+ * over node copies (1 / mult).  C^-1: the order-1 operator of the rectilinear
+ * grid whose vertex planes are the mesh's averaged planes, inverted by global
+ * fast diagonalisation (exact on rectilinear meshes).  Lottes & Fischer
+ * (2005) describe this family of hybrid Schwarz/multigrid methods; the
+ * additive combination over levels is the one the paper's Neko code uses. */
 
 typedef struct {
     double h1, h2;              /* Helmholtz coefficients (Poisson: 1, 0) */
@@ -179,6 +230,7 @@ typedef struct {
     double *history;            /* HOST, optional: relative residual per iteration */
     int32_t history_len;        /* capacity of history */
     int32_t inner_iters;        /* inner steps per outer iteration (FCG_INNER forms) */
+    int32_t restart;            /* GMRES restart length m, 1..30 (0 = 30) */
 } sem_solve_opts;
 
 typedef struct {

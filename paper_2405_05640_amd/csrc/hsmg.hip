@@ -1,0 +1,980 @@
+// hsmg.hip -- the paper's pressure preconditioner and Krylov method
+// (section 3.1, "Neko": restarted GMRES with a hybrid-Schwarz multigrid
+// preconditioner; CG with block-Jacobi for the velocity solves), on
+// assembled vectors.
+//
+// One preconditioner application z = M r (three levels, orders N, 3, 1):
+//   1. fine Schwarz: per element (one workgroup, one thread per node) gather
+//      r_e, fast-diagonalisation solve (three forward contractions with the
+//      element's S^T, division by h1 (lx + ly + lz) + h2, three backward
+//      contractions with S) -> fine rows; in the same pass r_e / mult is
+//      restricted to order 3 (J^T along r, s, t) -> mid rows
+//   2. mid assembly: r_m = mask(sum of copies)
+//   3. mid Schwarz (one wavefront per element at order 3) -> mid rows, and
+//      restriction to order 1 -> coarse rows
+//   4. coarse assembly; 5. coarse solve: six axis contractions with the
+//      global separable factors on the order-1 lattice
+//   6. z_m = mask(sum of copies / mult) + P z_c (node-wise interpolation)
+//   7. per element: fine rows += J (x) J (x) J z_m   (every copy gets the
+//      whole interpolated value)
+//   8. z = mask(sum of copies / mult): the averaged fine Schwarz correction
+//      plus the prolongated coarser levels.
+// All sums run in a fixed order, so results are bitwise reproducible.
+//
+// Flexible GMRES(m) (Saad 2003, Algorithm 9.6) keeps V (m+1 vectors) and
+// Z = M V (m vectors) on the device; the Hessenberg column and Givens
+// rotations are handled on the host, which reads the (j+2) inner products
+// of each Arnoldi step (one synchronisation per iteration).  The new
+// direction's inner products with every V_i and its own norm come from one
+// fused pass that also assembles S Z_j (wave-shuffle partial sums, fixed
+// order); classical Gram-Schmidt takes a second pass when the direction
+// loses more than half its norm.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "hsmg.hpp"
+
+namespace sem {
+namespace mg {
+
+#define GRID_STRIDE(g, n) for (int64_t g = (int64_t)blockIdx.x * kBS + threadIdx.x; g < (n); g += (int64_t)gridDim.x * kBS)
+
+__device__ __forceinline__ bool node_masked(const Lattice &L, int gi, int gj, int gk)
+{
+    return axis_dirichlet(L, 0, gi, L.nelx) || axis_dirichlet(L, 1, gj, L.nely) || axis_dirichlet(L, 2, gk, L.nelz);
+}
+
+__device__ __forceinline__ int node_count(const Lattice &L, int gi, int gj, int gk)
+{
+    int X[2];
+    return axis_copies(gi, L.nelx, L.N, L.per[0] != 0, X) * axis_copies(gj, L.nely, L.N, L.per[1] != 0, X) *
+           axis_copies(gk, L.nelz, L.N, L.per[2] != 0, X);
+}
+
+// ---------------------------------------------------------------- level kernels
+
+// Element Schwarz solve (and, NPC > 0, restriction of r / mult to the
+// coarser level's NPC points per direction).  One workgroup of NP^3 threads
+// per element, thread = node (i, j, k).
+template <int NP, int NPC>
+__global__ void __launch_bounds__(NP * NP * NP)
+schwarz_kernel(const double *__restrict__ rg, Lattice L, const double *__restrict__ fdm, double h1, double h2,
+               double *__restrict__ rows, const double *__restrict__ J, Lattice Lc, double *__restrict__ rows_c)
+{
+    constexpr int P2 = NP * NP, P3 = P2 * NP, NF = 3 * P2 + 3 * NP;
+    constexpr int NJ = NPC > 0 ? NP * NPC : 1;
+    __shared__ double sF[NF];
+    __shared__ double sa[P3], sb[P3];
+    __shared__ double sJ[NJ];
+    const int t = threadIdx.x, i = t % NP, j = (t / NP) % NP, k = t / P2;
+    const int64_t e = xcd_block();
+    int ex, ey, ez;
+    elem_coords(L, e, ex, ey, ez);
+    const double r = rg[gather_index32(L, ex, ey, ez, i, j, k)];
+    for (int q = t; q < NF; q += P3) sF[q] = fdm[e * NF + q];
+    if constexpr (NPC > 0)
+        for (int q = t; q < NJ; q += P3) sJ[q] = J[q];
+    sa[t] = r;
+    __syncthreads();
+    const double *Sx = sF, *Sy = sF + P2, *Sz = sF + 2 * P2;
+    const double *lx = sF + 3 * P2, *ly = lx + NP, *lz = ly + NP;
+    double v = 0.0;
+#pragma unroll
+    for (int a = 0; a < NP; ++a) v += Sx[a * NP + i] * sa[k * P2 + j * NP + a];   // modes along r
+    sb[t] = v;
+    __syncthreads();
+    v = 0.0;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) v += Sy[b * NP + j] * sb[k * P2 + b * NP + i];   // along s
+    sa[t] = v;
+    __syncthreads();
+    v = 0.0;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) v += Sz[c * NP + k] * sa[c * P2 + j * NP + i];   // along t
+    const double d = h1 * (lx[i] + ly[j] + lz[k]) + h2;                         // +inf on unused modes
+    sb[t] = d > 0.0 ? v / d : 0.0;
+    __syncthreads();
+    v = 0.0;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) v += Sz[k * NP + c] * sb[c * P2 + j * NP + i];
+    sa[t] = v;
+    __syncthreads();
+    v = 0.0;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) v += Sy[j * NP + b] * sa[k * P2 + b * NP + i];
+    sb[t] = v;
+    __syncthreads();
+    v = 0.0;
+#pragma unroll
+    for (int a = 0; a < NP; ++a) v += Sx[i * NP + a] * sb[k * P2 + j * NP + a];
+    rows[rows_index32(L, ex, ey, ez, i, j, k)] = v;
+    if constexpr (NPC > 0) {
+        // restriction of r / mult: J^T along r, then s, then t
+        const int gi = ex * L.N + i, gj = ey * L.N + j, gk = ez * L.N + k;
+        const int cnt = node_count(L, gi >= L.nx ? gi - (int)L.nx : gi, gj >= L.ny ? gj - (int)L.ny : gj,
+                                   gk >= L.nz ? gk - (int)L.nz : gk);
+        __syncthreads();   // sa is free again
+        sa[t] = r / cnt;
+        __syncthreads();
+        if (t < NPC * P2) {
+            const int c = t % NPC, jj = (t / NPC) % NP, kk = t / (NPC * NP);
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NP; ++q) s += sJ[q * NPC + c] * sa[kk * P2 + jj * NP + q];
+            sb[(kk * NP + jj) * NPC + c] = s;
+        }
+        __syncthreads();
+        if (t < NPC * NPC * NP) {
+            const int a = t % NPC, b = (t / NPC) % NPC, kk = t / (NPC * NPC);
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NP; ++q) s += sJ[q * NPC + b] * sb[(kk * NP + q) * NPC + a];
+            sa[(kk * NPC + b) * NPC + a] = s;
+        }
+        __syncthreads();
+        if (t < NPC * NPC * NPC) {
+            const int a = t % NPC, b = (t / NPC) % NPC, c = t / (NPC * NPC);
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NP; ++q) s += sJ[q * NPC + c] * sa[(q * NPC + b) * NPC + a];
+            rows_c[rows_index32(Lc, ex, ey, ez, a, b, c)] = s;
+        }
+    }
+}
+
+// out[g] = mask(sum of the copies of rows at g, times 1 / count when
+// weighted) + (zc != null: the order-1 interpolant of zc at g)
+__global__ void __launch_bounds__(kBS)
+assemble_kernel(const double *__restrict__ rows, Lattice L, int weighted, double *__restrict__ out,
+                const double *__restrict__ zc, Lattice Lc, const double *__restrict__ J)
+{
+    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
+    {
+        if (node_masked(L, gi, gj, gk)) {
+            out[g] = 0.0;
+            continue;
+        }
+        double v = node_assemble_rows<0>(L, rows, gi, gj, gk);
+        if (weighted) v /= node_count(L, gi, gj, gk);
+        if (zc) {
+            const int N = L.N;
+            int ex = gi / N, ey = gj / N, ez = gk / N;
+            if (ex >= L.nelx) ex = L.nelx - 1;
+            if (ey >= L.nely) ey = L.nely - 1;
+            if (ez >= L.nelz) ez = L.nelz - 1;
+            const int i = gi - ex * N, j = gj - ey * N, k = gk - ez * N;
+            double s = 0.0;
+            for (int c = 0; c < 2; ++c)
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a)
+                        s += J[i * 2 + a] * J[j * 2 + b] * J[k * 2 + c] * zc[gather_index32(Lc, ex, ey, ez, a, b, c)];
+            v += s;
+        }
+        out[g] = v;
+    }
+}
+
+// rows (fine, row layout) += J (x) J (x) J zm_e on every element (zm: the
+// mid level's assembled correction)
+template <int NP, int NPM>
+__global__ void __launch_bounds__(NP * NP * NP)
+prolong_add_kernel(const double *__restrict__ zm, Lattice Lm, const double *__restrict__ J, Lattice L,
+                   double *__restrict__ rows)
+{
+    constexpr int P3 = NP * NP * NP;
+    __shared__ double s0[NPM * NPM * NPM], s1[NP * NPM * NPM], s2[NP * NP * NPM];
+    __shared__ double sJ[NP * NPM];
+    const int t = threadIdx.x, i = t % NP, j = (t / NP) % NP, k = t / (NP * NP);
+    const int64_t e = xcd_block();
+    int ex, ey, ez;
+    elem_coords(L, e, ex, ey, ez);
+    const int out = rows_index32(L, ex, ey, ez, i, j, k);
+    const double cur = rows[out];
+    if (t < NPM * NPM * NPM) {
+        const int a = t % NPM, b = (t / NPM) % NPM, c = t / (NPM * NPM);
+        s0[t] = zm[gather_index32(Lm, ex, ey, ez, a, b, c)];
+    }
+    for (int q = t; q < NP * NPM; q += P3) sJ[q] = J[q];
+    __syncthreads();
+    if (t < NP * NPM * NPM) {
+        const int ii = t % NP, b = (t / NP) % NPM, c = t / (NP * NPM);
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < NPM; ++a) s += sJ[ii * NPM + a] * s0[(c * NPM + b) * NPM + a];
+        s1[t] = s;   // [c][b][i]
+    }
+    __syncthreads();
+    if (t < NP * NP * NPM) {
+        const int ii = t % NP, jj = (t / NP) % NP, c = t / (NP * NP);
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < NPM; ++b) s += sJ[jj * NPM + b] * s1[(c * NPM + b) * NP + ii];
+        s2[t] = s;   // [c][j][i]
+    }
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < NPM; ++c) s += sJ[k * NPM + c] * s2[(c * NP + j) * NP + i];
+    rows[out] = cur + s;
+}
+
+// One axis of the global coarse solve on the (nz, ny, nx) order-1 lattice:
+// forward out[.., q, ..] = sum_a S[a][q] in[.., a, ..] (then, scale != 0,
+// divided by h1 (lx + ly + lz) + h2), backward out[.., a, ..] = sum_q S[a][q] in[.., q, ..].
+__global__ void __launch_bounds__(kBS)
+coarse_axis_kernel(const double *__restrict__ in, double *__restrict__ out, const double *__restrict__ S, int axis,
+                   int fwd, int nx, int ny, int nz, const double *__restrict__ lx, const double *__restrict__ ly,
+                   const double *__restrict__ lz, double h1, double h2, int scale)
+{
+    const int64_t ntot = (int64_t)nx * ny * nz;
+    const int n = axis == 0 ? nx : (axis == 1 ? ny : nz);
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? nx : (int64_t)nx * ny);
+    GRID_STRIDE(g, ntot)
+    {
+        const int i = (int)(g % nx), j = (int)((g / nx) % ny), k = (int)(g / ((int64_t)nx * ny));
+        const int idx = axis == 0 ? i : (axis == 1 ? j : k);
+        const int64_t base = g - idx * stride;
+        double v = 0.0;
+        if (fwd)
+            for (int a = 0; a < n; ++a) v += S[a * n + idx] * in[base + a * stride];
+        else
+            for (int q = 0; q < n; ++q) v += S[idx * n + q] * in[base + q * stride];
+        if (scale) {
+            const double d = h1 * (lx[i] + ly[j] + lz[k]) + h2;
+            v = d > 0.0 ? v / d : 0.0;
+        }
+        out[g] = v;
+    }
+}
+
+// ---------------------------------------------------------------- Krylov kernels
+
+// Block partial sums of NV values per thread: wave butterfly, then the
+// waves of the block in order (deterministic); part[q * nb + block].
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&acc)[NV], int nv, double *__restrict__ part, int nb)
+{
+    __shared__ double red[kBS / 64][NV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        if (q < nv) {
+            double v = acc[q];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) red[wv][q] = v;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nv; q += kBS) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBS / 64; ++w) s += red[w][q];
+        part[(int64_t)q * nb + blockIdx.x] = s;
+    }
+}
+
+constexpr int kMaxDots = kGmresMaxRestart + 2;   // (V_i, w) for i <= j, plus (w, w)
+
+// w = mask(Q^T rows) -> wout; partials of (V_i, w), i <= j, and (w, w)
+__global__ void __launch_bounds__(kBS)
+assemble_dots_kernel(const double *__restrict__ rows, Lattice L, double *__restrict__ wout,
+                     const double *__restrict__ V, int64_t ng, int j, double *__restrict__ part)
+{
+    double acc[kMaxDots];
+#pragma unroll
+    for (int q = 0; q < kMaxDots; ++q) acc[q] = 0.0;
+    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
+    {
+        const double w = node_masked(L, gi, gj, gk) ? 0.0 : node_assemble_rows<0>(L, rows, gi, gj, gk);
+        wout[g] = w;
+#pragma unroll
+        for (int q = 0; q < kMaxDots - 1; ++q)
+            if (q <= j) acc[q] += V[q * ng + g] * w;
+        double ww = w * w;
+#pragma unroll
+        for (int q = 0; q < kMaxDots; ++q)
+            if (q == j + 1) acc[q] += ww;
+    }
+    block_partials<kMaxDots>(acc, j + 2, part, gridDim.x);
+}
+
+// partials of (V_i, w), i <= j, and (w, w) for an assembled w
+__global__ void __launch_bounds__(kBS)
+dots_kernel(const double *__restrict__ w, const double *__restrict__ V, int64_t ng, int j, double *__restrict__ part)
+{
+    double acc[kMaxDots];
+#pragma unroll
+    for (int q = 0; q < kMaxDots; ++q) acc[q] = 0.0;
+    GRID_STRIDE(g, ng)
+    {
+        const double wg = w[g];
+#pragma unroll
+        for (int q = 0; q < kMaxDots - 1; ++q)
+            if (q <= j) acc[q] += V[q * ng + g] * wg;
+        const double ww = wg * wg;
+#pragma unroll
+        for (int q = 0; q < kMaxDots; ++q)
+            if (q == j + 1) acc[q] += ww;
+    }
+    block_partials<kMaxDots>(acc, j + 2, part, gridDim.x);
+}
+
+// h[q] = sum of stage[q * kStage ...] for q < nv
+__global__ void __launch_bounds__(kBS) sums_finalize(const double *__restrict__ stage, int nv, double *__restrict__ h)
+{
+    for (int q = 0; q < nv; ++q) {
+        __shared__ double red[kBS];
+        red[threadIdx.x] = stage[q * kStage + threadIdx.x];
+        __syncthreads();
+        for (int w = kBS / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) h[q] = red[0];
+        __syncthreads();
+    }
+}
+
+// w = (w - sum_{i <= j} h_i V_i) * scale
+__global__ void __launch_bounds__(kBS)
+orth_kernel(double *__restrict__ w, const double *__restrict__ V, int64_t ng, int j, const double *__restrict__ h,
+            double scale)
+{
+    double hq[kMaxDots];
+#pragma unroll
+    for (int q = 0; q < kMaxDots - 1; ++q) hq[q] = q <= j ? h[q] : 0.0;
+    GRID_STRIDE(g, ng)
+    {
+        double v = w[g];
+#pragma unroll
+        for (int q = 0; q < kMaxDots - 1; ++q)
+            if (q <= j) v -= hq[q] * V[q * ng + g];
+        w[g] = v * scale;
+    }
+}
+
+// x += sum_{i < k} y_i Z_i
+__global__ void __launch_bounds__(kBS)
+combine_kernel(double *__restrict__ x, const double *__restrict__ Z, int64_t ng, int k, const double *__restrict__ y)
+{
+    double yq[kMaxDots];
+#pragma unroll
+    for (int q = 0; q < kMaxDots; ++q) yq[q] = q < k ? y[q] : 0.0;
+    GRID_STRIDE(g, ng)
+    {
+        double v = x[g];
+#pragma unroll
+        for (int q = 0; q < kMaxDots; ++q)
+            if (q < k) v += yq[q] * Z[q * ng + g];
+        x[g] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kBS) scale_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t ng,
+                                                    double s)
+{
+    GRID_STRIDE(g, ng) out[g] = in[g] * s;
+}
+
+// ---------------------------------------------------------------- block-Jacobi CG kernels
+
+// x = 0, r = b (0 on Dirichlet nodes); partial (r, r)
+__global__ void __launch_bounds__(kBS)
+bj_init_kernel(const double *__restrict__ b, const double *__restrict__ dinv, double *__restrict__ x,
+               double *__restrict__ r, int64_t ng, double *__restrict__ part)
+{
+    double acc[1] = {0.0};
+    GRID_STRIDE(g, ng)
+    {
+        const double rg = dinv[g] == 0.0 ? 0.0 : b[g];
+        x[g] = 0.0;
+        r[g] = rg;
+        acc[0] += rg * rg;
+    }
+    block_partials<1>(acc, 1, part, gridDim.x);
+}
+
+// partial (r, z)
+__global__ void __launch_bounds__(kBS) bj_dot_kernel(const CgState *st, const double *__restrict__ r,
+                                                     const double *__restrict__ z, int64_t ng, double *__restrict__ part)
+{
+    if (st->done) return;
+    double acc[1] = {0.0};
+    GRID_STRIDE(g, ng) acc[0] += r[g] * z[g];
+    block_partials<1>(acc, 1, part, gridDim.x);
+}
+
+// first = 1: bb, tol2, rr from the (r, r) partials (run start)
+__global__ void __launch_bounds__(kBS) bj_start_finalize(CgState *st, const double *__restrict__ part, int nb, double tol)
+{
+    __shared__ double red[kBS];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nb; q += kBS) s += part[q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->bb = red[0];
+        st->rr = red[0];
+        st->tol2 = tol * tol * red[0];
+        st->it = 0;
+        st->status = 0;
+        st->beta = 0.0;
+        st->done = red[0] == 0.0 ? 1 : 0;
+    }
+}
+
+// rz_new from the partials: beta = rz_new / rz (0 on the first call), rz = rz_new
+__global__ void __launch_bounds__(kBS) bj_rz_finalize(CgState *st, const double *__restrict__ part, int nb, int first)
+{
+    if (st->done) return;
+    __shared__ double red[kBS];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nb; q += kBS) s += part[q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double rz = red[0];
+        if (!(rz > 0.0) || !isfinite(rz)) {
+            st->done = 2;
+            st->status = SEM_ERR_BREAKDOWN;
+            return;
+        }
+        st->beta = first ? 0.0 : rz / st->rz;
+        st->rz = rz;
+    }
+}
+
+// wg = Q^T rows; x += alpha p; r -= alpha wg; partial (r, r)
+__global__ void __launch_bounds__(kBS)
+bj_update_kernel(const CgState *__restrict__ st, const double *__restrict__ rows, double *__restrict__ x,
+                 double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ dinv, Lattice L,
+                 double *__restrict__ part)
+{
+    if (st->done) return;
+    const double alpha = st->alpha;
+    double acc[1] = {0.0};
+    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
+    {
+        if (dinv[g] == 0.0) continue;
+        const double wg = node_assemble_rows<0>(L, rows, gi, gj, gk);
+        x[g] += alpha * p[g];
+        const double rg = r[g] - alpha * wg;
+        r[g] = rg;
+        acc[0] += rg * rg;
+    }
+    block_partials<1>(acc, 1, part, gridDim.x);
+}
+
+// iteration count, convergence test on (r, r)
+__global__ void __launch_bounds__(kBS) bj_check_finalize(CgState *st, const double *__restrict__ part, int nb,
+                                                         double *hist)
+{
+    if (st->done) return;
+    __shared__ double red[kBS];
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nb; q += kBS) s += part[q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double rr = red[0];
+        const int it = st->it + 1;
+        st->it = it;
+        st->rr = rr;
+        if (hist && it < st->hist_len) hist[it] = sqrt(rr / st->bb);
+        if (!isfinite(rr)) {
+            st->done = 2;
+            st->status = SEM_ERR_BREAKDOWN;
+        } else if (rr <= st->tol2) {
+            st->done = 1;
+        } else if (it >= st->max_it) {
+            st->done = 3;
+        }
+    }
+}
+
+// p = z + beta p
+__global__ void __launch_bounds__(kBS) bj_p_kernel(const CgState *st, double *__restrict__ p,
+                                                   const double *__restrict__ z, int64_t ng)
+{
+    if (st->done) return;
+    const double beta = st->beta;
+    GRID_STRIDE(g, ng) p[g] = z[g] + beta * p[g];
+}
+
+}  // namespace mg
+
+// ---------------------------------------------------------------- preconditioner
+
+size_t hsmg_bufs_bytes(const Mesh &m)
+{
+    const Hsmg &h = *m.hsmg;
+    auto a = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t E = (size_t)m.E, Pm = (size_t)h.lat_m.P, Pc = 8;
+    return a(m.nl * 8) + a(E * Pm * 8) + 2 * a(h.ng_m * 8) + a(E * Pc * 8) + 2 * a(h.ng_c * 8);
+}
+
+HsmgBufs hsmg_bufs_carve(const Mesh &m, char *base)
+{
+    const Hsmg &h = *m.hsmg;
+    auto a = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t E = (size_t)m.E, Pm = (size_t)h.lat_m.P, Pc = 8;
+    HsmgBufs b{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        double *p = (double *)(base + off);
+        off += a(bytes);
+        return p;
+    };
+    b.rows_f = take(m.nl * 8);
+    b.rows_m = take(E * Pm * 8);
+    b.rm = take(h.ng_m * 8);
+    b.zm = take(h.ng_m * 8);
+    b.rows_c = take(E * Pc * 8);
+    b.rc = take(h.ng_c * 8);
+    b.tc = take(h.ng_c * 8);
+    return b;
+}
+
+namespace {
+
+template <int NP, int NPC>
+void launch_schwarz(const Mesh &m, const Lattice &L, const double *r, const double *fdm, double h1, double h2,
+                    double *rows, const double *J, const Lattice &Lc, double *rows_c, hipStream_t s)
+{
+    hipLaunchKernelGGL((mg::schwarz_kernel<NP, NPC>), dim3((unsigned)m.E), dim3(NP * NP * NP), 0, s, r, L, fdm, h1,
+                       h2, rows, J, Lc, rows_c);
+}
+
+// fine Schwarz (+ restriction to the mid level when restrict_mid)
+hipError_t fine_schwarz(const Mesh &m, const double *r, double h1, double h2, const HsmgBufs &b, bool restrict_mid,
+                        hipStream_t s)
+{
+    const Hsmg &h = *m.hsmg;
+#define SEM_FS(NP, NPM)                                                                                          \
+    case NP:                                                                                                     \
+        if (restrict_mid)                                                                                        \
+            launch_schwarz<NP, NPM>(m, m.lat, r, h.d_fdm_f, h1, h2, b.rows_f, h.d_Jfm, h.lat_m, b.rows_m, s);    \
+        else                                                                                                     \
+            launch_schwarz<NP, 0>(m, m.lat, r, h.d_fdm_f, h1, h2, b.rows_f, nullptr, h.lat_m, nullptr, s);       \
+        break;
+    switch (m.NP) {
+        SEM_FS(3, 2)
+        SEM_FS(4, 3)
+        SEM_FS(5, 4)
+        SEM_FS(6, 4)
+        SEM_FS(7, 4)
+        SEM_FS(8, 4)
+        SEM_FS(9, 4)
+        SEM_FS(10, 4)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef SEM_FS
+    return hipGetLastError();
+}
+
+hipError_t mid_schwarz(const Mesh &m, double h1, double h2, const HsmgBufs &b, hipStream_t s)
+{
+    const Hsmg &h = *m.hsmg;
+    switch (h.lat_m.NP) {
+    case 2: launch_schwarz<2, 2>(m, h.lat_m, b.rm, h.d_fdm_m, h1, h2, b.rows_m, h.d_Jmc, h.lat_c, b.rows_c, s); break;
+    case 3: launch_schwarz<3, 2>(m, h.lat_m, b.rm, h.d_fdm_m, h1, h2, b.rows_m, h.d_Jmc, h.lat_c, b.rows_c, s); break;
+    case 4: launch_schwarz<4, 2>(m, h.lat_m, b.rm, h.d_fdm_m, h1, h2, b.rows_m, h.d_Jmc, h.lat_c, b.rows_c, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t prolong_fine(const Mesh &m, const HsmgBufs &b, hipStream_t s)
+{
+    const Hsmg &h = *m.hsmg;
+#define SEM_PF(NP, NPM)                                                                                           \
+    case NP:                                                                                                      \
+        hipLaunchKernelGGL((mg::prolong_add_kernel<NP, NPM>), dim3((unsigned)m.E), dim3(NP * NP * NP), 0, s, b.zm, \
+                           h.lat_m, h.d_Jfm, m.lat, b.rows_f);                                                    \
+        break;
+    switch (m.NP) {
+        SEM_PF(3, 2)
+        SEM_PF(4, 3)
+        SEM_PF(5, 4)
+        SEM_PF(6, 4)
+        SEM_PF(7, 4)
+        SEM_PF(8, 4)
+        SEM_PF(9, 4)
+        SEM_PF(10, 4)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef SEM_PF
+    return hipGetLastError();
+}
+
+hipError_t coarse_solve(const Mesh &m, double h1, double h2, const HsmgBufs &b, hipStream_t s)
+{
+    const Hsmg &h = *m.hsmg;
+    const int nx = h.cn[0], ny = h.cn[1], nz = h.cn[2];
+    const int nb = cg_blocks(h.ng_c);
+    double *in = b.rc, *out = b.tc;
+    const int axes[6] = {0, 1, 2, 2, 1, 0};
+    for (int q = 0; q < 6; ++q) {
+        const int ax = axes[q];
+        hipLaunchKernelGGL(mg::coarse_axis_kernel, dim3(nb), dim3(kBS), 0, s, in, out, h.d_cS[ax], ax, q < 3 ? 1 : 0,
+                           nx, ny, nz, h.d_clam[0], h.d_clam[1], h.d_clam[2], h1, h2, q == 2 ? 1 : 0);
+        std::swap(in, out);
+    }
+    // six passes: the result is back in b.rc
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, double *z, const HsmgBufs &b, int levels,
+                      bool weighted, hipStream_t s)
+{
+    const Hsmg &h = *m.hsmg;
+    hipError_t e;
+    if (levels == 1) {
+        if ((e = fine_schwarz(m, r, h1, h2, b, false, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(mg::assemble_kernel, dim3(node_grid(m.lat)), dim3(kBS), 0, s, b.rows_f, m.lat,
+                           weighted ? 1 : 0, z, (const double *)nullptr, h.lat_c, (const double *)nullptr);
+        return hipGetLastError();
+    }
+    if ((e = fine_schwarz(m, r, h1, h2, b, true, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(mg::assemble_kernel, dim3(node_grid(h.lat_m)), dim3(kBS), 0, s, b.rows_m, h.lat_m, 0, b.rm,
+                       (const double *)nullptr, h.lat_c, (const double *)nullptr);
+    if ((e = mid_schwarz(m, h1, h2, b, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(mg::assemble_kernel, dim3(node_grid(h.lat_c)), dim3(kBS), 0, s, b.rows_c, h.lat_c, 0, b.rc,
+                       (const double *)nullptr, h.lat_c, (const double *)nullptr);
+    if ((e = coarse_solve(m, h1, h2, b, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(mg::assemble_kernel, dim3(node_grid(h.lat_m)), dim3(kBS), 0, s, b.rows_m, h.lat_m, 1, b.zm,
+                       (const double *)b.rc, h.lat_c, (const double *)h.d_Jmc);
+    if ((e = prolong_fine(m, b, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(mg::assemble_kernel, dim3(node_grid(m.lat)), dim3(kBS), 0, s, b.rows_f, m.lat, 1, z,
+                       (const double *)nullptr, h.lat_c, (const double *)nullptr);
+    return hipGetLastError();
+}
+
+}  // namespace sem
+
+// ---------------------------------------------------------------- solvers
+
+namespace sem {
+namespace {
+
+sem_status read_st(CgState &h, const CgState *d, hipStream_t s)
+{
+    SEM_HIP_TRY(hipMemcpyAsync(&h, d, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    SEM_HIP_TRY(hipStreamSynchronize(s));
+    return SEM_OK;
+}
+
+// sums of nv quantities from block partials part[q * nb + b] into host out
+sem_status reduce_to_host(const double *part, int nb, int nv, double *stage, double *hdev, double *out, hipStream_t s)
+{
+    SEM_HIP_TRY(cg_reduce(part, nb, nv, stage, s));
+    hipLaunchKernelGGL(mg::sums_finalize, dim3(1), dim3(kBS), 0, s, stage, nv, hdev);
+    SEM_HIP_TRY(hipGetLastError());
+    SEM_HIP_TRY(hipMemcpyAsync(out, hdev, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+    SEM_HIP_TRY(hipStreamSynchronize(s));
+    return SEM_OK;
+}
+
+#define SEM_TRY(x)                   \
+    do {                             \
+        sem_status _s = (x);         \
+        if (_s != SEM_OK) return _s; \
+    } while (0)
+
+}  // namespace
+
+size_t gmres_bufs_bytes(const Mesh &m, int mres)
+{
+    auto a = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t ng = (size_t)m.ng;
+    const size_t nb = (size_t)std::max<int64_t>(node_grid(m.lat), cg_blocks(m.ng));
+    return a((size_t)(mres + 1) * ng * 8) + a((size_t)mres * ng * 8) + a(nb * mg::kMaxDots * 8) +
+           a((size_t)mg::kMaxDots * kStage * 8) + 2 * a(mg::kMaxDots * 8) + hsmg_bufs_bytes(m);
+}
+
+GmresBufs gmres_bufs_carve(const Mesh &m, int mres, char *base)
+{
+    auto a = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t ng = (size_t)m.ng;
+    const size_t nb = (size_t)std::max<int64_t>(node_grid(m.lat), cg_blocks(m.ng));
+    GmresBufs g{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base + off;
+        off += a(bytes);
+        return p;
+    };
+    g.V = (double *)take((size_t)(mres + 1) * ng * 8);
+    g.Z = (double *)take((size_t)mres * ng * 8);
+    g.part = (double *)take(nb * mg::kMaxDots * 8);
+    g.stage = (double *)take((size_t)mg::kMaxDots * kStage * 8);
+    g.hdev = (double *)take(mg::kMaxDots * 8);
+    g.ydev = (double *)take(mg::kMaxDots * 8);
+    g.hb = hsmg_bufs_carve(m, base + off);
+    return g;
+}
+
+sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
+                            CgState *st, const GmresBufs &gb, hipStream_t s, sem_solve_report *rep, CgState &h)
+{
+    const int mres = o.restart > 0 ? std::min(o.restart, kGmresMaxRestart) : kGmresMaxRestart;
+    const int64_t ng = m.ng;
+    const int nbn = (int)node_grid(m.lat), nbf = cg_blocks(ng);
+    double hv[mg::kMaxDots], h2v[mg::kMaxDots];
+    std::vector<double> H((size_t)(mres + 1) * mres), cs(mres), sn(mres), g(mres + 1), y(mres);
+    auto Hs = [&](int r, int c) -> double & { return H[(size_t)r * mres + c]; };
+    h = CgState{};
+    h.max_it = o.max_iter;
+    // x = 0, r = b, |b|
+    SEM_HIP_TRY(hipMemsetAsync(v.x, 0, sizeof(double) * ng, s));
+    hipLaunchKernelGGL(mg::scale_kernel, dim3(nbf), dim3(kBS), 0, s, b, v.r, ng, 1.0);
+    hipLaunchKernelGGL(mg::dots_kernel, dim3(nbf), dim3(kBS), 0, s, v.r, gb.V, ng, -1, gb.part);
+    SEM_HIP_TRY(hipGetLastError());
+    SEM_TRY(reduce_to_host(gb.part, nbf, 1, gb.stage, gb.hdev, hv, s));
+    h.bb = hv[0];
+    h.tol2 = o.rel_tol * o.rel_tol * h.bb;
+    h.rr = h.true_rr = h.bb;
+    int hist_written = 0;
+    if (o.history && o.history_len > 0) o.history[hist_written++] = 1.0;
+    if (h.bb == 0.0) {
+        h.done = 1;
+        rep->iterations = 0;
+        rep->history_written = hist_written;
+        return SEM_OK;
+    }
+    const double bn = std::sqrt(h.bb), tol_abs = o.rel_tol * bn;
+    double beta = bn;
+    int it = 0, restarts = 0;
+    for (;;) {
+        hipLaunchKernelGGL(mg::scale_kernel, dim3(nbf), dim3(kBS), 0, s, v.r, gb.V, ng, 1.0 / beta);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        bool stop = false;
+        for (int j = 0; j < mres; ++j) {
+            double *Vj = gb.V + (size_t)j * ng, *Vn = gb.V + (size_t)(j + 1) * ng, *Zj = gb.Z + (size_t)j * ng;
+            SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, Vj, Zj, gb.hb, 3, true, s));
+            SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, Zj, v.w, nullptr, s));
+            hipLaunchKernelGGL(mg::assemble_dots_kernel, dim3(nbn), dim3(kBS), 0, s, v.w, m.lat, Vn, gb.V, ng, j,
+                               gb.part);
+            SEM_HIP_TRY(hipGetLastError());
+            SEM_TRY(reduce_to_host(gb.part, nbn, j + 2, gb.stage, gb.hdev, hv, s));
+            double ww = hv[j + 1], hh = 0.0;
+            for (int i = 0; i <= j; ++i) hh += hv[i] * hv[i];
+            double beta2 = ww - hh;
+            for (int i = 0; i <= j; ++i) Hs(i, j) = hv[i];
+            if (!(beta2 >= 0.25 * ww)) {
+                // second classical Gram-Schmidt pass (the new direction lost
+                // more than half its norm to the projections)
+                hipLaunchKernelGGL(mg::orth_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.hdev, 1.0);
+                hipLaunchKernelGGL(mg::dots_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.part);
+                SEM_HIP_TRY(hipGetLastError());
+                SEM_TRY(reduce_to_host(gb.part, nbf, j + 2, gb.stage, gb.hdev, h2v, s));
+                double h2 = 0.0;
+                for (int i = 0; i <= j; ++i) {
+                    Hs(i, j) += h2v[i];
+                    h2 += h2v[i] * h2v[i];
+                }
+                beta2 = h2v[j + 1] - h2;
+            }
+            if (!std::isfinite(beta2)) {
+                h.done = 2;
+                rep->iterations = it;
+                return SEM_OK;
+            }
+            const double bj = beta2 > 0.0 ? std::sqrt(beta2) : 0.0;
+            if (bj > 0.0)
+                hipLaunchKernelGGL(mg::orth_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.hdev, 1.0 / bj);
+            Hs(j + 1, j) = bj;
+            for (int i = 0; i < j; ++i) {
+                const double a = Hs(i, j), c = Hs(i + 1, j);
+                Hs(i, j) = cs[i] * a + sn[i] * c;
+                Hs(i + 1, j) = -sn[i] * a + cs[i] * c;
+            }
+            const double den = std::hypot(Hs(j, j), Hs(j + 1, j));
+            cs[j] = Hs(j, j) / den;
+            sn[j] = Hs(j + 1, j) / den;
+            Hs(j, j) = den;
+            Hs(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            k = j + 1;
+            if (o.history && hist_written < o.history_len) o.history[hist_written++] = std::fabs(g[j + 1]) / bn;
+            if (std::fabs(g[j + 1]) <= tol_abs || it >= o.max_iter || bj == 0.0) {
+                stop = true;
+                break;
+            }
+        }
+        // x += Z y, y from the triangular system H y = g
+        for (int i = k - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int c = i + 1; c < k; ++c) acc -= Hs(i, c) * y[c];
+            y[i] = acc / Hs(i, i);
+        }
+        SEM_HIP_TRY(hipMemcpyAsync(gb.ydev, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(mg::combine_kernel, dim3(nbf), dim3(kBS), 0, s, v.x, gb.Z, ng, k, gb.ydev);
+        // true residual r = b - S x
+        SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.x, v.w, nullptr, s));
+        SEM_HIP_TRY(cg_resid<double>(m, v, b, v.r, st, s));
+        CgState t;
+        SEM_TRY(read_st(t, st, s));
+        h.true_rr = h.rr = t.true_rr;
+        if (!std::isfinite(h.true_rr)) {
+            h.done = 2;
+            break;
+        }
+        if (h.true_rr <= h.tol2) {
+            h.done = 1;
+            break;
+        }
+        if (it >= o.max_iter) {
+            h.done = 3;
+            break;
+        }
+        (void)stop;
+        ++restarts;
+        beta = std::sqrt(h.true_rr);
+    }
+    h.it = it;
+    rep->iterations = it;
+    rep->restarts = restarts;
+    rep->outer_iterations = restarts + 1;
+    rep->history_written = hist_written;
+    return SEM_OK;
+}
+
+sem_status solve_pcg_block_jacobi(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
+                                  double *z, CgState *st, const HsmgBufs &hb, double *hist, int hist_len,
+                                  int check_every, hipStream_t s, sem_solve_report *rep, CgState &h)
+{
+    const int64_t ng = m.ng;
+    const int nbf = cg_blocks(ng), nbn = (int)node_grid(m.lat);
+    CgState init{};
+    init.max_it = o.max_iter;
+    init.hist_len = hist_len;
+    SEM_HIP_TRY(hipMemcpyAsync(st, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(mg::bj_init_kernel, dim3(nbf), dim3(kBS), 0, s, b, v.dinv, v.x, v.r, ng, v.part_b);
+    hipLaunchKernelGGL(mg::bj_start_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nbf, o.rel_tol);
+    if (hist && hist_len > 0) {
+        const double one = 1.0;
+        SEM_HIP_TRY(hipMemcpyAsync(hist, &one, sizeof(double), hipMemcpyHostToDevice, s));
+        SEM_HIP_TRY(hipStreamSynchronize(s));
+    }
+    auto direction = [&](int first) -> sem_status {
+        SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, v.r, z, hb, 1, false, s));
+        hipLaunchKernelGGL(mg::bj_dot_kernel, dim3(nbf), dim3(kBS), 0, s, st, v.r, z, ng, v.part_b);
+        hipLaunchKernelGGL(mg::bj_rz_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nbf, first);
+        if (first)
+            hipLaunchKernelGGL(mg::scale_kernel, dim3(nbf), dim3(kBS), 0, s, z, v.p, ng, 1.0);
+        else
+            hipLaunchKernelGGL(mg::bj_p_kernel, dim3(nbf), dim3(kBS), 0, s, st, v.p, z, ng);
+        SEM_HIP_TRY(hipGetLastError());
+        return SEM_OK;
+    };
+    SEM_TRY(direction(1));
+    int restarts = 0;
+    for (;;) {
+        for (;;) {
+            SEM_TRY(read_st(h, st, s));
+            if (h.done) break;
+            for (int q = 0; q < check_every; ++q) {
+                SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.p, v.w, v.part_e, s, &st->done));
+                SEM_HIP_TRY(cg_alpha(m, v.part_e, v.stage, st, s));
+                hipLaunchKernelGGL(mg::bj_update_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,
+                                   m.lat, v.part_b);
+                hipLaunchKernelGGL(mg::bj_check_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nbn, hist);
+                SEM_TRY(direction(0));
+            }
+        }
+        if (h.done != 1 || h.bb == 0.0) break;
+        SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.x, v.w, nullptr, s));
+        SEM_HIP_TRY(cg_resid<double>(m, v, b, v.r, st, s));
+        SEM_TRY(read_st(h, st, s));
+        if (h.true_rr <= h.tol2 || restarts == 3 || h.it >= h.max_it) break;
+        ++restarts;   // the recursive residual drifted: restart from x with the true residual
+        CgState patch = h;
+        patch.done = 0;
+        patch.rr = h.true_rr;
+        SEM_HIP_TRY(hipMemcpyAsync(st, &patch, sizeof(CgState), hipMemcpyHostToDevice, s));
+        SEM_TRY(direction(1));
+    }
+    if (h.done != 1 && h.bb > 0.0) {
+        SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.x, v.w, nullptr, s));
+        SEM_HIP_TRY(cg_resid<double>(m, v, b, v.r, st, s));
+        SEM_TRY(read_st(h, st, s));
+    }
+    rep->iterations = h.it;
+    rep->restarts = restarts;
+    return SEM_OK;
+}
+
+}  // namespace sem
+
+// ---------------------------------------------------------------- C ABI
+
+using namespace sem;
+
+extern "C" {
+
+sem_status sem_precond_workspace_bytes(const sem_mesh *mesh, size_t *bytes)
+{
+    if (!mesh || !bytes) return fail(SEM_ERR_INVALID_ARG, "null mesh or bytes");
+    const Mesh &m = mesh->m;
+    if (!m.hsmg) return fail(SEM_ERR_INVALID_ARG, "the mesh was created without SEM_PREP_HSMG");
+    const size_t v = ((size_t)m.ng * 8 + 255) & ~(size_t)255;
+    *bytes = hsmg_bufs_bytes(m) + 2 * v;
+    return SEM_OK;
+}
+
+sem_status sem_precond_apply(const sem_mesh *mesh, int kind, double h1, double h2, const double *r_local,
+                             double *z_local, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!mesh || !r_local || !z_local || !workspace) return fail(SEM_ERR_INVALID_ARG, "null argument");
+    const Mesh &m = mesh->m;
+    if (!m.hsmg) return fail(SEM_ERR_INVALID_ARG, "the mesh was created without SEM_PREP_HSMG");
+    if (!(h1 > 0.0) || !(h2 >= 0.0) || !std::isfinite(h1) || !std::isfinite(h2))
+        return fail(SEM_ERR_INVALID_ARG, "the preconditioners need h1 > 0 and h2 >= 0");
+    int levels = 3;
+    bool weighted = true;
+    switch (kind) {
+    case SEM_PRECOND_HSMG: break;
+    case SEM_PRECOND_SCHWARZ: levels = 1; break;
+    case SEM_PRECOND_BLOCK_JACOBI: levels = 1; weighted = false; break;
+    default: return fail(SEM_ERR_INVALID_ARG, "unknown preconditioner kind");
+    }
+    size_t need = 0;
+    sem_status st = sem_precond_workspace_bytes(mesh, &need);
+    if (st != SEM_OK) return st;
+    if (ws_bytes < need) return fail(SEM_ERR_INVALID_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t v = ((size_t)m.ng * 8 + 255) & ~(size_t)255;
+    char *base = (char *)workspace;
+    double *rg = (double *)base, *zg = (double *)(base + v);
+    HsmgBufs hb = hsmg_bufs_carve(m, base + 2 * v);
+    SEM_HIP_TRY(cg_gather<double>(m, r_local, rg, s));
+    SEM_HIP_TRY(hsmg_apply(m, h1, h2, rg, zg, hb, levels, weighted, s));
+    SEM_HIP_TRY(cg_scatter<double>(m, zg, z_local, s));
+    return SEM_OK;
+}
+
+}  // extern "C"

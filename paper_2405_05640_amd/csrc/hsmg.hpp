@@ -1,0 +1,85 @@
+// hsmg.hpp -- internal interface of the hybrid Schwarz multigrid
+// preconditioner and the flexible GMRES solver (the paper's pressure solver,
+// section 3.1: restarted GMRES with a hybrid-Schwarz multigrid
+// preconditioner; CG with block-Jacobi for the velocity solves).
+#pragma once
+
+#include "cg.hpp"
+#include "sem_internal.hpp"
+
+namespace sem {
+
+constexpr int kHsmgMidOrder = 3;      // p-multigrid levels N -> 3 -> 1
+constexpr int kGmresMaxRestart = 30;  // upper bound on the restart length m
+
+// Device data of the preconditioner (built by SEM_PREP_HSMG).
+//  - fdm_f, fdm_m: per element the separable local solver of the fine and
+//    mid levels, [E][3 * NP * NP + 3 * NP] doubles: S_x, S_y, S_z (row a =
+//    node, column q = mode; B-orthonormal columns) then the eigenvalues
+//    l_x, l_y, l_z.  A node on a Dirichlet face has a zero row and its mode
+//    slot a zero column with eigenvalue +inf (its inverse is 0).
+//  - Jfm [(N+1) x 4], Jmc [4 x 2]: GLL-to-GLL interpolation, row = fine node.
+//  - coarse (order 1): per axis S [n x n] and eigenvalues of the global
+//    separable operator, same conventions; n = nodes of the order-1 lattice.
+struct Hsmg {
+    int Nm = kHsmgMidOrder;
+    Lattice lat_m{}, lat_c{};     // mid and coarse lattices (closed form, no tables)
+    int64_t ng_m = 0, ng_c = 0;
+    double *d_fdm_f = nullptr, *d_fdm_m = nullptr;
+    double *d_Jfm = nullptr, *d_Jmc = nullptr;
+    double *d_cS[3] = {nullptr, nullptr, nullptr};
+    double *d_clam[3] = {nullptr, nullptr, nullptr};
+    int cn[3] = {0, 0, 0};
+    size_t bytes = 0;
+};
+
+// host setup from the mesh description (vertices) and the built mesh
+sem_status hsmg_setup(const sem_mesh_desc &d, Mesh &m);
+void hsmg_release(Mesh &m);
+
+// Work buffers of one preconditioner application.
+struct HsmgBufs {
+    double *rows_f;   // fine local rows (n_local): Schwarz corrections, then + prolongation
+    double *rows_m;   // mid local rows (E * 64): restricted residual, then Schwarz corrections
+    double *rm;       // mid assembled residual (ng_m)
+    double *zm;       // mid assembled correction (ng_m)
+    double *rows_c;   // coarse local rows (E * 8)
+    double *rc;       // coarse assembled residual (ng_c)
+    double *tc;       // coarse scratch (ng_c)
+};
+size_t hsmg_bufs_bytes(const Mesh &m);
+HsmgBufs hsmg_bufs_carve(const Mesh &m, char *base);
+
+// z = M r on assembled fine vectors (z and r distinct; both zero on
+// Dirichlet nodes).  weighted = false skips the 1/mult averaging of the
+// fine level and every coarser level (block-Jacobi use: levels = 1).
+// levels: 1 = fine Schwarz only, 3 = the full three-level cycle.
+hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, double *z, const HsmgBufs &b,
+                      int levels, bool weighted, hipStream_t s);
+
+// Flexible GMRES work buffers: V [(m+1) ng], Z [m ng], block partials,
+// reduction stage, device vectors of inner products and of y.
+struct GmresBufs {
+    double *V, *Z, *part, *stage, *hdev, *ydev;
+    HsmgBufs hb;
+};
+size_t gmres_bufs_bytes(const Mesh &m, int mres);
+GmresBufs gmres_bufs_carve(const Mesh &m, int mres, char *base);
+
+// Flexible GMRES(m) with the hybrid Schwarz multigrid preconditioner on
+// S x = b (assembled b; x from zero).  v: x, r (assembled), w (row-layout
+// operator output), dinv, part_b, stage of the caller's workspace; st: a
+// device CgState used for the true residual.  Fills h (bb, tol2, rr,
+// true_rr, done) and rep (iterations, restarts, history).
+sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
+                            CgState *st, const GmresBufs &gb, hipStream_t s, sem_solve_report *rep, CgState &h);
+
+// CG with the block-Jacobi preconditioner (unweighted element-local
+// separable solves); z: assembled scratch vector; same conventions as the
+// FP64 Jacobi-PCG (device scalars, host polls every check_every iterations,
+// true-residual restarts).
+sem_status solve_pcg_block_jacobi(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
+                                  double *z, CgState *st, const HsmgBufs &hb, double *hist, int hist_len,
+                                  int check_every, hipStream_t s, sem_solve_report *rep, CgState &h);
+
+}  // namespace sem

@@ -12,6 +12,7 @@
 #include <memory>
 #include <new>
 
+#include "hsmg.hpp"
 #include "sem_internal.hpp"
 
 namespace sem {
@@ -47,7 +48,7 @@ static void legendre3(int N, double x, double &p, double &dp, double &ddp)
 
 // GLL nodes (endpoints and the zeros of P_N', by Newton on P_N') and weights
 // 2 / (N (N+1) P_N^2).
-static void gll_rule(int N, std::vector<double> &x, std::vector<double> &w)
+void gll_rule(int N, std::vector<double> &x, std::vector<double> &w)
 {
     x.assign(N + 1, 0.0);
     w.assign(N + 1, 0.0);
@@ -80,7 +81,7 @@ static void gll_rule(int N, std::vector<double> &x, std::vector<double> &w)
 // Derivative of the Lagrange basis at the nodes in barycentric form:
 // D_ij = (lam_j / lam_i) / (x_i - x_j) for i != j, D_ii = -sum_{j!=i} D_ij,
 // lam_j = 1 / prod_{k != j} (x_j - x_k).
-static std::vector<double> deriv_matrix(const std::vector<double> &x)
+std::vector<double> deriv_matrix(const std::vector<double> &x)
 {
     const int n = (int)x.size();
     std::vector<double> lam(n, 1.0), D(n * n, 0.0);
@@ -188,6 +189,7 @@ static void release(Mesh &m)
                     m.d_G32, m.d_B32, m.d_Gbf, m.d_Bbf, m.d_Gh, m.d_Bh, m.d_hscale, m.d_scratch, m.d_tab};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    hsmg_release(m);
 }
 
 #define SEM_TRY(x)                      \
@@ -404,6 +406,10 @@ static sem_status build(const sem_mesh_desc &d, Mesh &m)
         SEM_TRY(upload(&m.d_Gh, gh.data(), gh.size(), acc));
         SEM_TRY(upload(&m.d_Bh, bh.data(), bh.size(), acc));
         SEM_TRY(upload(&m.d_hscale, sc.data(), sc.size(), acc));
+    }
+    if (d.prepare & SEM_PREP_HSMG) {
+        SEM_TRY(hsmg_setup(d, m));
+        acc += m.hsmg->bytes;
     }
     m.scratch_len = dot_blocks(m) + 1;
     {

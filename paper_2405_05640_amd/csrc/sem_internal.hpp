@@ -25,6 +25,12 @@ sem_status fail(sem_status st, const std::string &msg);
 
 constexpr int kMaxOrder = 15;
 
+struct Hsmg;
+
+// GLL rule and derivative matrix of the library (mesh.cpp)
+void gll_rule(int N, std::vector<double> &x, std::vector<double> &w);
+std::vector<double> deriv_matrix(const std::vector<double> &x);
+
 // Device-resident mesh.  Local fields are [E][NP][NP][NP], i fastest.
 struct Mesh {
     int nelx = 0, nely = 0, nelz = 0, N = 0, NP = 0;
@@ -55,6 +61,7 @@ struct Mesh {
     float *d_hscale = nullptr;
     double *d_scratch = nullptr;  // small device scratch for sem_dot partials
     int32_t scratch_len = 0;
+    Hsmg *hsmg = nullptr;         // multigrid preconditioner (SEM_PREP_HSMG)
     size_t device_bytes = 0;
     uint64_t serial = 0;          // unique per created mesh (process-wide counter)
 

@@ -24,6 +24,7 @@
 #include <mutex>
 
 #include "cg.hpp"
+#include "hsmg.hpp"
 #include "nn.hpp"
 #include "sem_internal.hpp"
 
@@ -46,6 +47,8 @@ struct Workspace {
     double *z, *q;           // flexible CG: smoother output and S p (assembled)
     CgState *st64, *st32;
     double *hist;
+    GmresBufs gm;            // flexible GMRES with the multigrid preconditioner
+    HsmgBufs hb;             // block-Jacobi preconditioner buffers
     size_t bytes;
 };
 
@@ -59,10 +62,12 @@ bool uses_fcg(int form)
     return form == SEM_FORM_FCG_LEARNED || form == SEM_FORM_FCG_INNER_FP32 || form == SEM_FORM_FCG_INNER_BF16;
 }
 // forms that need the two extra assembled FP64 vectors z and q
-bool uses_zq(int form) { return uses_fcg(form) || form == SEM_FORM_PCG_1RED; }
+bool uses_zq(int form) { return uses_fcg(form) || form == SEM_FORM_PCG_1RED || form == SEM_FORM_PCG_BLOCK_JACOBI; }
+int gmres_restart(const sem_solve_opts &o) { return o.restart > 0 ? std::min(o.restart, kGmresMaxRestart) : kGmresMaxRestart; }
 
-Workspace carve(const Mesh &m, int form, int hist_len, char *base)
+Workspace carve(const Mesh &m, const sem_solve_opts &o, int hist_len, char *base)
 {
+    const int form = o.form;
     Workspace ws{};
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
@@ -97,6 +102,15 @@ Workspace carve(const Mesh &m, int form, int hist_len, char *base)
         ws.v32.part_e = ws.v64.part_e;
         ws.v32.part_b = ws.v64.part_b;
         ws.v32.stage = ws.v64.stage;
+    }
+    if (form == SEM_FORM_GMRES_HSMG) {
+        const int mres = gmres_restart(o);
+        char *p = take(gmres_bufs_bytes(m, mres));
+        if (base) ws.gm = gmres_bufs_carve(m, mres, p);
+    }
+    if (form == SEM_FORM_PCG_BLOCK_JACOBI) {
+        char *p = take(hsmg_bufs_bytes(m));
+        if (base) ws.hb = hsmg_bufs_carve(m, p);
     }
     ws.bytes = off;
     return ws;
@@ -148,6 +162,14 @@ sem_status check_opts(const Mesh &m, const sem_solve_opts *o)
             return fail(SEM_ERR_UNSUPPORTED, "the bf16 operator needs order N = 7");
         if (!(o->inner_tol > 0.0 && o->inner_tol < 1.0))
             return fail(SEM_ERR_INVALID_ARG, "inner_tol (the replacement threshold) must be in (0, 1)");
+        return SEM_OK;
+    case SEM_FORM_GMRES_HSMG:
+    case SEM_FORM_PCG_BLOCK_JACOBI:
+        if (!m.hsmg) return fail(SEM_ERR_INVALID_ARG, "this form needs a mesh created with SEM_PREP_HSMG");
+        if (!(o->h1 > 0.0)) return fail(SEM_ERR_INVALID_ARG, "the multigrid and block-Jacobi forms need h1 > 0");
+        if (o->h2 < 0.0) return fail(SEM_ERR_INVALID_ARG, "h2 must be >= 0");
+        if (o->restart < 0 || o->restart > kGmresMaxRestart)
+            return fail(SEM_ERR_INVALID_ARG, "restart must be in 0.." + std::to_string(kGmresMaxRestart));
         return SEM_OK;
     case SEM_FORM_FCG_LEARNED:
         if (!o->smoother) return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_FCG_LEARNED needs opts.smoother");
@@ -476,7 +498,7 @@ sem_status sem_solve_workspace_bytes(const sem_mesh *mesh, const sem_solve_opts 
 {
     if (!mesh || !bytes) return fail(SEM_ERR_INVALID_ARG, "null mesh or bytes");
     SEM_TRY(check_opts(mesh->m, opts));
-    *bytes = carve(mesh->m, opts->form, hist_len_for(*opts), nullptr).bytes;
+    *bytes = carve(mesh->m, *opts, hist_len_for(*opts), nullptr).bytes;
     return SEM_OK;
 }
 
@@ -489,7 +511,7 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
     SEM_TRY(check_opts(m, opts));
     std::memset(rep, 0, sizeof(*rep));
     const int hist_len = hist_len_for(*opts);
-    Workspace ws = carve(m, opts->form, hist_len, (char *)workspace);
+    Workspace ws = carve(m, *opts, hist_len, (char *)workspace);
     if (ws_bytes < ws.bytes)
         return fail(SEM_ERR_INVALID_ARG, "workspace too small: need " + std::to_string(ws.bytes) + " bytes");
     hipStream_t s = (hipStream_t)stream;
@@ -512,6 +534,11 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
         SEM_TRY(solve_pcg1(m, *opts, ws, hist_len, s, check_every, rep, h));
     else if (opts->form == SEM_FORM_RELIABLE_FP32 || opts->form == SEM_FORM_RELIABLE_BF16)
         SEM_TRY(solve_reliable(m, *opts, ws, hist_len, s, check_every, rep, h));
+    else if (opts->form == SEM_FORM_GMRES_HSMG)
+        SEM_TRY(solve_gmres_hsmg(m, *opts, ws.v64, ws.b64, ws.st64, ws.gm, s, rep, h));
+    else if (opts->form == SEM_FORM_PCG_BLOCK_JACOBI)
+        SEM_TRY(solve_pcg_block_jacobi(m, *opts, ws.v64, ws.b64, ws.z, ws.st64, ws.hb, ws.hist, hist_len, check_every,
+                                       s, rep, h));
     else if (opts->form == SEM_FORM_FCG_LEARNED)
         SEM_TRY(solve_fcg(m, opts->smoother->s, *opts, ws.v64, ws.b64, ws.z, ws.q, ws.st64, ws.hist, hist_len,
                           check_every, s, rep, h));
@@ -522,7 +549,8 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
     rep->rel_res = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
     rep->true_rel_res = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
     if (opts->history && opts->history_len > 0 &&
-        (opts->form == SEM_FORM_JACOBI_PCG || opts->form == SEM_FORM_PCG_1RED || uses_fcg(opts->form))) {
+        (opts->form == SEM_FORM_JACOBI_PCG || opts->form == SEM_FORM_PCG_1RED || opts->form == SEM_FORM_PCG_BLOCK_JACOBI ||
+         uses_fcg(opts->form))) {
         const int n = std::min(opts->history_len, std::min(h.it + 1, hist_len));
         SEM_HIP_TRY(hipMemcpyAsync(opts->history, ws.hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         SEM_HIP_TRY(hipStreamSynchronize(s));
@@ -565,7 +593,7 @@ sem_status sem_pcg_snapshots(const sem_mesh *mesh, const sem_solve_opts *opts, c
             return fail(SEM_ERR_INVALID_ARG, "iters must be non-negative and ascending");
     std::memset(rep, 0, sizeof(*rep));
     const int hist_len = hist_len_for(o);
-    Workspace ws = carve(m, o.form, hist_len, (char *)workspace);
+    Workspace ws = carve(m, o, hist_len, (char *)workspace);
     if (ws_bytes < ws.bytes)
         return fail(SEM_ERR_INVALID_ARG, "workspace too small: need " + std::to_string(ws.bytes) + " bytes");
     hipStream_t s = (hipStream_t)stream;
@@ -775,7 +803,7 @@ sem_status sem_pcg_solve_noalloc(const sem_mesh *mesh, const sem_solve_opts *opt
     int dev = 0;
     SEM_HIP_TRY(hipGetDevice(&dev));
     if (dev != m.device) return fail(SEM_ERR_INVALID_ARG, "the mesh lives on another device than the current one");
-    const size_t need = carve(m, opts->form, hist_len_for(*opts), nullptr).bytes;
+    const size_t need = carve(m, *opts, hist_len_for(*opts), nullptr).bytes;
     if (need > kNoAllocScratchBytes)
         return fail(SEM_ERR_INVALID_ARG, "solve needs " + std::to_string(need) + " bytes of workspace, more than the " +
                                              std::to_string(kNoAllocScratchBytes) + "-byte static scratch");

@@ -20,10 +20,11 @@ LIB_PATH = os.path.join(_HERE, "libsem.so")
 SEM_OK, SEM_ERR_INVALID_ARG, SEM_ERR_OUT_OF_MEMORY, SEM_ERR_HIP, SEM_ERR_NOT_CONVERGED, \
     SEM_ERR_BREAKDOWN, SEM_ERR_UNSUPPORTED = range(7)
 SEM_F64, SEM_F32, SEM_BF16, SEM_BF16_SPLIT = 0, 1, 2, 3
-SEM_PREP_F32, SEM_PREP_BF16 = 1, 2
+SEM_PREP_F32, SEM_PREP_BF16, SEM_PREP_HSMG = 1, 2, 4
 FIELD_GLO_NUM, FIELD_MULT, FIELD_MASK, FIELD_G, FIELD_B, FIELD_XYZ, FIELD_GLL, FIELD_DERIV = range(8)
 (FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED, FORM_FCG_INNER_FP32, FORM_FCG_INNER_BF16,
- FORM_RELIABLE_FP32, FORM_RELIABLE_BF16, FORM_PCG_1RED) = range(9)
+ FORM_RELIABLE_FP32, FORM_RELIABLE_BF16, FORM_PCG_1RED, FORM_GMRES_HSMG, FORM_PCG_BLOCK_JACOBI) = range(11)
+PRECOND_HSMG, PRECOND_SCHWARZ, PRECOND_BLOCK_JACOBI = 0, 1, 2
 SMOOTHER_PARAMS = 8208
 NOALLOC_SCRATCH_BYTES = 32 << 20    # SEM_NOALLOC_SCRATCH_BYTES
 
@@ -33,7 +34,8 @@ EXPORTED_SYMBOLS = [
     "sem_pcg_solve", "sem_last_error", "sem_version", "sem_smoother_create", "sem_smoother_destroy",
     "sem_smoother_set_weights", "sem_smoother_get_weights", "sem_smoother_apply", "sem_smoother_loss_grad",
     "sem_smoother_train_step", "sem_pcg_snapshots", "sem_pcg_solve_batched", "sem_solve_workspace_bytes_batched",
-    "sem_smoother_get_state", "sem_smoother_set_state", "sem_pcg_solve_noalloc",
+    "sem_smoother_get_state", "sem_smoother_set_state", "sem_pcg_solve_noalloc", "sem_precond_workspace_bytes",
+    "sem_precond_apply",
 ]
 
 
@@ -63,7 +65,7 @@ class SolveOpts(ctypes.Structure):
                 ("form", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("smoother", ctypes.c_void_p),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int32),
-                ("inner_iters", ctypes.c_int32)]
+                ("inner_iters", ctypes.c_int32), ("restart", ctypes.c_int32)]
 
 
 class SmootherDesc(ctypes.Structure):
@@ -111,6 +113,8 @@ def lib():
             "sem_pcg_solve": [vp, ctypes.POINTER(SolveOpts), vp, vp, vp, ctypes.c_size_t,
                               ctypes.POINTER(SolveReport), vp],
             "sem_pcg_solve_noalloc": [vp, ctypes.POINTER(SolveOpts), vp, vp, ctypes.POINTER(SolveReport), vp],
+            "sem_precond_workspace_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
+            "sem_precond_apply": [vp, ctypes.c_int, dbl, dbl, vp, vp, vp, ctypes.c_size_t, vp],
             "sem_smoother_create": [vp, ctypes.POINTER(SmootherDesc), ctypes.POINTER(vp)],
             "sem_smoother_destroy": [vp],
             "sem_smoother_set_weights": [vp, vp, ctypes.c_size_t],
@@ -274,12 +278,26 @@ class Mesh:
                              _want(out, "f64", 1, "out"), _stream()))
         return out
 
+    def precond(self, r, z, kind=PRECOND_HSMG, h1=1.0, h2=0.0, workspace=None):
+        """z = M r for a continuous, masked local r (sem_precond_apply)."""
+        import torch
+        n = ctypes.c_size_t()
+        _check(lib().sem_precond_workspace_bytes(self._h, ctypes.byref(n)))
+        if workspace is None:
+            workspace = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        if workspace.numel() * workspace.element_size() < n.value:
+            raise ValueError("workspace too small")
+        _check(lib().sem_precond_apply(self._h, int(kind), float(h1), float(h2), _want(r, "f64", self.n_local, "r"),
+                                       _want(z, "f64", self.n_local, "z"), ctypes.c_void_p(workspace.data_ptr()),
+                                       workspace.numel() * workspace.element_size(), _stream()))
+        return z
+
     def solve_opts(self, h1=1.0, h2=0.0, rel_tol=1e-10, max_iter=20000, check_every=16,
                    form=FORM_JACOBI_PCG, max_outer=30, inner_tol=1e-4, smoother=None, history=None,
-                   inner_iters=8):
+                   inner_iters=8, restart=0):
         o = SolveOpts()
         o.h1, o.h2, o.rel_tol, o.max_iter, o.check_every = h1, h2, rel_tol, max_iter, check_every
-        o.form, o.max_outer, o.inner_tol, o.inner_iters = form, max_outer, inner_tol, inner_iters
+        o.form, o.max_outer, o.inner_tol, o.inner_iters, o.restart = form, max_outer, inner_tol, inner_iters, restart
         o.smoother = smoother._h.value if smoother is not None else None
         if history is not None:
             o.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

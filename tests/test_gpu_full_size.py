@@ -4,7 +4,8 @@ configuration the benchmark times.  The oracle handles this size directly,
 so every output is compared, not a sample: numbering bit-exact, the operator
 within 1e-12 (max-norm, relative), the gather-scatter bit-exact, and every
 solver form (FP64, single-reduction, FP32 and split-BF16 defect correction,
-nested flexible CG with FP32 and BF16 inner steps, reliable updates) to an
+nested flexible CG with FP32 and BF16 inner steps, reliable updates, GMRES
+with the hybrid Schwarz multigrid preconditioner, block-Jacobi CG) to an
 FP64 true residual of 1e-10 as evaluated by the oracle, with its distance
 to the FP64 solution reported per precision."""
 import numpy as np
@@ -20,7 +21,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def c1():
     print("building the 32^3 N=7 deformed cube (oracle and library)", flush=True)
-    return pair(wl.deformed_cube(32, 7), prepare=sem.SEM_PREP_F32 | sem.SEM_PREP_BF16)
+    return pair(wl.deformed_cube(32, 7), prepare=sem.SEM_PREP_F32 | sem.SEM_PREP_BF16 | sem.SEM_PREP_HSMG)
 
 
 def test_full_size_numbering_operator_dssum(c1):
@@ -78,7 +79,9 @@ FORMS = [("fp64_pcg", sem.FORM_JACOBI_PCG, {}),
          ("fcg_inner_fp32", sem.FORM_FCG_INNER_FP32, {"inner_iters": 8, "inner_tol": 0.0}),
          ("fcg_inner_bf16", sem.FORM_FCG_INNER_BF16, {"inner_iters": 8, "inner_tol": 0.0}),
          ("reliable_fp32", sem.FORM_RELIABLE_FP32, {"inner_tol": 0.1}),
-         ("reliable_bf16split", sem.FORM_RELIABLE_BF16, {"inner_tol": 0.1})]
+         ("reliable_bf16split", sem.FORM_RELIABLE_BF16, {"inner_tol": 0.1}),
+         ("gmres_hsmg", sem.FORM_GMRES_HSMG, {}),
+         ("pcg_block_jacobi", sem.FORM_PCG_BLOCK_JACOBI, {})]
 
 
 @pytest.mark.parametrize("name,form,kw", FORMS, ids=[f[0] for f in FORMS])
