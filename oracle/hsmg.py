@@ -63,7 +63,10 @@ combines them): for a fine residual r,
 
   z = Sw_0(r) + P_01 [ Sw_1(R_10 r) + P_12 C^-1 R_21 R_10 r ]
 
-with Sw_l the level-l Schwarz smoother and C^-1 the coarse solve.
+with Sw_l the level-l Schwarz smoother and C^-1 the coarse solve.  In the
+symmetric variant each Sw_l = W^1/2 K_l W^1/2 (W = 1/mult) instead of W K_l,
+which makes the whole preconditioner symmetric positive definite, so that CG
+can use it.
 
 Flexible GMRES(m) with right preconditioning (Saad 2003, Algorithm 9.6),
 modified Gram-Schmidt, Givens rotations, restarts from the true residual;
@@ -219,9 +222,15 @@ class SchwarzLevel:
         r = np.asarray(r).reshape(self.mesh.shape)
         return np.stack([fdm_solve(self.factors[e], r[e], h1, h2) for e in range(self.mesh.E)])
 
-    def smooth(self, r, h1, h2, weighted=True):
+    def smooth(self, r, h1, h2, weighted=True, sym=False):
         """Additive Schwarz: sum of the local corrections, averaged over the
-        copies of every node (weighted) or plainly summed, masked."""
+        copies of every node (weighted) or plainly summed, masked.  sym: the
+        symmetric weighting W^1/2 K W^1/2 with W = 1/mult (the residual and
+        the summed corrections each divided by sqrt(mult))."""
+        if sym:
+            ms = np.sqrt(self.mesh.mult)
+            z = self.mesh.dssum(self.local_solves(np.asarray(r).reshape(self.mesh.shape) / ms, h1, h2)) / ms
+            return self.mesh.apply_mask(z)
         z = self.mesh.dssum(self.local_solves(r, h1, h2))
         if weighted:
             z = z / self.mesh.mult
@@ -320,11 +329,13 @@ class HSMG:
         self.sw_m = SchwarzLevel(self.mid)
         self.coarse = CoarseSolver(self.crs)
 
-    def apply(self, r, h1=1.0, h2=0.0):
+    def apply(self, r, h1=1.0, h2=0.0, sym=False):
+        """z = M r; sym: the symmetric weighting on the fine and mid levels
+        (a symmetric positive definite M, for CG)."""
         r = np.asarray(r).reshape(self.fine.shape)
-        z = self.sw_f.smooth(r, h1, h2)
+        z = self.sw_f.smooth(r, h1, h2, sym=sym)
         r1 = restrict(self.J_fm, self.fine, self.mid, r)
-        z1 = self.sw_m.smooth(r1, h1, h2)
+        z1 = self.sw_m.smooth(r1, h1, h2, sym=sym)
         r2 = restrict(self.J_mc, self.mid, self.crs, r1)
         z2 = self.coarse.solve(r2, h1, h2)
         z1 = z1 + prolong(self.J_mc, self.crs, self.mid, z2)
