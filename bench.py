@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--no-learned", action="store_true", help="skip training and timing the learned smoother")
     p.add_argument("--no-large", action="store_true", help="skip the 64^3 channel workload")
     p.add_argument("--no-small", action="store_true", help="skip the 4^3 cube and 16^3 channel solves")
-    p.add_argument("--train-fields", type=int, default=500,
+    p.add_argument("--train-fields", type=int, default=300,
                    help="16^3-channel right-hand sides generated online for training (2000 = the full set)")
     p.add_argument("--heldout", type=int, default=4)
     p.add_argument("--profile-kernels", action="store_true",
@@ -295,14 +295,16 @@ def small_section(args):
     _, f = wl.manufactured(xyz[0], xyz[1], xyz[2])
     b = torch.empty_like(xyz[0].contiguous())
     mesh.rhs(f.contiguous(), b)
-    forms = [("fp64_jacobi_pcg", dict(check_every=8)), ("gmres_hsmg", dict(form=sem.FORM_GMRES_HSMG)),
+    forms = [("fp64_jacobi_pcg", dict(check_every=8)), ("gmres_hsmg", dict(form=sem.FORM_GMRES_HSMG, restart=10)),
+             ("pcg_hsmg", dict(form=sem.FORM_PCG_HSMG, check_every=4)),
              ("pcg_1red", dict(form=sem.FORM_PCG_1RED, check_every=8))]
     out["c0_cube4_N5"] = run_forms(mesh, b, forms, 5, tag="c0")
     del mesh
     spec = wl.config("c3")
     mesh = sem.Mesh.from_spec(spec, prepare=sem.SEM_PREP_HSMG | sem.SEM_PREP_F32)
     b = channel_rhs(mesh, "c3", 16)
-    forms = [("fp64_jacobi_pcg", dict(check_every=32)), ("gmres_hsmg", dict(form=sem.FORM_GMRES_HSMG)),
+    forms = [("fp64_jacobi_pcg", dict(check_every=32)), ("gmres_hsmg", dict(form=sem.FORM_GMRES_HSMG, restart=10)),
+             ("pcg_hsmg", dict(form=sem.FORM_PCG_HSMG, check_every=4)),
              ("reliable_fp32", dict(form=sem.FORM_RELIABLE_FP32, inner_tol=0.1, check_every=32))]
     out["c3_channel16_N7"] = run_forms(mesh, b, forms, 3, tag="c3")
     return out
@@ -337,7 +339,8 @@ def large_section(args):
     del w
     print("large: Ax+dssum %.1f us" % (dt * 1e6), flush=True)
     forms = [("fp64_jacobi_pcg", dict(check_every=32, max_iter=40000)),
-             ("gmres_hsmg", dict(form=sem.FORM_GMRES_HSMG, max_iter=2000)),
+             ("gmres_hsmg", dict(form=sem.FORM_GMRES_HSMG, restart=10, max_iter=2000)),
+             ("pcg_hsmg", dict(form=sem.FORM_PCG_HSMG, check_every=4, max_iter=2000)),
              ("reliable_fp32", dict(form=sem.FORM_RELIABLE_FP32, inner_tol=0.1, check_every=32, max_iter=40000)),
              ("reliable_bf16split", dict(form=sem.FORM_RELIABLE_BF16, inner_tol=0.1, check_every=32,
                                          max_iter=40000))]
@@ -538,7 +541,8 @@ def main():
 
     if not args.no_solve:
         forms = [("fp64_jacobi_pcg", dict(check_every=32)),
-                 ("gmres_hsmg", dict(form=sem.FORM_GMRES_HSMG)),
+                 ("gmres_hsmg", dict(form=sem.FORM_GMRES_HSMG, restart=10)),
+                 ("pcg_hsmg", dict(form=sem.FORM_PCG_HSMG, check_every=4)),
                  ("pcg_block_jacobi", dict(form=sem.FORM_PCG_BLOCK_JACOBI, check_every=32))]
         if not args.no_mixed:
             forms += [("dc_fp32", dict(form=sem.FORM_DC_FP32, inner_tol=1e-5, max_outer=60, check_every=32)),

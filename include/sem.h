@@ -156,9 +156,13 @@ sem_status sem_dot(const sem_mesh *mesh, const double *u, const double *v, doubl
  *   SEM_PRECOND_SCHWARZ       its fine level alone: W0 K0 r;
  *   SEM_PRECOND_BLOCK_JACOBI  K0 r without the averaging (the velocity
  *                             solves' block-Jacobi, symmetric positive
- *                             definite).
+ *                             definite);
+ *   SEM_PRECOND_HSMG_SYM      the three-level cycle with W^1/2 K W^1/2 in
+ *                             place of W K on the fine and mid levels
+ *                             (SEM_FORM_PCG_HSMG's symmetric positive
+ *                             definite preconditioner).
  * workspace: device, >= sem_precond_workspace_bytes. */
-enum { SEM_PRECOND_HSMG = 0, SEM_PRECOND_SCHWARZ = 1, SEM_PRECOND_BLOCK_JACOBI = 2 };
+enum { SEM_PRECOND_HSMG = 0, SEM_PRECOND_SCHWARZ = 1, SEM_PRECOND_BLOCK_JACOBI = 2, SEM_PRECOND_HSMG_SYM = 3 };
 sem_status sem_precond_workspace_bytes(const sem_mesh *mesh, size_t *bytes);
 sem_status sem_precond_apply(const sem_mesh *mesh, int kind, double h1, double h2, const double *r_local,
                              double *z_local, void *workspace, size_t ws_bytes, void *stream);
@@ -187,17 +191,23 @@ typedef enum {
                                     one reduction phase per iteration; same stopping test */
     SEM_FORM_GMRES_HSMG = 9,     /* the paper's pressure solver (section 3.1): restarted flexible
                                     GMRES(m) (right preconditioning, Saad 2003 Alg. 9.6; classical
-                                    Gram-Schmidt with a second pass when a new direction loses
-                                    more than half its norm) with the three-level hybrid Schwarz
+                                    Gram-Schmidt with a second pass when a new direction keeps
+                                    less than 1/sqrt(2) of its norm) with the three-level hybrid Schwarz
                                     multigrid preconditioner below; FP64 throughout.  m =
                                     opts.restart; iterations = preconditioned operator
                                     applications.  Needs SEM_PREP_HSMG, h1 > 0, and at least two
                                     elements along every periodic direction. */
-    SEM_FORM_PCG_BLOCK_JACOBI = 10 /* FP64 CG with the block-Jacobi preconditioner of the paper's
+    SEM_FORM_PCG_BLOCK_JACOBI = 10, /* FP64 CG with the block-Jacobi preconditioner of the paper's
                                     velocity solves (section 3.1): z = sum over elements of the
                                     element's separable local solve (the fine level of
                                     SEM_FORM_GMRES_HSMG, unweighted, so symmetric positive
                                     definite).  Needs SEM_PREP_HSMG and h1 > 0. */
+    SEM_FORM_PCG_HSMG = 11       /* FP64 CG with the hybrid Schwarz multigrid in its symmetric
+                                    weighting (1/sqrt(mult) before the local solves and after their
+                                    sum, on the fine and mid levels; symmetric positive definite):
+                                    the same preconditioner family as SEM_FORM_GMRES_HSMG at CG's
+                                    cost per iteration (no growing Krylov basis).  Needs
+                                    SEM_PREP_HSMG and h1 > 0. */
 } sem_form;
 
 /* Hybrid Schwarz multigrid (SEM_FORM_GMRES_HSMG), for an assembled fine

@@ -12,10 +12,11 @@
 // sem_dssum.
 //
 // Dirichlet nodes carry dinv = 0: r, p, x are forced to zero there and they
-// drop out of every inner product.  Partial sums are per block in FP64 and
-// are reduced by one-block finalize kernels in a fixed order, so every run is
-// bitwise reproducible.
+// drop out of every inner product.  Partial sums are per block in FP64
+// (cross-lane shuffles within a wavefront) and are reduced in a fixed order
+// by one-workgroup finalize kernels, so every run is bitwise reproducible.
 #include "cg.hpp"
+#include "reduce.hpp"
 
 namespace sem {
 namespace cg {
@@ -40,23 +41,30 @@ __device__ __forceinline__ double assemble_at(const Lattice &L, const T *__restr
     return (double)s;
 }
 
+// Block sums of NV values per thread: a butterfly of cross-lane shuffles in
+// each wavefront, then the wavefronts' sums in order; thread 0 stores
+// out[q * stride + block].
 template <int NV>
 __device__ __forceinline__ void block_store(double (&v)[NV], double *out, int stride)
 {
-    __shared__ double red[NV][kBS];
+    __shared__ double red[NV][kBS / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) red[q][threadIdx.x] = v[q];
-    __syncthreads();
-    for (int w = kBS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
-        }
-        __syncthreads();
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) red[q][wv] = x;
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) out[q * stride + blockIdx.x] = red[q][0];
+        for (int q = 0; q < NV; ++q) {
+            double x = red[q][0];
+#pragma unroll
+            for (int w = 1; w < kBS / 64; ++w) x += red[q][w];
+            out[q * stride + blockIdx.x] = x;
+        }
     }
 }
 
@@ -169,18 +177,49 @@ __global__ void __launch_bounds__(kBS) reduce_stage_kernel(const double *__restr
     }
 }
 
+__device__ __forceinline__ void alpha_finalize(CgState *st, double pw)
+{
+    st->pw = pw;
+    if (!(pw > 0.0) || !isfinite(pw) || !isfinite(st->rz)) {
+        st->done = 2;
+        st->status = SEM_ERR_BREAKDOWN;
+    } else {
+        st->alpha = st->rz / pw;
+    }
+}
+
+// alpha = rz / (p, S p) from n <= kDirectMax per-element partials, one launch
+__global__ void __launch_bounds__(kWide) alpha_direct_kernel(CgState *st, const double *__restrict__ part, int64_t n)
+{
+    const double pw = wide_sum(part, n);
+    if (threadIdx.x == 0 && !st->done) alpha_finalize(st, pw);
+}
+
+// alpha from the kStage sums of the two-stage reduction (more partials)
 __global__ void __launch_bounds__(kBS) alpha_kernel(CgState *st, const double *__restrict__ stage)
 {
     if (st->done) return;
     const double pw = block_sum(stage, kStage);
-    if (threadIdx.x == 0) {
-        st->pw = pw;
-        if (!(pw > 0.0) || !isfinite(pw) || !isfinite(st->rz)) {
-            st->done = 2;
-            st->status = SEM_ERR_BREAKDOWN;
-        } else {
-            st->alpha = st->rz / pw;
-        }
+    if (threadIdx.x == 0) alpha_finalize(st, pw);
+}
+
+// iteration count, residual history, convergence test and beta
+__device__ __forceinline__ void beta_finalize(CgState *st, double rr, double rz, double *hist)
+{
+    const int it = st->it + 1;
+    st->it = it;
+    st->rr = rr;
+    if (hist && it < st->hist_len) hist[it] = sqrt(rr / st->bb);
+    if (!isfinite(rr) || !isfinite(rz)) {
+        st->done = 2;
+        st->status = SEM_ERR_BREAKDOWN;
+    } else if (rr <= st->tol2) {
+        st->done = 1;
+    } else if (it >= st->max_it) {
+        st->done = 3;
+    } else {
+        st->beta = rz / st->rz;
+        st->rz = rz;
     }
 }
 
@@ -188,6 +227,8 @@ __global__ void __launch_bounds__(kBS) alpha_kernel(CgState *st, const double *_
 // (r,r), (r, dinv r).  RPB rows per workgroup, unrolled so that the loads of
 // all of them are in flight together; NPC = N + 1 fixed at compile time
 // (0: any order).
+// Workgroups stride over groups of RPB rows (at most kUpdateBlocks of them,
+// so that one wide workgroup sums the partials).
 template <typename T, int RPB, int NPC>
 __global__ void __launch_bounds__(kBS)
 update_kernel(const CgState *__restrict__ st, const T *__restrict__ w, T *__restrict__ x, T *__restrict__ r,
@@ -196,8 +237,10 @@ update_kernel(const CgState *__restrict__ st, const T *__restrict__ w, T *__rest
     if (st->done) return;
     const T alpha = (T)st->alpha;
     double acc[2] = {0.0, 0.0};
-    const int nrows = (int)(L.ny * L.nz), row0 = (int)blockIdx.x * RPB, ny = (int)L.ny, nx = (int)L.nx;
-    for (int gi = threadIdx.x; gi < nx; gi += kBS) {
+    const int nrows = (int)(L.ny * L.nz), ny = (int)L.ny, nx = (int)L.nx;
+    const int ngroups = (nrows + RPB - 1) / RPB;
+    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x)
+    for (int gi = threadIdx.x, row0 = grp * RPB; gi < nx; gi += kBS) {
         T d[RPB], xg[RPB], pg[RPB], rg0[RPB], wg[RPB];
         int64_t g[RPB];
 #pragma unroll
@@ -223,28 +266,14 @@ update_kernel(const CgState *__restrict__ st, const T *__restrict__ w, T *__rest
     block_store<2>(acc, part, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBS) beta_kernel(CgState *st, const double *__restrict__ part, int nb, double *hist)
+// (r, r) and (r, z) from nb <= kDirectMax update partials: iteration count,
+// convergence test and beta in one launch
+__global__ void __launch_bounds__(kWide) beta_direct_kernel(CgState *st, const double *__restrict__ part, int nb,
+                                                             double *hist)
 {
-    if (st->done) return;
-    const double rr = block_sum(part, nb);
-    const double rz = block_sum(part + nb, nb);
-    if (threadIdx.x == 0) {
-        const int it = st->it + 1;
-        st->it = it;
-        st->rr = rr;
-        if (hist && it < st->hist_len) hist[it] = sqrt(rr / st->bb);
-        if (!isfinite(rr) || !isfinite(rz)) {
-            st->done = 2;
-            st->status = SEM_ERR_BREAKDOWN;
-        } else if (rr <= st->tol2) {
-            st->done = 1;
-        } else if (it >= st->max_it) {
-            st->done = 3;
-        } else {
-            st->beta = rz / st->rz;
-            st->rz = rz;
-        }
-    }
+    double rr, rz;
+    wide_sum2(part, part + nb, nb, rr, rz);
+    if (threadIdx.x == 0 && !st->done) beta_finalize(st, rr, rz, hist);
 }
 
 template <typename T>
@@ -566,19 +595,17 @@ hipError_t cg_init(const Mesh &m, const CgVecs<T> &v, const T *b, CgState *st, d
 template <typename T>
 hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, double *hist, hipStream_t s)
 {
-    const int64_t rows = row_grid(m.lat, update_rpb<T>());
+    const unsigned nb = std::min<unsigned>(row_grid(m.lat, update_rpb<T>()), kUpdateBlocks);
     hipError_t e = cg_alpha(m, v.part_e, v.stage, st, s);
     if (e != hipSuccess) return e;
     constexpr int RPB = update_rpb<T>();
     if (m.lat.NP == 8)
-        hipLaunchKernelGGL((cg::update_kernel<T, RPB, 8>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
-                           v.dinv, m.lat, v.part_b);
+        hipLaunchKernelGGL((cg::update_kernel<T, RPB, 8>), dim3(nb), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,
+                           m.lat, v.part_b);
     else
-        hipLaunchKernelGGL((cg::update_kernel<T, RPB, 0>), dim3((unsigned)rows), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
-                           v.dinv, m.lat, v.part_b);
-    e = cg_reduce(v.part_b, rows, 2, v.stage, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(cg::beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.stage, kStage, hist);
+        hipLaunchKernelGGL((cg::update_kernel<T, RPB, 0>), dim3(nb), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,
+                           m.lat, v.part_b);
+    hipLaunchKernelGGL(cg::beta_direct_kernel, dim3(1), dim3(kWide), 0, s, st, v.part_b, (int)nb, hist);
     L3((cg::p_kernel<T>), m.ng) st, v.p, v.r, v.dinv, m.ng);
     return hipGetLastError();
 }
@@ -666,6 +693,10 @@ hipError_t cg_reduce(const double *part, int64_t n, int nv, double *stage, hipSt
 
 hipError_t cg_alpha(const Mesh &m, const double *part_e, double *stage, CgState *st, hipStream_t s)
 {
+    if (m.E <= kDirectMax) {
+        hipLaunchKernelGGL(cg::alpha_direct_kernel, dim3(1), dim3(kWide), 0, s, st, part_e, m.E);
+        return hipGetLastError();
+    }
     hipError_t e = cg_reduce(part_e, m.E, 1, stage, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(cg::alpha_kernel, dim3(1), dim3(kBS), 0, s, st, stage);

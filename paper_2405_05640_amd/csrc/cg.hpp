@@ -9,6 +9,7 @@ namespace sem {
 
 constexpr int kBS = 256;             // threads per block of the vector kernels
 constexpr int kMaxVecBlocks = 4096;  // grid cap of the flat vector kernels
+constexpr int kUpdateBlocks = 4096;  // grid cap of the row-update kernels (their partials feed one wide block)
 constexpr int kStage = 256;          // second-stage partial sums
 
 // Grid of the per-node kernels: one workgroup per lattice row (gj, gk).

@@ -15,10 +15,11 @@
 //   4. coarse assembly; 5. coarse solve: six axis contractions with the
 //      global separable factors on the order-1 lattice
 //   6. z_m = mask(sum of copies / mult) + P z_c (node-wise interpolation)
-//   7. per element: fine rows += J (x) J (x) J z_m   (every copy gets the
-//      whole interpolated value)
-//   8. z = mask(sum of copies / mult): the averaged fine Schwarz correction
-//      plus the prolongated coarser levels.
+//   7. per element: z_p = J (x) J (x) J z_m at the nodes the element owns
+//   8. z = mask(sum of copies / mult) + z_p: the averaged fine Schwarz
+//      correction plus the prolongated coarser levels.
+// (In the symmetric weighting the averages are 1/sqrt(mult) on both sides
+// of the local solves.)
 // All sums run in a fixed order, so results are bitwise reproducible.
 //
 // Flexible GMRES(m) (Saad 2003, Algorithm 9.6) keeps V (m+1 vectors) and
@@ -27,30 +28,38 @@
 // of each Arnoldi step (one synchronisation per iteration).  The new
 // direction's inner products with every V_i and its own norm come from one
 // fused pass that also assembles S Z_j (wave-shuffle partial sums, fixed
-// order); classical Gram-Schmidt takes a second pass when the direction
-// loses more than half its norm.
+// order); its norm after the projection follows from those (Pythagoras) and
+// one more pass subtracts the projections and normalises.  When the
+// direction keeps less than 1/sqrt(2) of its norm, classical Gram-Schmidt
+// takes a second pass ("twice is enough"), whose inner products come from
+// the same read of V as the first update: three passes over V instead of
+// four.
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
 
 #include "hsmg.hpp"
+#include "reduce.hpp"
 
 namespace sem {
 namespace mg {
 
 #define GRID_STRIDE(g, n) for (int64_t g = (int64_t)blockIdx.x * kBS + threadIdx.x; g < (n); g += (int64_t)gridDim.x * kBS)
 
+constexpr int kRowsPerBlock = 4;   // lattice rows per workgroup of the row-blocked node kernels
+
 __device__ __forceinline__ bool node_masked(const Lattice &L, int gi, int gj, int gk)
 {
     return axis_dirichlet(L, 0, gi, L.nelx) || axis_dirichlet(L, 1, gj, L.nely) || axis_dirichlet(L, 2, gk, L.nelz);
 }
 
+template <int NPC = 0>
 __device__ __forceinline__ int node_count(const Lattice &L, int gi, int gj, int gk)
 {
     int X[2];
-    return axis_copies(gi, L.nelx, L.N, L.per[0] != 0, X) * axis_copies(gj, L.nely, L.N, L.per[1] != 0, X) *
-           axis_copies(gk, L.nelz, L.N, L.per[2] != 0, X);
+    return axis_copies_t<NPC>(gi, L.nelx, L.N, L.per[0] != 0, X) * axis_copies_t<NPC>(gj, L.nely, L.N, L.per[1] != 0, X) *
+           axis_copies_t<NPC>(gk, L.nelz, L.N, L.per[2] != 0, X);
 }
 
 // ---------------------------------------------------------------- level kernels
@@ -61,7 +70,8 @@ __device__ __forceinline__ int node_count(const Lattice &L, int gi, int gj, int 
 template <int NP, int NPC>
 __global__ void __launch_bounds__(NP * NP * NP)
 schwarz_kernel(const double *__restrict__ rg, Lattice L, const double *__restrict__ fdm, double h1, double h2,
-               double *__restrict__ rows, const double *__restrict__ J, Lattice Lc, double *__restrict__ rows_c)
+               double *__restrict__ rows, const double *__restrict__ J, Lattice Lc, double *__restrict__ rows_c,
+               int sym)
 {
     constexpr int P2 = NP * NP, P3 = P2 * NP, NF = 3 * P2 + 3 * NP;
     constexpr int NJ = NPC > 0 ? NP * NPC : 1;
@@ -76,7 +86,10 @@ schwarz_kernel(const double *__restrict__ rg, Lattice L, const double *__restric
     for (int q = t; q < NF; q += P3) sF[q] = fdm[e * NF + q];
     if constexpr (NPC > 0)
         for (int q = t; q < NJ; q += P3) sJ[q] = J[q];
-    sa[t] = r;
+    const int gi0 = ex * L.N + i, gj0 = ey * L.N + j, gk0 = ez * L.N + k;
+    const int cnt = node_count(L, gi0 >= L.nx ? gi0 - (int)L.nx : gi0, gj0 >= L.ny ? gj0 - (int)L.ny : gj0,
+                               gk0 >= L.nz ? gk0 - (int)L.nz : gk0);
+    sa[t] = sym ? r / sqrt((double)cnt) : r;   // symmetric weighting: 1/sqrt(mult) on both sides
     __syncthreads();
     const double *Sx = sF, *Sy = sF + P2, *Sz = sF + 2 * P2;
     const double *lx = sF + 3 * P2, *ly = lx + NP, *lz = ly + NP;
@@ -112,9 +125,6 @@ schwarz_kernel(const double *__restrict__ rg, Lattice L, const double *__restric
     rows[rows_index32(L, ex, ey, ez, i, j, k)] = v;
     if constexpr (NPC > 0) {
         // restriction of r / mult: J^T along r, then s, then t
-        const int gi = ex * L.N + i, gj = ey * L.N + j, gk = ez * L.N + k;
-        const int cnt = node_count(L, gi >= L.nx ? gi - (int)L.nx : gi, gj >= L.ny ? gj - (int)L.ny : gj,
-                                   gk >= L.nz ? gk - (int)L.nz : gk);
         __syncthreads();   // sa is free again
         sa[t] = r / cnt;
         __syncthreads();
@@ -144,8 +154,260 @@ schwarz_kernel(const double *__restrict__ rg, Lattice L, const double *__restric
     }
 }
 
-// out[g] = mask(sum of the copies of rows at g, times 1 / count when
-// weighted) + (zc != null: the order-1 interpolant of zc at g)
+// The same element Schwarz solve at N = 7 with one wavefront per element and
+// one x-pencil of 8 nodes per lane: every contraction runs on the 8 values a
+// lane holds in registers, with the element's factors as wave-uniform
+// (scalar) operands, and the pencils change direction through a padded LDS
+// tile (four transposes per solve instead of six LDS-staged contractions of
+// 512 threads).  (Staging the factors in LDS instead made the compiler hold
+// all 64 entries of a matrix in vector registers: 210 VGPRs, or spills when
+// capped.)  Lane t = (a, b) owns the pencil along the direction of the
+// current phase; NPC > 0 also restricts r / mult to NPC points.
+template <int NPC>
+__global__ void __launch_bounds__(64)
+schwarz_pencil_kernel(const double *__restrict__ rg, Lattice L, const double *__restrict__ fdm, double h1, double h2,
+                      double *__restrict__ rows, const double *__restrict__ J, Lattice Lc, double *__restrict__ rows_c,
+                      int sym)
+{
+    constexpr int NP = 8, P2 = 64, NF = 3 * P2 + 3 * NP, PAD = 9;
+    __shared__ double T[NP * NP * PAD];   // [k][j][i] with a 9-double row pitch
+    const int t = threadIdx.x, ta = t & 7, tb = t >> 3;
+    const int64_t e = __builtin_amdgcn_readfirstlane((int)xcd_block());
+    int ex, ey, ez;
+    elem_coords(L, e, ex, ey, ez);
+    const double *__restrict__ F = fdm + e * NF;   // wave-uniform: scalar loads
+    const double *Sx = F, *Sy = F + P2, *Sz = F + 2 * P2, *lx = F + 3 * P2, *ly = lx + NP, *lz = ly + NP;
+    auto T_at = [&](int k, int j, int i) -> double & { return T[(k * NP + j) * PAD + i]; };
+    // x-pencils: lane (j, k) = (ta, tb)
+    double r[NP], v[NP], o[NP];
+    int cnt[NP];   // copies of each node of the pencil
+#pragma unroll
+    for (int i = 0; i < NP; ++i) r[i] = rg[gather_index32(L, ex, ey, ez, i, ta, tb)];
+    {
+        const int gj = ey * L.N + ta, gk = ez * L.N + tb;
+        int X[2];
+        const int cyz = axis_copies_t<NP>(gj >= L.ny ? gj - (int)L.ny : gj, L.nely, L.N, L.per[1] != 0, X) *
+                        axis_copies_t<NP>(gk >= L.nz ? gk - (int)L.nz : gk, L.nelz, L.N, L.per[2] != 0, X);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            int gi = ex * L.N + i;
+            if (gi >= L.nx) gi -= (int)L.nx;
+            cnt[i] = cyz * axis_copies_t<NP>(gi, L.nelx, L.N, L.per[0] != 0, X);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) v[i] = sym ? r[i] / sqrt((double)cnt[i]) : r[i];   // symmetric weighting
+#pragma unroll
+    for (int q = 0; q < NP; ++q) o[q] = 0.0;
+#pragma unroll
+    for (int a = 0; a < NP; ++a)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) o[q] += Sx[a * NP + q] * v[a];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) T_at(tb, ta, q) = o[q];
+    __syncthreads();
+    // y-pencils: lane (i, k) = (ta, tb)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) v[b] = T_at(tb, b, ta);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) o[q] = 0.0;
+#pragma unroll
+    for (int b = 0; b < NP; ++b)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) o[q] += Sy[b * NP + q] * v[b];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NP; ++q) T_at(tb, q, ta) = o[q];
+    __syncthreads();
+    // z-pencils: lane (i, j) = (ta, tb); forward, divide, backward in registers
+#pragma unroll
+    for (int c = 0; c < NP; ++c) v[c] = T_at(c, tb, ta);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) o[q] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) o[q] += Sz[c * NP + q] * v[c];
+    const double lxy = lx[ta] + ly[tb];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const double d = h1 * (lxy + lz[q]) + h2;   // +inf on unused modes
+        o[q] = d > 0.0 ? o[q] / d : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) s += Sz[c * NP + q] * o[q];
+        v[c] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NP; ++c) T_at(c, tb, ta) = v[c];
+    __syncthreads();
+    // y-pencils again: lane (i, k)
+#pragma unroll
+    for (int q = 0; q < NP; ++q) o[q] = T_at(tb, q, ta);
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) s += Sy[b * NP + q] * o[q];
+        v[b] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NP; ++b) T_at(tb, b, ta) = v[b];
+    __syncthreads();
+    // x-pencils again: lane (j, k)
+#pragma unroll
+    for (int q = 0; q < NP; ++q) o[q] = T_at(tb, ta, q);
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) s += Sx[a * NP + q] * o[q];
+        rows[rows_index32(L, ex, ey, ez, a, ta, tb)] = s;
+    }
+    if constexpr (NPC > 0) {
+        // restriction of r / mult (x-pencils still in r): J^T along x in
+        // registers, then along y and z through the tile
+        double s1[NPC];
+#pragma unroll
+        for (int c = 0; c < NPC; ++c) s1[c] = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const double rr = r[i] / cnt[i];
+#pragma unroll
+            for (int c = 0; c < NPC; ++c) s1[c] += J[i * NPC + c] * rr;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NPC; ++c) T_at(tb, ta, c) = s1[c];   // [k][j][a']
+        __syncthreads();
+        // lanes (a', k) with a' < NPC: along y
+        double s2[NPC];
+        if (ta < NPC) {
+#pragma unroll
+            for (int c = 0; c < NPC; ++c) s2[c] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const double w = T_at(tb, j, ta);
+#pragma unroll
+                for (int c = 0; c < NPC; ++c) s2[c] += J[j * NPC + c] * w;
+            }
+        }
+        __syncthreads();
+        if (ta < NPC) {
+#pragma unroll
+            for (int c = 0; c < NPC; ++c) T_at(tb, c, ta) = s2[c];   // [k][b'][a']
+        }
+        __syncthreads();
+        // lanes (a', b') with both < NPC: along z
+        if (ta < NPC && tb < NPC) {
+#pragma unroll
+            for (int c = 0; c < NPC; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < NP; ++k) s += J[k * NPC + c] * T_at(k, tb, ta);
+                rows_c[rows_index32(Lc, ex, ey, ez, ta, tb, c)] = s;
+            }
+        }
+    }
+}
+
+// Fine-level result: z[g] = mask(W (sum of the copies of rows at g)) +
+// zp[g], W = 1, 1 / mult or 1 / sqrt(mult); zp (optional) is the
+// prolongated coarser-level correction, one value per node.  kRowsPerBlock
+// lattice rows per workgroup, every load issued before the arithmetic.
+template <int NPC>
+__global__ void __launch_bounds__(kBS)
+assemble_fine_kernel(const double *__restrict__ rows, Lattice L, int weighted, const double *__restrict__ zp,
+                     double *__restrict__ out)
+{
+    const int nrows = (int)(L.ny * L.nz), ny = (int)L.ny, nx = (int)L.nx, row0 = (int)blockIdx.x * kRowsPerBlock;
+    for (int gi = threadIdx.x; gi < nx; gi += kBS) {
+        double v[kRowsPerBlock], a[kRowsPerBlock];
+        int64_t g[kRowsPerBlock];
+        int gj[kRowsPerBlock], gk[kRowsPerBlock];
+#pragma unroll
+        for (int q = 0; q < kRowsPerBlock; ++q) {
+            const int row = row0 + q < nrows ? row0 + q : nrows - 1;
+            gj[q] = row % ny;
+            gk[q] = row / ny;
+            g[q] = gi + (int64_t)nx * row;
+            v[q] = node_assemble_rows<NPC>(L, rows, gi, gj[q], gk[q]);
+            a[q] = zp ? zp[g[q]] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kRowsPerBlock; ++q) {
+            if (row0 + q >= nrows) continue;
+            double z = 0.0;
+            if (!node_masked(L, gi, gj[q], gk[q])) {
+                z = v[q];
+                if (weighted == kWeightAvg) z /= node_count<NPC>(L, gi, gj[q], gk[q]);
+                if (weighted == kWeightSym) z /= sqrt((double)node_count<NPC>(L, gi, gj[q], gk[q]));
+                z += a[q];
+            }
+            out[g[q]] = z;
+        }
+    }
+}
+
+// zp = J (x) J (x) J zm (the mid level's assembled correction interpolated
+// to the fine nodes), one value per fine node: every element interpolates
+// its nodes and writes those it owns (local index below N along each axis,
+// or the last element along a non-periodic axis), so each node is written
+// once
+template <int NP, int NPM>
+__global__ void __launch_bounds__(NP * NP * NP)
+prolong_owned_kernel(const double *__restrict__ zm, Lattice Lm, const double *__restrict__ J, Lattice L,
+                     double *__restrict__ zp)
+{
+    constexpr int P3 = NP * NP * NP;
+    __shared__ double s0[NPM * NPM * NPM], s1[NP * NPM * NPM], s2[NP * NP * NPM];
+    __shared__ double sJ[NP * NPM];
+    const int t = threadIdx.x, i = t % NP, j = (t / NP) % NP, k = t / (NP * NP);
+    const int64_t e = xcd_block();
+    int ex, ey, ez;
+    elem_coords(L, e, ex, ey, ez);
+    if (t < NPM * NPM * NPM) {
+        const int a = t % NPM, b = (t / NPM) % NPM, c = t / (NPM * NPM);
+        s0[t] = zm[gather_index32(Lm, ex, ey, ez, a, b, c)];
+    }
+    for (int q = t; q < NP * NPM; q += P3) sJ[q] = J[q];
+    __syncthreads();
+    if (t < NP * NPM * NPM) {
+        const int ii = t % NP, b = (t / NP) % NPM, c = t / (NP * NPM);
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < NPM; ++a) s += sJ[ii * NPM + a] * s0[(c * NPM + b) * NPM + a];
+        s1[t] = s;
+    }
+    __syncthreads();
+    if (t < NP * NP * NPM) {
+        const int ii = t % NP, jj = (t / NP) % NP, c = t / (NP * NP);
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < NPM; ++b) s += sJ[jj * NPM + b] * s1[(c * NPM + b) * NP + ii];
+        s2[t] = s;
+    }
+    __syncthreads();
+    const int N = L.N;
+    const bool own = (i < N || (ex == L.nelx - 1 && !L.per[0])) && (j < N || (ey == L.nely - 1 && !L.per[1])) &&
+                     (k < N || (ez == L.nelz - 1 && !L.per[2]));
+    if (!own) return;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < NPM; ++c) s += sJ[k * NPM + c] * s2[(c * NP + j) * NP + i];
+    zp[gather_index32(L, ex, ey, ez, i, j, k)] = s;
+}
+
+// out[g] = mask(sum of the copies of rows at g, times 1 / count
+// (kWeightAvg) or 1 / sqrt(count) (kWeightSym)) + (zc != null: the order-1
+// interpolant of zc at g); NPC = N + 1 of the level fixed at compile time
+// (0: any)
+template <int NPC>
 __global__ void __launch_bounds__(kBS)
 assemble_kernel(const double *__restrict__ rows, Lattice L, int weighted, double *__restrict__ out,
                 const double *__restrict__ zc, Lattice Lc, const double *__restrict__ J)
@@ -156,8 +418,9 @@ assemble_kernel(const double *__restrict__ rows, Lattice L, int weighted, double
             out[g] = 0.0;
             continue;
         }
-        double v = node_assemble_rows<0>(L, rows, gi, gj, gk);
-        if (weighted) v /= node_count(L, gi, gj, gk);
+        double v = node_assemble_rows<NPC>(L, rows, gi, gj, gk);
+        if (weighted == kWeightAvg) v /= node_count<NPC>(L, gi, gj, gk);
+        if (weighted == kWeightSym) v /= sqrt((double)node_count<NPC>(L, gi, gj, gk));
         if (zc) {
             const int N = L.N;
             int ex = gi / N, ey = gj / N, ez = gk / N;
@@ -174,50 +437,6 @@ assemble_kernel(const double *__restrict__ rows, Lattice L, int weighted, double
         }
         out[g] = v;
     }
-}
-
-// rows (fine, row layout) += J (x) J (x) J zm_e on every element (zm: the
-// mid level's assembled correction)
-template <int NP, int NPM>
-__global__ void __launch_bounds__(NP * NP * NP)
-prolong_add_kernel(const double *__restrict__ zm, Lattice Lm, const double *__restrict__ J, Lattice L,
-                   double *__restrict__ rows)
-{
-    constexpr int P3 = NP * NP * NP;
-    __shared__ double s0[NPM * NPM * NPM], s1[NP * NPM * NPM], s2[NP * NP * NPM];
-    __shared__ double sJ[NP * NPM];
-    const int t = threadIdx.x, i = t % NP, j = (t / NP) % NP, k = t / (NP * NP);
-    const int64_t e = xcd_block();
-    int ex, ey, ez;
-    elem_coords(L, e, ex, ey, ez);
-    const int out = rows_index32(L, ex, ey, ez, i, j, k);
-    const double cur = rows[out];
-    if (t < NPM * NPM * NPM) {
-        const int a = t % NPM, b = (t / NPM) % NPM, c = t / (NPM * NPM);
-        s0[t] = zm[gather_index32(Lm, ex, ey, ez, a, b, c)];
-    }
-    for (int q = t; q < NP * NPM; q += P3) sJ[q] = J[q];
-    __syncthreads();
-    if (t < NP * NPM * NPM) {
-        const int ii = t % NP, b = (t / NP) % NPM, c = t / (NP * NPM);
-        double s = 0.0;
-#pragma unroll
-        for (int a = 0; a < NPM; ++a) s += sJ[ii * NPM + a] * s0[(c * NPM + b) * NPM + a];
-        s1[t] = s;   // [c][b][i]
-    }
-    __syncthreads();
-    if (t < NP * NP * NPM) {
-        const int ii = t % NP, jj = (t / NP) % NP, c = t / (NP * NP);
-        double s = 0.0;
-#pragma unroll
-        for (int b = 0; b < NPM; ++b) s += sJ[jj * NPM + b] * s1[(c * NPM + b) * NP + ii];
-        s2[t] = s;   // [c][j][i]
-    }
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < NPM; ++c) s += sJ[k * NPM + c] * s2[(c * NP + j) * NP + i];
-    rows[out] = cur + s;
 }
 
 // One axis of the global coarse solve on the (nz, ny, nx) order-1 lattice:
@@ -278,7 +497,12 @@ __device__ __forceinline__ void block_partials(double (&acc)[NV], int nv, double
 
 constexpr int kMaxDots = kGmresMaxRestart + 2;   // (V_i, w) for i <= j, plus (w, w)
 
-// w = mask(Q^T rows) -> wout; partials of (V_i, w), i <= j, and (w, w)
+// w = mask(Q^T rows) -> wout; partials of (V_i, w), i <= j, and (w, w).
+// RPB lattice rows per workgroup (the partial-sum reduction of up to 32
+// quantities is paid once per RPB rows); NPC = N + 1 fixed at compile time
+// (0: any order).
+constexpr int kDotRows = 8;
+template <int NPC>
 __global__ void __launch_bounds__(kBS)
 assemble_dots_kernel(const double *__restrict__ rows, Lattice L, double *__restrict__ wout,
                      const double *__restrict__ V, int64_t ng, int j, double *__restrict__ part)
@@ -286,17 +510,23 @@ assemble_dots_kernel(const double *__restrict__ rows, Lattice L, double *__restr
     double acc[kMaxDots];
 #pragma unroll
     for (int q = 0; q < kMaxDots; ++q) acc[q] = 0.0;
-    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
-    {
-        const double w = node_masked(L, gi, gj, gk) ? 0.0 : node_assemble_rows<0>(L, rows, gi, gj, gk);
-        wout[g] = w;
+    const int nrows = (int)(L.ny * L.nz), ny = (int)L.ny, nx = (int)L.nx;
+    for (int rr = 0; rr < kDotRows; ++rr) {
+        const int row = (int)blockIdx.x * kDotRows + rr;
+        if (row >= nrows) break;
+        const int gj = row % ny, gk = row / ny;
+        for (int gi = threadIdx.x; gi < nx; gi += kBS) {
+            const int64_t g = gi + (int64_t)nx * row;
+            const double w = node_masked(L, gi, gj, gk) ? 0.0 : node_assemble_rows<NPC>(L, rows, gi, gj, gk);
+            wout[g] = w;
 #pragma unroll
-        for (int q = 0; q < kMaxDots - 1; ++q)
-            if (q <= j) acc[q] += V[q * ng + g] * w;
-        double ww = w * w;
+            for (int q = 0; q < kMaxDots - 1; ++q)
+                if (q <= j) acc[q] += V[q * ng + g] * w;
+            const double ww = w * w;
 #pragma unroll
-        for (int q = 0; q < kMaxDots; ++q)
-            if (q == j + 1) acc[q] += ww;
+            for (int q = 0; q < kMaxDots; ++q)
+                if (q == j + 1) acc[q] += ww;
+        }
     }
     block_partials<kMaxDots>(acc, j + 2, part, gridDim.x);
 }
@@ -356,6 +586,40 @@ orth_kernel(double *__restrict__ w, const double *__restrict__ V, int64_t ng, in
     }
 }
 
+// s = w - sum_{i <= j} h_i V_i written back to w, and partials of (V_i, s),
+// i <= j, and (s, s): the first update of a two-pass classical Gram-Schmidt
+// with the second pass's inner products from the same read of V
+__global__ void __launch_bounds__(kBS)
+orth_dots_kernel(double *__restrict__ w, const double *__restrict__ V, int64_t ng, int j, const double *__restrict__ h,
+                 double *__restrict__ part)
+{
+    double hq[kMaxDots - 1], acc[kMaxDots];
+#pragma unroll
+    for (int q = 0; q < kMaxDots - 1; ++q) hq[q] = q <= j ? h[q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxDots; ++q) acc[q] = 0.0;
+    GRID_STRIDE(g, ng)
+    {
+        double vq[kMaxDots - 1];
+        double v = w[g];
+#pragma unroll
+        for (int q = 0; q < kMaxDots - 1; ++q)
+            if (q <= j) {
+                vq[q] = V[q * ng + g];
+                v -= hq[q] * vq[q];
+            }
+        w[g] = v;
+#pragma unroll
+        for (int q = 0; q < kMaxDots - 1; ++q)
+            if (q <= j) acc[q] += vq[q] * v;
+        const double ss = v * v;
+#pragma unroll
+        for (int q = 0; q < kMaxDots; ++q)
+            if (q == j + 1) acc[q] += ss;
+    }
+    block_partials<kMaxDots>(acc, j + 2, part, gridDim.x);
+}
+
 // x += sum_{i < k} y_i Z_i
 __global__ void __launch_bounds__(kBS)
 combine_kernel(double *__restrict__ x, const double *__restrict__ Z, int64_t ng, int k, const double *__restrict__ y)
@@ -407,6 +671,21 @@ __global__ void __launch_bounds__(kBS) bj_dot_kernel(const CgState *st, const do
     block_partials<1>(acc, 1, part, gridDim.x);
 }
 
+// (r, z) from nb <= kDirectMax partials: beta = (r, z) / rz_old (0 on the
+// first call), rz = (r, z); a breakdown if (r, z) is not positive
+__global__ void __launch_bounds__(kWide) bj_rz_finalize(CgState *st, const double *__restrict__ part, int nb, int first)
+{
+    const double rz = wide_sum(part, nb);
+    if (threadIdx.x != 0 || st->done) return;
+    if (!(rz > 0.0) || !isfinite(rz)) {
+        st->done = 2;
+        st->status = SEM_ERR_BREAKDOWN;
+        return;
+    }
+    st->beta = first ? 0.0 : rz / st->rz;
+    st->rz = rz;
+}
+
 // first = 1: bb, tol2, rr from the (r, r) partials (run start)
 __global__ void __launch_bounds__(kBS) bj_start_finalize(CgState *st, const double *__restrict__ part, int nb, double tol)
 {
@@ -430,32 +709,11 @@ __global__ void __launch_bounds__(kBS) bj_start_finalize(CgState *st, const doub
     }
 }
 
-// rz_new from the partials: beta = rz_new / rz (0 on the first call), rz = rz_new
-__global__ void __launch_bounds__(kBS) bj_rz_finalize(CgState *st, const double *__restrict__ part, int nb, int first)
-{
-    if (st->done) return;
-    __shared__ double red[kBS];
-    double s = 0.0;
-    for (int q = threadIdx.x; q < nb; q += kBS) s += part[q];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kBS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double rz = red[0];
-        if (!(rz > 0.0) || !isfinite(rz)) {
-            st->done = 2;
-            st->status = SEM_ERR_BREAKDOWN;
-            return;
-        }
-        st->beta = first ? 0.0 : rz / st->rz;
-        st->rz = rz;
-    }
-}
-
-// wg = Q^T rows; x += alpha p; r -= alpha wg; partial (r, r)
+// wg = Q^T rows; x += alpha p; r -= alpha wg; partial (r, r).  Workgroups
+// stride over groups of kRowsPerBlock lattice rows (at most kUpdateBlocks
+// workgroups), with every load of a node issued before its arithmetic;
+// NPC = N + 1 fixed at compile time (0: any order).
+template <int NPC>
 __global__ void __launch_bounds__(kBS)
 bj_update_kernel(const CgState *__restrict__ st, const double *__restrict__ rows, double *__restrict__ x,
                  double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ dinv, Lattice L,
@@ -464,46 +722,52 @@ bj_update_kernel(const CgState *__restrict__ st, const double *__restrict__ rows
     if (st->done) return;
     const double alpha = st->alpha;
     double acc[1] = {0.0};
-    SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
-    {
-        if (dinv[g] == 0.0) continue;
-        const double wg = node_assemble_rows<0>(L, rows, gi, gj, gk);
-        x[g] += alpha * p[g];
-        const double rg = r[g] - alpha * wg;
-        r[g] = rg;
-        acc[0] += rg * rg;
+    const int nrows = (int)(L.ny * L.nz), ny = (int)L.ny, nx = (int)L.nx;
+    const int ngroups = (nrows + kRowsPerBlock - 1) / kRowsPerBlock;
+    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x)
+    for (int gi = threadIdx.x, row0 = grp * kRowsPerBlock; gi < nx; gi += kBS) {
+        double d[kRowsPerBlock], xg[kRowsPerBlock], pg[kRowsPerBlock], rg0[kRowsPerBlock], wg[kRowsPerBlock];
+        int64_t g[kRowsPerBlock];
+#pragma unroll
+        for (int q = 0; q < kRowsPerBlock; ++q) {
+            const int row = row0 + q < nrows ? row0 + q : nrows - 1;   // clamped rows are not stored
+            g[q] = gi + (int64_t)nx * row;
+            d[q] = dinv[g[q]];
+            xg[q] = x[g[q]];
+            pg[q] = p[g[q]];
+            rg0[q] = r[g[q]];
+            wg[q] = node_assemble_rows<NPC>(L, rows, gi, row % ny, row / ny);
+        }
+#pragma unroll
+        for (int q = 0; q < kRowsPerBlock; ++q) {
+            if (row0 + q >= nrows || d[q] == 0.0) continue;
+            x[g[q]] = xg[q] + alpha * pg[q];
+            const double rg = rg0[q] - alpha * wg[q];
+            r[g[q]] = rg;
+            acc[0] += rg * rg;
+        }
     }
     block_partials<1>(acc, 1, part, gridDim.x);
 }
 
-// iteration count, convergence test on (r, r)
-__global__ void __launch_bounds__(kBS) bj_check_finalize(CgState *st, const double *__restrict__ part, int nb,
-                                                         double *hist)
+// (r, r) from nb <= kDirectMax partials: iteration count, residual history,
+// convergence test
+__global__ void __launch_bounds__(kWide) bj_check_finalize(CgState *st, const double *__restrict__ part, int nb,
+                                                           double *hist)
 {
-    if (st->done) return;
-    __shared__ double red[kBS];
-    double s = 0.0;
-    for (int q = threadIdx.x; q < nb; q += kBS) s += part[q];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kBS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double rr = red[0];
-        const int it = st->it + 1;
-        st->it = it;
-        st->rr = rr;
-        if (hist && it < st->hist_len) hist[it] = sqrt(rr / st->bb);
-        if (!isfinite(rr)) {
-            st->done = 2;
-            st->status = SEM_ERR_BREAKDOWN;
-        } else if (rr <= st->tol2) {
-            st->done = 1;
-        } else if (it >= st->max_it) {
-            st->done = 3;
-        }
+    const double rr = wide_sum(part, nb);
+    if (threadIdx.x != 0 || st->done) return;
+    const int it = st->it + 1;
+    st->it = it;
+    st->rr = rr;
+    if (hist && it < st->hist_len) hist[it] = sqrt(rr / st->bb);
+    if (!isfinite(rr)) {
+        st->done = 2;
+        st->status = SEM_ERR_BREAKDOWN;
+    } else if (rr <= st->tol2) {
+        st->done = 1;
+    } else if (it >= st->max_it) {
+        st->done = 3;
     }
 }
 
@@ -525,7 +789,7 @@ size_t hsmg_bufs_bytes(const Mesh &m)
     const Hsmg &h = *m.hsmg;
     auto a = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t E = (size_t)m.E, Pm = (size_t)h.lat_m.P, Pc = 8;
-    return a(m.nl * 8) + a(E * Pm * 8) + 2 * a(h.ng_m * 8) + a(E * Pc * 8) + 2 * a(h.ng_c * 8);
+    return a(m.nl * 8) + a(E * Pm * 8) + 2 * a(h.ng_m * 8) + a(E * Pc * 8) + 2 * a(h.ng_c * 8) + a(m.ng * 8);
 }
 
 HsmgBufs hsmg_bufs_carve(const Mesh &m, char *base)
@@ -547,30 +811,57 @@ HsmgBufs hsmg_bufs_carve(const Mesh &m, char *base)
     b.rows_c = take(E * Pc * 8);
     b.rc = take(h.ng_c * 8);
     b.tc = take(h.ng_c * 8);
+    b.zp = take(m.ng * 8);
     return b;
 }
 
 namespace {
 
+void launch_assemble_fine(const Lattice &L, const double *rows, int weighted, const double *zp, double *out,
+                          hipStream_t s)
+{
+    const dim3 grid((unsigned)((L.ny * L.nz + mg::kRowsPerBlock - 1) / mg::kRowsPerBlock)), block(kBS);
+    if (L.NP == 8)
+        hipLaunchKernelGGL(mg::assemble_fine_kernel<8>, grid, block, 0, s, rows, L, weighted, zp, out);
+    else
+        hipLaunchKernelGGL(mg::assemble_fine_kernel<0>, grid, block, 0, s, rows, L, weighted, zp, out);
+}
+
+void launch_assemble(const Lattice &L, const double *rows, int weighted, double *out, const double *zc,
+                     const Lattice &Lc, const double *J, hipStream_t s)
+{
+    const dim3 grid(node_grid(L)), block(kBS);
+    switch (L.NP) {
+    case 2: hipLaunchKernelGGL(mg::assemble_kernel<2>, grid, block, 0, s, rows, L, weighted, out, zc, Lc, J); break;
+    case 4: hipLaunchKernelGGL(mg::assemble_kernel<4>, grid, block, 0, s, rows, L, weighted, out, zc, Lc, J); break;
+    case 8: hipLaunchKernelGGL(mg::assemble_kernel<8>, grid, block, 0, s, rows, L, weighted, out, zc, Lc, J); break;
+    default: hipLaunchKernelGGL(mg::assemble_kernel<0>, grid, block, 0, s, rows, L, weighted, out, zc, Lc, J); break;
+    }
+}
+
 template <int NP, int NPC>
 void launch_schwarz(const Mesh &m, const Lattice &L, const double *r, const double *fdm, double h1, double h2,
-                    double *rows, const double *J, const Lattice &Lc, double *rows_c, hipStream_t s)
+                    double *rows, const double *J, const Lattice &Lc, double *rows_c, int sym, hipStream_t s)
 {
-    hipLaunchKernelGGL((mg::schwarz_kernel<NP, NPC>), dim3((unsigned)m.E), dim3(NP * NP * NP), 0, s, r, L, fdm, h1,
-                       h2, rows, J, Lc, rows_c);
+    if constexpr (NP == 8)
+        hipLaunchKernelGGL((mg::schwarz_pencil_kernel<NPC>), dim3((unsigned)m.E), dim3(64), 0, s, r, L, fdm, h1, h2,
+                           rows, J, Lc, rows_c, sym);
+    else
+        hipLaunchKernelGGL((mg::schwarz_kernel<NP, NPC>), dim3((unsigned)m.E), dim3(NP * NP * NP), 0, s, r, L, fdm,
+                           h1, h2, rows, J, Lc, rows_c, sym);
 }
 
 // fine Schwarz (+ restriction to the mid level when restrict_mid)
 hipError_t fine_schwarz(const Mesh &m, const double *r, double h1, double h2, const HsmgBufs &b, bool restrict_mid,
-                        hipStream_t s)
+                        int sym, hipStream_t s)
 {
     const Hsmg &h = *m.hsmg;
-#define SEM_FS(NP, NPM)                                                                                          \
-    case NP:                                                                                                     \
-        if (restrict_mid)                                                                                        \
-            launch_schwarz<NP, NPM>(m, m.lat, r, h.d_fdm_f, h1, h2, b.rows_f, h.d_Jfm, h.lat_m, b.rows_m, s);    \
-        else                                                                                                     \
-            launch_schwarz<NP, 0>(m, m.lat, r, h.d_fdm_f, h1, h2, b.rows_f, nullptr, h.lat_m, nullptr, s);       \
+#define SEM_FS(NP, NPM)                                                                                               \
+    case NP:                                                                                                          \
+        if (restrict_mid)                                                                                             \
+            launch_schwarz<NP, NPM>(m, m.lat, r, h.d_fdm_f, h1, h2, b.rows_f, h.d_Jfm, h.lat_m, b.rows_m, sym, s);    \
+        else                                                                                                          \
+            launch_schwarz<NP, 0>(m, m.lat, r, h.d_fdm_f, h1, h2, b.rows_f, nullptr, h.lat_m, nullptr, sym, s);       \
         break;
     switch (m.NP) {
         SEM_FS(3, 2)
@@ -588,13 +879,13 @@ hipError_t fine_schwarz(const Mesh &m, const double *r, double h1, double h2, co
     return hipGetLastError();
 }
 
-hipError_t mid_schwarz(const Mesh &m, double h1, double h2, const HsmgBufs &b, hipStream_t s)
+hipError_t mid_schwarz(const Mesh &m, double h1, double h2, const HsmgBufs &b, int sym, hipStream_t s)
 {
     const Hsmg &h = *m.hsmg;
     switch (h.lat_m.NP) {
-    case 2: launch_schwarz<2, 2>(m, h.lat_m, b.rm, h.d_fdm_m, h1, h2, b.rows_m, h.d_Jmc, h.lat_c, b.rows_c, s); break;
-    case 3: launch_schwarz<3, 2>(m, h.lat_m, b.rm, h.d_fdm_m, h1, h2, b.rows_m, h.d_Jmc, h.lat_c, b.rows_c, s); break;
-    case 4: launch_schwarz<4, 2>(m, h.lat_m, b.rm, h.d_fdm_m, h1, h2, b.rows_m, h.d_Jmc, h.lat_c, b.rows_c, s); break;
+    case 2: launch_schwarz<2, 2>(m, h.lat_m, b.rm, h.d_fdm_m, h1, h2, b.rows_m, h.d_Jmc, h.lat_c, b.rows_c, sym, s); break;
+    case 3: launch_schwarz<3, 2>(m, h.lat_m, b.rm, h.d_fdm_m, h1, h2, b.rows_m, h.d_Jmc, h.lat_c, b.rows_c, sym, s); break;
+    case 4: launch_schwarz<4, 2>(m, h.lat_m, b.rm, h.d_fdm_m, h1, h2, b.rows_m, h.d_Jmc, h.lat_c, b.rows_c, sym, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -603,10 +894,10 @@ hipError_t mid_schwarz(const Mesh &m, double h1, double h2, const HsmgBufs &b, h
 hipError_t prolong_fine(const Mesh &m, const HsmgBufs &b, hipStream_t s)
 {
     const Hsmg &h = *m.hsmg;
-#define SEM_PF(NP, NPM)                                                                                           \
-    case NP:                                                                                                      \
-        hipLaunchKernelGGL((mg::prolong_add_kernel<NP, NPM>), dim3((unsigned)m.E), dim3(NP * NP * NP), 0, s, b.zm, \
-                           h.lat_m, h.d_Jfm, m.lat, b.rows_f);                                                    \
+#define SEM_PF(NP, NPM)                                                                                             \
+    case NP:                                                                                                        \
+        hipLaunchKernelGGL((mg::prolong_owned_kernel<NP, NPM>), dim3((unsigned)m.E), dim3(NP * NP * NP), 0, s, b.zm, \
+                           h.lat_m, h.d_Jfm, m.lat, b.zp);                                                          \
         break;
     switch (m.NP) {
         SEM_PF(3, 2)
@@ -644,28 +935,24 @@ hipError_t coarse_solve(const Mesh &m, double h1, double h2, const HsmgBufs &b, 
 }  // namespace
 
 hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, double *z, const HsmgBufs &b, int levels,
-                      bool weighted, hipStream_t s)
+                      int weight, hipStream_t s)
 {
     const Hsmg &h = *m.hsmg;
+    const int sym = weight == kWeightSym ? 1 : 0;
     hipError_t e;
     if (levels == 1) {
-        if ((e = fine_schwarz(m, r, h1, h2, b, false, s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(mg::assemble_kernel, dim3(node_grid(m.lat)), dim3(kBS), 0, s, b.rows_f, m.lat,
-                           weighted ? 1 : 0, z, (const double *)nullptr, h.lat_c, (const double *)nullptr);
+        if ((e = fine_schwarz(m, r, h1, h2, b, false, sym, s)) != hipSuccess) return e;
+        launch_assemble_fine(m.lat, b.rows_f, weight, nullptr, z, s);
         return hipGetLastError();
     }
-    if ((e = fine_schwarz(m, r, h1, h2, b, true, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(mg::assemble_kernel, dim3(node_grid(h.lat_m)), dim3(kBS), 0, s, b.rows_m, h.lat_m, 0, b.rm,
-                       (const double *)nullptr, h.lat_c, (const double *)nullptr);
-    if ((e = mid_schwarz(m, h1, h2, b, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(mg::assemble_kernel, dim3(node_grid(h.lat_c)), dim3(kBS), 0, s, b.rows_c, h.lat_c, 0, b.rc,
-                       (const double *)nullptr, h.lat_c, (const double *)nullptr);
+    if ((e = fine_schwarz(m, r, h1, h2, b, true, sym, s)) != hipSuccess) return e;
+    launch_assemble(h.lat_m, b.rows_m, kWeightNone, b.rm, nullptr, h.lat_c, nullptr, s);
+    if ((e = mid_schwarz(m, h1, h2, b, sym, s)) != hipSuccess) return e;
+    launch_assemble(h.lat_c, b.rows_c, kWeightNone, b.rc, nullptr, h.lat_c, nullptr, s);
     if ((e = coarse_solve(m, h1, h2, b, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(mg::assemble_kernel, dim3(node_grid(h.lat_m)), dim3(kBS), 0, s, b.rows_m, h.lat_m, 1, b.zm,
-                       (const double *)b.rc, h.lat_c, (const double *)h.d_Jmc);
+    launch_assemble(h.lat_m, b.rows_m, weight, b.zm, b.rc, h.lat_c, h.d_Jmc, s);
     if ((e = prolong_fine(m, b, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(mg::assemble_kernel, dim3(node_grid(m.lat)), dim3(kBS), 0, s, b.rows_f, m.lat, 1, z,
-                       (const double *)nullptr, h.lat_c, (const double *)nullptr);
+    launch_assemble_fine(m.lat, b.rows_f, weight, b.zp, z, s);
     return hipGetLastError();
 }
 
@@ -738,7 +1025,8 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
 {
     const int mres = o.restart > 0 ? std::min(o.restart, kGmresMaxRestart) : kGmresMaxRestart;
     const int64_t ng = m.ng;
-    const int nbn = (int)node_grid(m.lat), nbf = cg_blocks(ng);
+    const int nbf = cg_blocks(ng);
+    const int nbd = (int)((node_grid(m.lat) + mg::kDotRows - 1) / mg::kDotRows);
     double hv[mg::kMaxDots], h2v[mg::kMaxDots];
     std::vector<double> H((size_t)(mres + 1) * mres), cs(mres), sn(mres), g(mres + 1), y(mres);
     auto Hs = [&](int r, int c) -> double & { return H[(size_t)r * mres + c]; };
@@ -772,21 +1060,26 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
         bool stop = false;
         for (int j = 0; j < mres; ++j) {
             double *Vj = gb.V + (size_t)j * ng, *Vn = gb.V + (size_t)(j + 1) * ng, *Zj = gb.Z + (size_t)j * ng;
-            SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, Vj, Zj, gb.hb, 3, true, s));
+            SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, Vj, Zj, gb.hb, 3, kWeightAvg, s));
             SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, Zj, v.w, nullptr, s));
-            hipLaunchKernelGGL(mg::assemble_dots_kernel, dim3(nbn), dim3(kBS), 0, s, v.w, m.lat, Vn, gb.V, ng, j,
-                               gb.part);
+            if (m.NP == 8)
+                hipLaunchKernelGGL(mg::assemble_dots_kernel<8>, dim3(nbd), dim3(kBS), 0, s, v.w, m.lat, Vn, gb.V, ng,
+                                   j, gb.part);
+            else
+                hipLaunchKernelGGL(mg::assemble_dots_kernel<0>, dim3(nbd), dim3(kBS), 0, s, v.w, m.lat, Vn, gb.V, ng,
+                                   j, gb.part);
             SEM_HIP_TRY(hipGetLastError());
-            SEM_TRY(reduce_to_host(gb.part, nbn, j + 2, gb.stage, gb.hdev, hv, s));
+            SEM_TRY(reduce_to_host(gb.part, nbd, j + 2, gb.stage, gb.hdev, hv, s));
             double ww = hv[j + 1], hh = 0.0;
             for (int i = 0; i <= j; ++i) hh += hv[i] * hv[i];
             double beta2 = ww - hh;
             for (int i = 0; i <= j; ++i) Hs(i, j) = hv[i];
-            if (!(beta2 >= 0.25 * ww)) {
-                // second classical Gram-Schmidt pass (the new direction lost
-                // more than half its norm to the projections)
-                hipLaunchKernelGGL(mg::orth_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.hdev, 1.0);
-                hipLaunchKernelGGL(mg::dots_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.part);
+            if (!(beta2 >= 0.5 * ww)) {
+                // second classical Gram-Schmidt pass ("twice is enough"): the
+                // new direction kept less than 1/sqrt(2) of its norm; the
+                // first update and the second pass's inner products share
+                // one read of V
+                hipLaunchKernelGGL(mg::orth_dots_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.hdev, gb.part);
                 SEM_HIP_TRY(hipGetLastError());
                 SEM_TRY(reduce_to_host(gb.part, nbf, j + 2, gb.stage, gb.hdev, h2v, s));
                 double h2 = 0.0;
@@ -863,12 +1156,15 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
     return SEM_OK;
 }
 
-sem_status solve_pcg_block_jacobi(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
-                                  double *z, CgState *st, const HsmgBufs &hb, double *hist, int hist_len,
-                                  int check_every, hipStream_t s, sem_solve_report *rep, CgState &h)
+sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
+                             double *z, CgState *st, const HsmgBufs &hb, int levels, double *hist, int hist_len,
+                             int check_every, hipStream_t s, sem_solve_report *rep, CgState &h)
 {
+    const int weight = levels == 1 ? kWeightNone : kWeightSym;
     const int64_t ng = m.ng;
-    const int nbf = cg_blocks(ng), nbn = (int)node_grid(m.lat);
+    const int nbf = cg_blocks(ng);
+    const int nbu = (int)std::min<int64_t>((m.lat.ny * m.lat.nz + mg::kRowsPerBlock - 1) / mg::kRowsPerBlock,
+                                           kUpdateBlocks);
     CgState init{};
     init.max_it = o.max_iter;
     init.hist_len = hist_len;
@@ -881,9 +1177,9 @@ sem_status solve_pcg_block_jacobi(const Mesh &m, const sem_solve_opts &o, const 
         SEM_HIP_TRY(hipStreamSynchronize(s));
     }
     auto direction = [&](int first) -> sem_status {
-        SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, v.r, z, hb, 1, false, s));
+        SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, v.r, z, hb, levels, weight, s));
         hipLaunchKernelGGL(mg::bj_dot_kernel, dim3(nbf), dim3(kBS), 0, s, st, v.r, z, ng, v.part_b);
-        hipLaunchKernelGGL(mg::bj_rz_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nbf, first);
+        hipLaunchKernelGGL(mg::bj_rz_finalize, dim3(1), dim3(kWide), 0, s, st, v.part_b, nbf, first);
         if (first)
             hipLaunchKernelGGL(mg::scale_kernel, dim3(nbf), dim3(kBS), 0, s, z, v.p, ng, 1.0);
         else
@@ -900,9 +1196,13 @@ sem_status solve_pcg_block_jacobi(const Mesh &m, const sem_solve_opts &o, const 
             for (int q = 0; q < check_every; ++q) {
                 SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.p, v.w, v.part_e, s, &st->done));
                 SEM_HIP_TRY(cg_alpha(m, v.part_e, v.stage, st, s));
-                hipLaunchKernelGGL(mg::bj_update_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,
-                                   m.lat, v.part_b);
-                hipLaunchKernelGGL(mg::bj_check_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nbn, hist);
+                if (m.NP == 8)
+                    hipLaunchKernelGGL(mg::bj_update_kernel<8>, dim3(nbu), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
+                                       v.dinv, m.lat, v.part_b);
+                else
+                    hipLaunchKernelGGL(mg::bj_update_kernel<0>, dim3(nbu), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
+                                       v.dinv, m.lat, v.part_b);
+                hipLaunchKernelGGL(mg::bj_check_finalize, dim3(1), dim3(kWide), 0, s, st, v.part_b, nbu, hist);
                 SEM_TRY(direction(0));
             }
         }
@@ -954,12 +1254,12 @@ sem_status sem_precond_apply(const sem_mesh *mesh, int kind, double h1, double h
     if (!m.hsmg) return fail(SEM_ERR_INVALID_ARG, "the mesh was created without SEM_PREP_HSMG");
     if (!(h1 > 0.0) || !(h2 >= 0.0) || !std::isfinite(h1) || !std::isfinite(h2))
         return fail(SEM_ERR_INVALID_ARG, "the preconditioners need h1 > 0 and h2 >= 0");
-    int levels = 3;
-    bool weighted = true;
+    int levels = 3, weight = kWeightAvg;
     switch (kind) {
     case SEM_PRECOND_HSMG: break;
     case SEM_PRECOND_SCHWARZ: levels = 1; break;
-    case SEM_PRECOND_BLOCK_JACOBI: levels = 1; weighted = false; break;
+    case SEM_PRECOND_BLOCK_JACOBI: levels = 1; weight = kWeightNone; break;
+    case SEM_PRECOND_HSMG_SYM: weight = kWeightSym; break;
     default: return fail(SEM_ERR_INVALID_ARG, "unknown preconditioner kind");
     }
     size_t need = 0;
@@ -972,7 +1272,7 @@ sem_status sem_precond_apply(const sem_mesh *mesh, int kind, double h1, double h
     double *rg = (double *)base, *zg = (double *)(base + v);
     HsmgBufs hb = hsmg_bufs_carve(m, base + 2 * v);
     SEM_HIP_TRY(cg_gather<double>(m, r_local, rg, s));
-    SEM_HIP_TRY(hsmg_apply(m, h1, h2, rg, zg, hb, levels, weighted, s));
+    SEM_HIP_TRY(hsmg_apply(m, h1, h2, rg, zg, hb, levels, weight, s));
     SEM_HIP_TRY(cg_scatter<double>(m, zg, z_local, s));
     return SEM_OK;
 }

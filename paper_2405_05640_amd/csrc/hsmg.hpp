@@ -39,23 +39,28 @@ void hsmg_release(Mesh &m);
 
 // Work buffers of one preconditioner application.
 struct HsmgBufs {
-    double *rows_f;   // fine local rows (n_local): Schwarz corrections, then + prolongation
+    double *rows_f;   // fine local rows (n_local): Schwarz corrections
     double *rows_m;   // mid local rows (E * 64): restricted residual, then Schwarz corrections
     double *rm;       // mid assembled residual (ng_m)
     double *zm;       // mid assembled correction (ng_m)
     double *rows_c;   // coarse local rows (E * 8)
     double *rc;       // coarse assembled residual (ng_c)
     double *tc;       // coarse scratch (ng_c)
+    double *zp;       // fine assembled prolongation of the mid correction (n_global)
 };
 size_t hsmg_bufs_bytes(const Mesh &m);
 HsmgBufs hsmg_bufs_carve(const Mesh &m, char *base);
 
+// Weighting of the Schwarz corrections over node copies: none (sum), the
+// average (1/mult after the sum), or symmetric (1/sqrt(mult) on the residual
+// before the local solves and on the sum after them).
+enum { kWeightNone = 0, kWeightAvg = 1, kWeightSym = 2 };
+
 // z = M r on assembled fine vectors (z and r distinct; both zero on
-// Dirichlet nodes).  weighted = false skips the 1/mult averaging of the
-// fine level and every coarser level (block-Jacobi use: levels = 1).
-// levels: 1 = fine Schwarz only, 3 = the full three-level cycle.
+// Dirichlet nodes).  levels: 1 = fine Schwarz only, 3 = the full
+// three-level cycle; weight applies to the fine and mid levels.
 hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, double *z, const HsmgBufs &b,
-                      int levels, bool weighted, hipStream_t s);
+                      int levels, int weight, hipStream_t s);
 
 // Flexible GMRES work buffers: V [(m+1) ng], Z [m ng], block partials,
 // reduction stage, device vectors of inner products and of y.
@@ -74,12 +79,13 @@ GmresBufs gmres_bufs_carve(const Mesh &m, int mres, char *base);
 sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
                             CgState *st, const GmresBufs &gb, hipStream_t s, sem_solve_report *rep, CgState &h);
 
-// CG with the block-Jacobi preconditioner (unweighted element-local
-// separable solves); z: assembled scratch vector; same conventions as the
-// FP64 Jacobi-PCG (device scalars, host polls every check_every iterations,
-// true-residual restarts).
-sem_status solve_pcg_block_jacobi(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
-                                  double *z, CgState *st, const HsmgBufs &hb, double *hist, int hist_len,
-                                  int check_every, hipStream_t s, sem_solve_report *rep, CgState &h);
+// CG with a symmetric positive definite preconditioner: levels = 1 is the
+// block-Jacobi one (unweighted element-local separable solves), levels = 3
+// the hybrid Schwarz multigrid with symmetric weighting; z: assembled
+// scratch vector; same conventions as the FP64 Jacobi-PCG (device scalars,
+// host polls every check_every iterations, true-residual restarts).
+sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
+                             double *z, CgState *st, const HsmgBufs &hb, int levels, double *hist, int hist_len,
+                             int check_every, hipStream_t s, sem_solve_report *rep, CgState &h);
 
 }  // namespace sem

@@ -62,7 +62,10 @@ bool uses_fcg(int form)
     return form == SEM_FORM_FCG_LEARNED || form == SEM_FORM_FCG_INNER_FP32 || form == SEM_FORM_FCG_INNER_BF16;
 }
 // forms that need the two extra assembled FP64 vectors z and q
-bool uses_zq(int form) { return uses_fcg(form) || form == SEM_FORM_PCG_1RED || form == SEM_FORM_PCG_BLOCK_JACOBI; }
+bool uses_zq(int form)
+{
+    return uses_fcg(form) || form == SEM_FORM_PCG_1RED || form == SEM_FORM_PCG_BLOCK_JACOBI || form == SEM_FORM_PCG_HSMG;
+}
 int gmres_restart(const sem_solve_opts &o) { return o.restart > 0 ? std::min(o.restart, kGmresMaxRestart) : kGmresMaxRestart; }
 
 Workspace carve(const Mesh &m, const sem_solve_opts &o, int hist_len, char *base)
@@ -108,7 +111,7 @@ Workspace carve(const Mesh &m, const sem_solve_opts &o, int hist_len, char *base
         char *p = take(gmres_bufs_bytes(m, mres));
         if (base) ws.gm = gmres_bufs_carve(m, mres, p);
     }
-    if (form == SEM_FORM_PCG_BLOCK_JACOBI) {
+    if (form == SEM_FORM_PCG_BLOCK_JACOBI || form == SEM_FORM_PCG_HSMG) {
         char *p = take(hsmg_bufs_bytes(m));
         if (base) ws.hb = hsmg_bufs_carve(m, p);
     }
@@ -165,6 +168,7 @@ sem_status check_opts(const Mesh &m, const sem_solve_opts *o)
         return SEM_OK;
     case SEM_FORM_GMRES_HSMG:
     case SEM_FORM_PCG_BLOCK_JACOBI:
+    case SEM_FORM_PCG_HSMG:
         if (!m.hsmg) return fail(SEM_ERR_INVALID_ARG, "this form needs a mesh created with SEM_PREP_HSMG");
         if (!(o->h1 > 0.0)) return fail(SEM_ERR_INVALID_ARG, "the multigrid and block-Jacobi forms need h1 > 0");
         if (o->h2 < 0.0) return fail(SEM_ERR_INVALID_ARG, "h2 must be >= 0");
@@ -536,9 +540,9 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
         SEM_TRY(solve_reliable(m, *opts, ws, hist_len, s, check_every, rep, h));
     else if (opts->form == SEM_FORM_GMRES_HSMG)
         SEM_TRY(solve_gmres_hsmg(m, *opts, ws.v64, ws.b64, ws.st64, ws.gm, s, rep, h));
-    else if (opts->form == SEM_FORM_PCG_BLOCK_JACOBI)
-        SEM_TRY(solve_pcg_block_jacobi(m, *opts, ws.v64, ws.b64, ws.z, ws.st64, ws.hb, ws.hist, hist_len, check_every,
-                                       s, rep, h));
+    else if (opts->form == SEM_FORM_PCG_BLOCK_JACOBI || opts->form == SEM_FORM_PCG_HSMG)
+        SEM_TRY(solve_pcg_precond(m, *opts, ws.v64, ws.b64, ws.z, ws.st64, ws.hb,
+                                  opts->form == SEM_FORM_PCG_HSMG ? 3 : 1, ws.hist, hist_len, check_every, s, rep, h));
     else if (opts->form == SEM_FORM_FCG_LEARNED)
         SEM_TRY(solve_fcg(m, opts->smoother->s, *opts, ws.v64, ws.b64, ws.z, ws.q, ws.st64, ws.hist, hist_len,
                           check_every, s, rep, h));
@@ -550,7 +554,7 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
     rep->true_rel_res = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
     if (opts->history && opts->history_len > 0 &&
         (opts->form == SEM_FORM_JACOBI_PCG || opts->form == SEM_FORM_PCG_1RED || opts->form == SEM_FORM_PCG_BLOCK_JACOBI ||
-         uses_fcg(opts->form))) {
+         opts->form == SEM_FORM_PCG_HSMG || uses_fcg(opts->form))) {
         const int n = std::min(opts->history_len, std::min(h.it + 1, hist_len));
         SEM_HIP_TRY(hipMemcpyAsync(opts->history, ws.hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
         SEM_HIP_TRY(hipStreamSynchronize(s));

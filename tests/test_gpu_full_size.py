@@ -81,6 +81,7 @@ FORMS = [("fp64_pcg", sem.FORM_JACOBI_PCG, {}),
          ("reliable_fp32", sem.FORM_RELIABLE_FP32, {"inner_tol": 0.1}),
          ("reliable_bf16split", sem.FORM_RELIABLE_BF16, {"inner_tol": 0.1}),
          ("gmres_hsmg", sem.FORM_GMRES_HSMG, {}),
+         ("pcg_hsmg", sem.FORM_PCG_HSMG, {}),
          ("pcg_block_jacobi", sem.FORM_PCG_BLOCK_JACOBI, {})]
 
 

@@ -48,7 +48,8 @@ def test_preconditioners_match_oracle(case):
     z = torch.empty(gm.shape, dtype=torch.float64, device="cuda")
     refs = {sem.PRECOND_HSMG: pc.apply(r, h1, h2),
             sem.PRECOND_SCHWARZ: pc.sw_f.smooth(r, h1, h2),
-            sem.PRECOND_BLOCK_JACOBI: hsmg.block_jacobi(pc.sw_f, r, h1, h2)}
+            sem.PRECOND_BLOCK_JACOBI: hsmg.block_jacobi(pc.sw_f, r, h1, h2),
+            sem.PRECOND_HSMG_SYM: pc.apply(r, h1, h2, sym=True)}
     for kind, ref in refs.items():
         gm.precond(dev(r), z, kind=kind, h1=h1, h2=h2)
         zh = host(z)
@@ -99,6 +100,24 @@ def test_block_jacobi_cg_matches_oracle(case):
     assert abs(rep.iterations - info["iterations"]) <= max(1, info["iterations"] // 50)
 
 
+def test_pcg_hsmg_solve_matches_oracle(case):
+    # CG with the symmetric multigrid preconditioner
+    import torch
+    name, om, gm, h1, h2, pc = case
+    rng = np.random.default_rng(16)
+    b = om.rhs(rng.standard_normal(om.shape))
+    xo, info = hsmg.pcg(om, b, lambda q: pc.apply(q, h1, h2, sym=True), h1, h2, tol=1e-10)
+    x = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
+    rep = gm.pcg_solve(dev(b), x, h1=h1, h2=h2, rel_tol=1e-10, form=sem.FORM_PCG_HSMG)
+    xh = host(x)
+    res = b - om.apply_S(xh, h1, h2)
+    true_rel = np.sqrt(om.dot(res, res) / om.dot(b, b))
+    print("%s: CG + symmetric HSMG %d iterations (oracle %d), true rel res %.2e" %
+          (name, rep.iterations, info["iterations"], true_rel))
+    assert true_rel <= 1.05e-10
+    assert abs(rep.iterations - info["iterations"]) <= max(1, info["iterations"] // 20)
+
+
 def test_gmres_restart_and_history():
     # a short restart length forces several cycles; the residual history is
     # non-increasing within each cycle and ends below the tolerance
@@ -124,7 +143,7 @@ def test_gmres_hsmg_edge_cases_and_checks():
     om, gm = pair(wl.channel(3, 5), prepare=sem.SEM_PREP_HSMG)
     b = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
     x = torch.ones_like(b)
-    for form in (sem.FORM_GMRES_HSMG, sem.FORM_PCG_BLOCK_JACOBI):
+    for form in (sem.FORM_GMRES_HSMG, sem.FORM_PCG_BLOCK_JACOBI, sem.FORM_PCG_HSMG):
         rep = gm.pcg_solve(b, x, form=form)
         assert rep.status == 0 and rep.iterations == 0 and torch.count_nonzero(x) == 0
     rng = np.random.default_rng(15)
