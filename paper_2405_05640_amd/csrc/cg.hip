@@ -188,19 +188,11 @@ __device__ __forceinline__ void alpha_finalize(CgState *st, double pw)
     }
 }
 
-// alpha = rz / (p, S p) from n <= kDirectMax per-element partials, one launch
+// alpha = rz / (p, S p) from n partials (per element, or the stage sums)
 __global__ void __launch_bounds__(kWide) alpha_direct_kernel(CgState *st, const double *__restrict__ part, int64_t n)
 {
     const double pw = wide_sum(part, n);
     if (threadIdx.x == 0 && !st->done) alpha_finalize(st, pw);
-}
-
-// alpha from the kStage sums of the two-stage reduction (more partials)
-__global__ void __launch_bounds__(kBS) alpha_kernel(CgState *st, const double *__restrict__ stage)
-{
-    if (st->done) return;
-    const double pw = block_sum(stage, kStage);
-    if (threadIdx.x == 0) alpha_finalize(st, pw);
 }
 
 // iteration count, residual history, convergence test and beta
@@ -227,8 +219,6 @@ __device__ __forceinline__ void beta_finalize(CgState *st, double rr, double rz,
 // (r,r), (r, dinv r).  RPB rows per workgroup, unrolled so that the loads of
 // all of them are in flight together; NPC = N + 1 fixed at compile time
 // (0: any order).
-// Workgroups stride over groups of RPB rows (at most kUpdateBlocks of them,
-// so that one wide workgroup sums the partials).
 template <typename T, int RPB, int NPC>
 __global__ void __launch_bounds__(kBS)
 update_kernel(const CgState *__restrict__ st, const T *__restrict__ w, T *__restrict__ x, T *__restrict__ r,
@@ -237,10 +227,8 @@ update_kernel(const CgState *__restrict__ st, const T *__restrict__ w, T *__rest
     if (st->done) return;
     const T alpha = (T)st->alpha;
     double acc[2] = {0.0, 0.0};
-    const int nrows = (int)(L.ny * L.nz), ny = (int)L.ny, nx = (int)L.nx;
-    const int ngroups = (nrows + RPB - 1) / RPB;
-    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x)
-    for (int gi = threadIdx.x, row0 = grp * RPB; gi < nx; gi += kBS) {
+    const int nrows = (int)(L.ny * L.nz), row0 = (int)blockIdx.x * RPB, ny = (int)L.ny, nx = (int)L.nx;
+    for (int gi = threadIdx.x; gi < nx; gi += kBS) {
         T d[RPB], xg[RPB], pg[RPB], rg0[RPB], wg[RPB];
         int64_t g[RPB];
 #pragma unroll
@@ -266,8 +254,8 @@ update_kernel(const CgState *__restrict__ st, const T *__restrict__ w, T *__rest
     block_store<2>(acc, part, gridDim.x);
 }
 
-// (r, r) and (r, z) from nb <= kDirectMax update partials: iteration count,
-// convergence test and beta in one launch
+// (r, r) and (r, z) from nb partials each (per workgroup, or the stage
+// sums): iteration count, convergence test and beta
 __global__ void __launch_bounds__(kWide) beta_direct_kernel(CgState *st, const double *__restrict__ part, int nb,
                                                              double *hist)
 {
@@ -595,7 +583,7 @@ hipError_t cg_init(const Mesh &m, const CgVecs<T> &v, const T *b, CgState *st, d
 template <typename T>
 hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, double *hist, hipStream_t s)
 {
-    const unsigned nb = std::min<unsigned>(row_grid(m.lat, update_rpb<T>()), kUpdateBlocks);
+    const unsigned nb = row_grid(m.lat, update_rpb<T>());
     hipError_t e = cg_alpha(m, v.part_e, v.stage, st, s);
     if (e != hipSuccess) return e;
     constexpr int RPB = update_rpb<T>();
@@ -605,7 +593,10 @@ hipError_t cg_step_after_ax(const Mesh &m, const CgVecs<T> &v, CgState *st, doub
     else
         hipLaunchKernelGGL((cg::update_kernel<T, RPB, 0>), dim3(nb), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,
                            m.lat, v.part_b);
-    hipLaunchKernelGGL(cg::beta_direct_kernel, dim3(1), dim3(kWide), 0, s, st, v.part_b, (int)nb, hist);
+    const double *in = v.part_b;
+    int64_t n = nb;
+    if ((e = finalize_input(v.part_b, n, 2, v.stage, s, &in)) != hipSuccess) return e;
+    hipLaunchKernelGGL(cg::beta_direct_kernel, dim3(1), dim3(kWide), 0, s, st, in, (int)n, hist);
     L3((cg::p_kernel<T>), m.ng) st, v.p, v.r, v.dinv, m.ng);
     return hipGetLastError();
 }
@@ -691,15 +682,23 @@ hipError_t cg_reduce(const double *part, int64_t n, int nv, double *stage, hipSt
     return hipGetLastError();
 }
 
+hipError_t finalize_input(const double *part, int64_t &n, int nv, double *stage, hipStream_t s, const double **in)
+{
+    *in = part;
+    if (n <= kDirectMax) return hipSuccess;
+    hipError_t e = cg_reduce(part, n, nv, stage, s);
+    *in = stage;
+    n = kStage;
+    return e;
+}
+
 hipError_t cg_alpha(const Mesh &m, const double *part_e, double *stage, CgState *st, hipStream_t s)
 {
-    if (m.E <= kDirectMax) {
-        hipLaunchKernelGGL(cg::alpha_direct_kernel, dim3(1), dim3(kWide), 0, s, st, part_e, m.E);
-        return hipGetLastError();
-    }
-    hipError_t e = cg_reduce(part_e, m.E, 1, stage, s);
+    const double *in = part_e;
+    int64_t n = m.E;
+    hipError_t e = finalize_input(part_e, n, 1, stage, s, &in);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(cg::alpha_kernel, dim3(1), dim3(kBS), 0, s, st, stage);
+    hipLaunchKernelGGL(cg::alpha_direct_kernel, dim3(1), dim3(kWide), 0, s, st, in, n);
     return hipGetLastError();
 }
 

@@ -9,7 +9,6 @@ namespace sem {
 
 constexpr int kBS = 256;             // threads per block of the vector kernels
 constexpr int kMaxVecBlocks = 4096;  // grid cap of the flat vector kernels
-constexpr int kUpdateBlocks = 4096;  // grid cap of the row-update kernels (their partials feed one wide block)
 constexpr int kStage = 256;          // second-stage partial sums
 
 // Grid of the per-node kernels: one workgroup per lattice row (gj, gk).
@@ -69,6 +68,10 @@ template <typename T>
 hipError_t cg_resid(const Mesh &m, const CgVecs<T> &v, const T *b, T *r, CgState *st, hipStream_t s);
 template <typename T> hipError_t cg_restart(const Mesh &m, const CgVecs<T> &v, CgState *st, hipStream_t s);
 // alpha from the per-element partials of (p, S p) (reduces them first)
+// Input of a one-workgroup finalize over nv quantities of n partials each
+// (part[q * n + b]): the partials themselves when n <= kDirectMax, else the
+// kStage sums of a queued two-stage reduction (then n = kStage).
+hipError_t finalize_input(const double *part, int64_t &n, int nv, double *stage, hipStream_t s, const double **in);
 hipError_t cg_alpha(const Mesh &m, const double *part_e, double *stage, CgState *st, hipStream_t s);
 // e = x - e on assembled vectors
 hipError_t cg_rsub(const Mesh &m, const double *x, double *e, hipStream_t s);

@@ -671,7 +671,7 @@ __global__ void __launch_bounds__(kBS) bj_dot_kernel(const CgState *st, const do
     block_partials<1>(acc, 1, part, gridDim.x);
 }
 
-// (r, z) from nb <= kDirectMax partials: beta = (r, z) / rz_old (0 on the
+// (r, z) from nb partials (per workgroup, or the stage sums): beta = (r, z) / rz_old (0 on the
 // first call), rz = (r, z); a breakdown if (r, z) is not positive
 __global__ void __launch_bounds__(kWide) bj_rz_finalize(CgState *st, const double *__restrict__ part, int nb, int first)
 {
@@ -709,10 +709,9 @@ __global__ void __launch_bounds__(kBS) bj_start_finalize(CgState *st, const doub
     }
 }
 
-// wg = Q^T rows; x += alpha p; r -= alpha wg; partial (r, r).  Workgroups
-// stride over groups of kRowsPerBlock lattice rows (at most kUpdateBlocks
-// workgroups), with every load of a node issued before its arithmetic;
-// NPC = N + 1 fixed at compile time (0: any order).
+// wg = Q^T rows; x += alpha p; r -= alpha wg; partial (r, r).  kRowsPerBlock
+// lattice rows per workgroup with every load of a node issued before its
+// arithmetic; NPC = N + 1 fixed at compile time (0: any order).
 template <int NPC>
 __global__ void __launch_bounds__(kBS)
 bj_update_kernel(const CgState *__restrict__ st, const double *__restrict__ rows, double *__restrict__ x,
@@ -722,10 +721,8 @@ bj_update_kernel(const CgState *__restrict__ st, const double *__restrict__ rows
     if (st->done) return;
     const double alpha = st->alpha;
     double acc[1] = {0.0};
-    const int nrows = (int)(L.ny * L.nz), ny = (int)L.ny, nx = (int)L.nx;
-    const int ngroups = (nrows + kRowsPerBlock - 1) / kRowsPerBlock;
-    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x)
-    for (int gi = threadIdx.x, row0 = grp * kRowsPerBlock; gi < nx; gi += kBS) {
+    const int nrows = (int)(L.ny * L.nz), ny = (int)L.ny, nx = (int)L.nx, row0 = (int)blockIdx.x * kRowsPerBlock;
+    for (int gi = threadIdx.x; gi < nx; gi += kBS) {
         double d[kRowsPerBlock], xg[kRowsPerBlock], pg[kRowsPerBlock], rg0[kRowsPerBlock], wg[kRowsPerBlock];
         int64_t g[kRowsPerBlock];
 #pragma unroll
@@ -750,8 +747,8 @@ bj_update_kernel(const CgState *__restrict__ st, const double *__restrict__ rows
     block_partials<1>(acc, 1, part, gridDim.x);
 }
 
-// (r, r) from nb <= kDirectMax partials: iteration count, residual history,
-// convergence test
+// (r, r) from nb partials (per workgroup, or the stage sums): iteration
+// count, residual history, convergence test
 __global__ void __launch_bounds__(kWide) bj_check_finalize(CgState *st, const double *__restrict__ part, int nb,
                                                            double *hist)
 {
@@ -1163,8 +1160,7 @@ sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVec
     const int weight = levels == 1 ? kWeightNone : kWeightSym;
     const int64_t ng = m.ng;
     const int nbf = cg_blocks(ng);
-    const int nbu = (int)std::min<int64_t>((m.lat.ny * m.lat.nz + mg::kRowsPerBlock - 1) / mg::kRowsPerBlock,
-                                           kUpdateBlocks);
+    const int nbu = (int)((node_grid(m.lat) + mg::kRowsPerBlock - 1) / mg::kRowsPerBlock);
     CgState init{};
     init.max_it = o.max_iter;
     init.hist_len = hist_len;
@@ -1179,7 +1175,10 @@ sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVec
     auto direction = [&](int first) -> sem_status {
         SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, v.r, z, hb, levels, weight, s));
         hipLaunchKernelGGL(mg::bj_dot_kernel, dim3(nbf), dim3(kBS), 0, s, st, v.r, z, ng, v.part_b);
-        hipLaunchKernelGGL(mg::bj_rz_finalize, dim3(1), dim3(kWide), 0, s, st, v.part_b, nbf, first);
+        const double *in;
+        int64_t n = nbf;
+        SEM_HIP_TRY(finalize_input(v.part_b, n, 1, v.stage, s, &in));
+        hipLaunchKernelGGL(mg::bj_rz_finalize, dim3(1), dim3(kWide), 0, s, st, in, (int)n, first);
         if (first)
             hipLaunchKernelGGL(mg::scale_kernel, dim3(nbf), dim3(kBS), 0, s, z, v.p, ng, 1.0);
         else
@@ -1202,7 +1201,10 @@ sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVec
                 else
                     hipLaunchKernelGGL(mg::bj_update_kernel<0>, dim3(nbu), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
                                        v.dinv, m.lat, v.part_b);
-                hipLaunchKernelGGL(mg::bj_check_finalize, dim3(1), dim3(kWide), 0, s, st, v.part_b, nbu, hist);
+                const double *in;
+                int64_t n = nbu;
+                SEM_HIP_TRY(finalize_input(v.part_b, n, 1, v.stage, s, &in));
+                hipLaunchKernelGGL(mg::bj_check_finalize, dim3(1), dim3(kWide), 0, s, st, in, (int)n, hist);
                 SEM_TRY(direction(0));
             }
         }

@@ -8,10 +8,12 @@
 namespace sem {
 
 // A scalar finalize (alpha, beta, the convergence test) needs the sum of the
-// per-workgroup partials of the kernel before it.  When there are at most
-// kDirectMax of them, one workgroup of kWide threads sums them and runs the
-// finalize in the same launch (one launch per scalar instead of a stage
-// kernel plus a finalize kernel).
+// per-workgroup partials of the kernel before it.  One workgroup of kWide
+// threads sums them and runs the finalize in the same launch when there are
+// at most kDirectMax of them; with more, a kStage-workgroup stage kernel runs
+// first (one workgroup reading ~25,000 partials per quantity was measured
+// slower than the two launches on the 32^3 mesh; with ~6,000, as on the 16^3
+// channel, the single launch wins by about 4 % of the CG iteration).
 //
 // Doing the sum inside the producing kernel (the workgroup that finishes
 // last finalizes) was measured and rejected: each XCD has its own L2, so
@@ -20,7 +22,7 @@ namespace sem {
 // FP64 CG iteration on the 32^3 mesh took 1.5 ms (release and acquire
 // fences split) to 3.9 ms (full fences), against 0.41 ms.
 constexpr int kWide = 1024;
-constexpr int64_t kDirectMax = 1 << 16;
+constexpr int64_t kDirectMax = 1 << 14;
 
 // Fixed-order sums of a[0..n) and b[0..n) (b may be null) by one workgroup
 // of kWide threads, every thread gets both: strided per-thread sums with up
