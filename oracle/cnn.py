@@ -19,6 +19,8 @@ out plainly:
   zero network gives exactly Jacobi, and M(a r) = a M(r) for a > 0.
 * Loss of one pair (r, e) with e the error that r belongs to (S e = r):
       L = ||e - M(r)||_S^2 / ||e||_S^2,
+  or, trained in the context of the learned multigrid, with M(r) + C(r) in
+  place of M(r), C the fixed coarser-level part,
   dL/dz = -2 S (e - M(r)) / ||e||_S^2 (z = M(r)), and
   dL/dc_l = dL/dz_{glo(l)} / mult_l on free nodes.
 * Training updates the weights with Adam (Kingma & Ba 2015): with gradient
@@ -143,9 +145,14 @@ def smoother(mesh, net, r, dinv, keep=False):
     return z
 
 
-def loss_and_grad(mesh, net, r, e, dinv, h1=1.0, h2=0.0):
-    """A-norm loss of one (r, e) pair and its weight gradients."""
+def loss_and_grad(mesh, net, r, e, dinv, h1=1.0, h2=0.0, extra=None):
+    """A-norm loss of one (r, e) pair and its weight gradients.  extra: a
+    fixed field added to the smoother output before the loss (training in
+    context: the coarser levels' part of the learned multigrid, so that the
+    network learns what those levels leave over)."""
     z, (cache, t, live) = smoother(mesh, net, r, dinv, keep=True)
+    if extra is not None:
+        z = z + extra
     Se = mesh.apply_S(e, h1, h2)
     en = mesh.dot(e, Se)
     d = e - z

@@ -63,7 +63,9 @@ combines them): for a fine residual r,
 
   z = Sw_0(r) + P_01 [ Sw_1(R_10 r) + P_12 C^-1 R_21 R_10 r ]
 
-with Sw_l the level-l Schwarz smoother and C^-1 the coarse solve.  In the
+with Sw_l the level-l Schwarz smoother and C^-1 the coarse solve.  The
+learned multigrid (not in the paper) keeps the two coarser levels and puts
+the learned smoother of oracle/cnn.py in place of Sw_0.  In the
 symmetric variant each Sw_l = W^1/2 K_l W^1/2 (W = 1/mult) instead of W K_l,
 which makes the whole preconditioner symmetric positive definite, so that CG
 can use it.
@@ -329,17 +331,25 @@ class HSMG:
         self.sw_m = SchwarzLevel(self.mid)
         self.coarse = CoarseSolver(self.crs)
 
-    def apply(self, r, h1=1.0, h2=0.0, sym=False):
+    def apply(self, r, h1=1.0, h2=0.0, sym=False, fine=None):
         """z = M r; sym: the symmetric weighting on the fine and mid levels
-        (a symmetric positive definite M, for CG)."""
+        (a symmetric positive definite M, for CG).  fine: a callable r -> z
+        that replaces the fine Schwarz level (the learned multigrid puts the
+        learned smoother there); the coarser levels are unchanged."""
         r = np.asarray(r).reshape(self.fine.shape)
-        z = self.sw_f.smooth(r, h1, h2, sym=sym)
+        z = self.sw_f.smooth(r, h1, h2, sym=sym) if fine is None else fine(r)
+        return z + self.coarse_part(r, h1, h2, sym)
+
+    def coarse_part(self, r, h1=1.0, h2=0.0, sym=False):
+        """P_01 [Sw_1(R_10 r) + P_12 C^-1 R_21 R_10 r]: what the middle and
+        coarse levels add to the fine level's output."""
+        r = np.asarray(r).reshape(self.fine.shape)
         r1 = restrict(self.J_fm, self.fine, self.mid, r)
         z1 = self.sw_m.smooth(r1, h1, h2, sym=sym)
         r2 = restrict(self.J_mc, self.mid, self.crs, r1)
         z2 = self.coarse.solve(r2, h1, h2)
         z1 = z1 + prolong(self.J_mc, self.crs, self.mid, z2)
-        return z + prolong(self.J_fm, self.mid, self.fine, z1)
+        return prolong(self.J_fm, self.mid, self.fine, z1)
 
 
 def block_jacobi(level, r, h1, h2):

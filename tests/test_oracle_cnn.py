@@ -77,25 +77,33 @@ def test_zero_net_is_jacobi_and_homogeneity():
     assert np.all(z[m.mask == 1] == 0)
 
 
-@pytest.mark.parametrize("h2", [0.0, 0.1])
-def test_loss_gradient_matches_finite_differences(h2):
+@pytest.mark.parametrize("h2,with_extra", [(0.0, False), (0.1, False), (0.1, True)])
+def test_loss_gradient_matches_finite_differences(h2, with_extra):
+    # with_extra: the in-context loss of the learned multigrid, where a fixed
+    # coarser-level field is added to the smoother output
     m = _mesh(wl.deformed_cube(2, 7, amp=0.2))
     rng = np.random.default_rng(4)
     net = cnn.Net.init(4, seed=2)
     net.W[2] = rng.standard_normal(net.W[2].shape) * 0.1
     r, e = _pair(m, rng, h2)
     dinv = m.jacobi_inv(1.0, h2)
-    L, grads = cnn.loss_and_grad(m, net, r, e, dinv, 1.0, h2)
+    extra = None
+    if with_extra:
+        extra = brute.continuous_random(m, rng) * 0.3 * np.max(np.abs(e))
+    L, grads = cnn.loss_and_grad(m, net, r, e, dinv, 1.0, h2, extra=extra)
     assert 0 < L
+    if with_extra:
+        L0, g0 = cnn.loss_and_grad(m, net, r, e, dinv, 1.0, h2)
+        assert L != L0 and not np.allclose(grads[1], g0[1])
     h = 1e-6
     picks = [(0, (1, 0, 1, 1, 1)), (0, (3, 1, 0, 2, 1)), (1, (2, 3, 1, 1, 0)), (1, (0, 0, 2, 2, 2)),
              (2, (0, 1, 1, 1, 1)), (2, (0, 3, 0, 1, 2))]
     for layer, idx in picks:
         W0 = net.W[layer][idx]
         net.W[layer][idx] = W0 + h
-        Lp, _ = cnn.loss_and_grad(m, net, r, e, dinv, 1.0, h2)
+        Lp, _ = cnn.loss_and_grad(m, net, r, e, dinv, 1.0, h2, extra=extra)
         net.W[layer][idx] = W0 - h
-        Lm, _ = cnn.loss_and_grad(m, net, r, e, dinv, 1.0, h2)
+        Lm, _ = cnn.loss_and_grad(m, net, r, e, dinv, 1.0, h2, extra=extra)
         net.W[layer][idx] = W0
         fd = (Lp - Lm) / (2 * h)
         g = grads[layer][idx]

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import hsmg
+from oracle import cnn, hsmg
 from paper_2405_05640_amd import workloads as wl
 from tests import brute
 
@@ -266,3 +266,46 @@ def test_symmetric_hsmg_is_spd_and_serves_cg():
           (ci["iterations"], gi["iterations"]))
     assert ci["true_rel_res"] <= 1.05e-10
     assert ci["iterations"] <= gi["iterations"] + 5
+
+
+def test_learned_multigrid_composition():
+    # the learned multigrid keeps the middle and coarse levels and puts the
+    # learned smoother in place of the fine Schwarz level.  With a zero
+    # network the fine level is Jacobi, and with the symmetric middle level
+    # the whole preconditioner is then symmetric positive definite (a
+    # transposed restriction or prolongation would break the symmetry)
+    m = _mesh(wl.random_deformed_box(2, 2, 2, 4, seed=18, amp=0.1))
+    pc = hsmg.HSMG(m)
+    dinv = m.jacobi_inv()
+    zero = cnn.Net.init(4, seed=0)
+    _, free = brute.dense_S(m)
+    glo = m.glo.ravel()
+    M = np.zeros((len(free), len(free)))
+    for c, g in enumerate(free):
+        u = (glo == g).astype(np.float64).reshape(m.shape)
+        M[:, c] = m.gather_global(pc.apply(u, sym=True, fine=lambda q: cnn.smoother(m, zero, q, dinv)))[free]
+    assert np.allclose(M, M.T, rtol=0, atol=1e-13 * np.max(np.abs(M)))
+    assert np.min(np.linalg.eigvalsh(0.5 * (M + M.T))) > 0
+    # the coarser levels' part is what the full cycle adds to its fine level
+    rng = np.random.default_rng(19)
+    r = brute.continuous_random(m, rng)
+    assert np.allclose(pc.apply(r) - pc.sw_f.smooth(r, 1.0, 0.0), pc.coarse_part(r), rtol=0, atol=1e-13)
+
+
+def test_learned_multigrid_fgmres_converges():
+    # flexible GMRES with the learned multigrid (a random network: a
+    # nonlinear, non-symmetric preconditioner) reaches 1e-10, in far fewer
+    # iterations than Jacobi-PCG
+    m = _mesh(wl.random_deformed_box(3, 3, 2, 5, seed=20, amp=0.1, periodic=(1, 0, 0), dirichlet=0x3c))
+    pc = hsmg.HSMG(m)
+    dinv = m.jacobi_inv()
+    net = cnn.Net.init(4, seed=3)
+    net.W[2] = np.random.default_rng(21).standard_normal(net.W[2].shape) * 0.05
+    rng = np.random.default_rng(22)
+    b = m.rhs(rng.standard_normal(m.shape))
+    x, info = hsmg.fgmres(m, b, lambda q: pc.apply(q, fine=lambda t: cnn.smoother(m, net, t, dinv)), tol=1e-10)
+    _, pinfo = m.pcg(b, tol=1e-10)
+    res = b - m.apply_S(x)
+    print("learned multigrid FGMRES %d iterations, Jacobi-PCG %d" % (info["iterations"], pinfo["iterations"]))
+    assert np.sqrt(m.dot(res, res) / m.dot(b, b)) <= 1.05e-10
+    assert info["iterations"] < 0.6 * pinfo["iterations"]
