@@ -202,12 +202,18 @@ typedef enum {
                                     element's separable local solve (the fine level of
                                     SEM_FORM_GMRES_HSMG, unweighted, so symmetric positive
                                     definite).  Needs SEM_PREP_HSMG and h1 > 0. */
-    SEM_FORM_PCG_HSMG = 11       /* FP64 CG with the hybrid Schwarz multigrid in its symmetric
+    SEM_FORM_PCG_HSMG = 11,      /* FP64 CG with the hybrid Schwarz multigrid in its symmetric
                                     weighting (1/sqrt(mult) before the local solves and after their
                                     sum, on the fine and mid levels; symmetric positive definite):
                                     the same preconditioner family as SEM_FORM_GMRES_HSMG at CG's
                                     cost per iteration (no growing Krylov basis).  Needs
                                     SEM_PREP_HSMG and h1 > 0. */
+    SEM_FORM_GMRES_LEARNED_MG = 12 /* flexible GMRES(m) as SEM_FORM_GMRES_HSMG with the learned
+                                    multigrid: the learned smoother (opts.smoother, BF16
+                                    inference) in place of the fine Schwarz level, the paper's
+                                    middle and coarse levels kept (not in the paper).  A zero
+                                    network makes the fine level Jacobi.  Needs SEM_PREP_HSMG,
+                                    N = 7 and h1 > 0. */
 } sem_form;
 
 /* Hybrid Schwarz multigrid (SEM_FORM_GMRES_HSMG), for an assembled fine
@@ -306,6 +312,10 @@ typedef struct {
     double stall_rate;        /* per-iteration residual reduction of plain Jacobi-PCG on the same
                                  problem; a window reducing less than rate^window switches to
                                  Jacobi-PCG.  0 disables the stall test. */
+    int32_t mg_context;       /* != 0: train for the learned multigrid.  The loss then uses
+                                 M(r) + C(r), C(r) the middle and coarse levels' part of the
+                                 cycle (fixed), so the network learns what those levels leave
+                                 over.  Needs a mesh created with SEM_PREP_HSMG. */
 } sem_smoother_desc;
 
 #define SEM_SMOOTHER_PARAMS 8208
@@ -328,6 +338,15 @@ sem_status sem_smoother_set_state(sem_smoother *sm, const float *weights, const 
  * runs the FP32 network, else the BF16 inference path.  Blocking on stream. */
 sem_status sem_smoother_apply(const sem_smoother *sm, const sem_mesh *mesh, double h1, double h2, int fp32,
                               const double *r_local, double *z_local, void *stream);
+/* z = M_mg(r): the learned multigrid, M_mg(r) = M(r) + C(r) with C(r) =
+ * P_01 [Sw_1(R_10 r) + P_12 C^-1 R_21 R_10 r] the middle and coarse levels of
+ * the hybrid Schwarz multigrid (averaged weighting; see SEM_FORM_GMRES_HSMG),
+ * for a continuous, masked local r (device double [E][P]).  fp32 as for
+ * sem_smoother_apply.  workspace: device, >= sem_precond_workspace_bytes.
+ * Needs SEM_PREP_HSMG, h1 > 0, h2 >= 0.  Async on stream. */
+sem_status sem_smoother_mg_apply(const sem_smoother *sm, const sem_mesh *mesh, double h1, double h2, int fp32,
+                                 const double *r_local, double *z_local, void *workspace, size_t ws_bytes,
+                                 void *stream);
 /* Loss L and dL/dW (FP32 path) for one error field e (continuous, masked local
  * double); loss and gradient are written to HOST memory.  Blocking. */
 sem_status sem_smoother_loss_grad(sem_smoother *sm, const sem_mesh *mesh, double h1, double h2,

@@ -40,6 +40,7 @@
 #include <vector>
 
 #include "hsmg.hpp"
+#include "nn.hpp"
 #include "reduce.hpp"
 
 namespace sem {
@@ -151,6 +152,55 @@ schwarz_kernel(const double *__restrict__ rg, Lattice L, const double *__restric
             for (int q = 0; q < NP; ++q) s += sJ[q * NPC + c] * sa[(q * NPC + b) * NPC + a];
             rows_c[rows_index32(Lc, ex, ey, ez, a, b, c)] = s;
         }
+    }
+}
+
+// Restriction alone (the learned multigrid, whose fine level is not a
+// Schwarz solve): rows_c = J^T (x) J^T (x) J^T (r / mult) per element, NPC
+// points per direction on the coarser level.  One workgroup of NP^3 threads
+// per element, thread = node (i, j, k); the same contraction order as the
+// Schwarz kernels' restriction.
+template <int NP, int NPC>
+__global__ void __launch_bounds__(NP * NP * NP)
+restrict_kernel(const double *__restrict__ rg, Lattice L, const double *__restrict__ J, Lattice Lc,
+                double *__restrict__ rows_c)
+{
+    constexpr int P2 = NP * NP;
+    __shared__ double sa[P2 * NP], sb[P2 * NP];
+    __shared__ double sJ[NP * NPC];
+    const int t = threadIdx.x, i = t % NP, j = (t / NP) % NP, k = t / P2;
+    const int64_t e = xcd_block();
+    int ex, ey, ez;
+    elem_coords(L, e, ex, ey, ez);
+    const double r = rg[gather_index32(L, ex, ey, ez, i, j, k)];
+    for (int q = t; q < NP * NPC; q += P2 * NP) sJ[q] = J[q];
+    const int gi0 = ex * L.N + i, gj0 = ey * L.N + j, gk0 = ez * L.N + k;
+    const int cnt = node_count(L, gi0 >= L.nx ? gi0 - (int)L.nx : gi0, gj0 >= L.ny ? gj0 - (int)L.ny : gj0,
+                               gk0 >= L.nz ? gk0 - (int)L.nz : gk0);
+    sa[t] = r / cnt;
+    __syncthreads();
+    if (t < NPC * P2) {
+        const int c = t % NPC, jj = (t / NPC) % NP, kk = t / (NPC * NP);
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) v += sJ[q * NPC + c] * sa[kk * P2 + jj * NP + q];
+        sb[(kk * NP + jj) * NPC + c] = v;
+    }
+    __syncthreads();
+    if (t < NPC * NPC * NP) {
+        const int a = t % NPC, b = (t / NPC) % NPC, kk = t / (NPC * NPC);
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) v += sJ[q * NPC + b] * sb[(kk * NP + q) * NPC + a];
+        sa[(kk * NPC + b) * NPC + a] = v;
+    }
+    __syncthreads();
+    if (t < NPC * NPC * NPC) {
+        const int a = t % NPC, b = (t / NPC) % NPC, c = t / (NPC * NPC);
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) v += sJ[q * NPC + c] * sa[(q * NPC + b) * NPC + a];
+        rows_c[rows_index32(Lc, ex, ey, ez, a, b, c)] = v;
     }
 }
 
@@ -929,14 +979,69 @@ hipError_t coarse_solve(const Mesh &m, double h1, double h2, const HsmgBufs &b, 
     return hipGetLastError();
 }
 
-}  // namespace
+hipError_t restrict_fine(const Mesh &m, const double *r, const HsmgBufs &b, hipStream_t s)
+{
+    const Hsmg &h = *m.hsmg;
+#define SEM_RF(NP, NPM)                                                                                              \
+    case NP:                                                                                                         \
+        hipLaunchKernelGGL((mg::restrict_kernel<NP, NPM>), dim3((unsigned)m.E), dim3(NP * NP * NP), 0, s, r, m.lat, \
+                           h.d_Jfm, h.lat_m, b.rows_m);                                                              \
+        break;
+    switch (m.NP) {
+        SEM_RF(3, 2)
+        SEM_RF(4, 3)
+        SEM_RF(5, 4)
+        SEM_RF(6, 4)
+        SEM_RF(7, 4)
+        SEM_RF(8, 4)
+        SEM_RF(9, 4)
+        SEM_RF(10, 4)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef SEM_RF
+    return hipGetLastError();
+}
 
-hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, double *z, const HsmgBufs &b, int levels,
-                      int weight, hipStream_t s)
+// mid and coarse levels from the restricted residual in b.rows_m: b.zp =
+// P_01 [Sw_1 r_1 + P_12 C^-1 R_21 r_1]
+hipError_t coarser_levels(const Mesh &m, double h1, double h2, const HsmgBufs &b, int weight, hipStream_t s)
 {
     const Hsmg &h = *m.hsmg;
     const int sym = weight == kWeightSym ? 1 : 0;
     hipError_t e;
+    launch_assemble(h.lat_m, b.rows_m, kWeightNone, b.rm, nullptr, h.lat_c, nullptr, s);
+    if ((e = mid_schwarz(m, h1, h2, b, sym, s)) != hipSuccess) return e;
+    launch_assemble(h.lat_c, b.rows_c, kWeightNone, b.rc, nullptr, h.lat_c, nullptr, s);
+    if ((e = coarse_solve(m, h1, h2, b, s)) != hipSuccess) return e;
+    launch_assemble(h.lat_m, b.rows_m, weight, b.zm, b.rc, h.lat_c, h.d_Jmc, s);
+    return prolong_fine(m, b, s);
+}
+
+}  // namespace
+
+hipError_t hsmg_coarse_part(const Mesh &m, double h1, double h2, const double *r, const HsmgBufs &b, int weight,
+                            hipStream_t s)
+{
+    hipError_t e = restrict_fine(m, r, b, s);
+    if (e != hipSuccess) return e;
+    return coarser_levels(m, h1, h2, b, weight, s);
+}
+
+hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, double *z, const HsmgBufs &b, int levels,
+                      int weight, hipStream_t s, const FineHook *fine)
+{
+    const Hsmg &h = *m.hsmg;
+    const int sym = weight == kWeightSym ? 1 : 0;
+    hipError_t e;
+    if (fine) {
+        // learned multigrid: the coarser levels, then z = M_learned(r) + zp
+        if ((e = hsmg_coarse_part(m, h1, h2, r, b, weight, s)) != hipSuccess) return e;
+        e = fine->fp32 ? nn_infer32(*fine->sm, m, r, fine->dinv, fine->c_local, s)
+                       : nn_infer<double>(*fine->sm, m, r, fine->dinv, fine->c_local, s, nullptr);
+        if (e != hipSuccess) return e;
+        return nn_assemble_z<double>(m, r, fine->dinv, fine->c_local, z, s, nullptr, b.zp);
+    }
     if (levels == 1) {
         if ((e = fine_schwarz(m, r, h1, h2, b, false, sym, s)) != hipSuccess) return e;
         launch_assemble_fine(m.lat, b.rows_f, weight, nullptr, z, s);
@@ -1018,7 +1123,8 @@ GmresBufs gmres_bufs_carve(const Mesh &m, int mres, char *base)
 }
 
 sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
-                            CgState *st, const GmresBufs &gb, hipStream_t s, sem_solve_report *rep, CgState &h)
+                            CgState *st, const GmresBufs &gb, hipStream_t s, sem_solve_report *rep, CgState &h,
+                            const FineHook *fine)
 {
     const int mres = o.restart > 0 ? std::min(o.restart, kGmresMaxRestart) : kGmresMaxRestart;
     const int64_t ng = m.ng;
@@ -1057,7 +1163,7 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
         bool stop = false;
         for (int j = 0; j < mres; ++j) {
             double *Vj = gb.V + (size_t)j * ng, *Vn = gb.V + (size_t)(j + 1) * ng, *Zj = gb.Z + (size_t)j * ng;
-            SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, Vj, Zj, gb.hb, 3, kWeightAvg, s));
+            SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, Vj, Zj, gb.hb, 3, kWeightAvg, s, fine));
             SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, Zj, v.w, nullptr, s));
             if (m.NP == 8)
                 hipLaunchKernelGGL(mg::assemble_dots_kernel<8>, dim3(nbd), dim3(kBS), 0, s, v.w, m.lat, Vn, gb.V, ng,

@@ -56,11 +56,31 @@ HsmgBufs hsmg_bufs_carve(const Mesh &m, char *base);
 // before the local solves and on the sum after them).
 enum { kWeightNone = 0, kWeightAvg = 1, kWeightSym = 2 };
 
+struct Smoother;
+
+// The learned multigrid's fine level: the learned smoother M(r) = dinv o r
+// + mask(Q^T (c / mult)) of the network sm (BF16 inference, or the FP32
+// network if fp32), with c_local the element-output buffer and dinv the
+// assembled Jacobi inverse (0 on Dirichlet nodes).
+struct FineHook {
+    const Smoother *sm;
+    const double *dinv;
+    float *c_local;
+    int fp32;
+};
+
 // z = M r on assembled fine vectors (z and r distinct; both zero on
 // Dirichlet nodes).  levels: 1 = fine Schwarz only, 3 = the full
-// three-level cycle; weight applies to the fine and mid levels.
+// three-level cycle; weight applies to the fine and mid levels.  fine (not
+// null): the three-level cycle with the learned smoother in place of the
+// fine Schwarz level (levels is then ignored).
 hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, double *z, const HsmgBufs &b,
-                      int levels, int weight, hipStream_t s);
+                      int levels, int weight, hipStream_t s, const FineHook *fine = nullptr);
+
+// The mid and coarse levels' part alone: b.zp = P_01 [Sw_1(R_10 r) +
+// P_12 C^-1 R_21 R_10 r] (what the cycle adds to its fine level).
+hipError_t hsmg_coarse_part(const Mesh &m, double h1, double h2, const double *r, const HsmgBufs &b, int weight,
+                            hipStream_t s);
 
 // Flexible GMRES work buffers: V [(m+1) ng], Z [m ng], block partials,
 // reduction stage, device vectors of inner products and of y.
@@ -75,9 +95,11 @@ GmresBufs gmres_bufs_carve(const Mesh &m, int mres, char *base);
 // S x = b (assembled b; x from zero).  v: x, r (assembled), w (row-layout
 // operator output), dinv, part_b, stage of the caller's workspace; st: a
 // device CgState used for the true residual.  Fills h (bb, tol2, rr,
-// true_rr, done) and rep (iterations, restarts, history).
+// true_rr, done) and rep (iterations, restarts, history).  fine: the
+// learned multigrid in place of the hybrid Schwarz multigrid.
 sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
-                            CgState *st, const GmresBufs &gb, hipStream_t s, sem_solve_report *rep, CgState &h);
+                            CgState *st, const GmresBufs &gb, hipStream_t s, sem_solve_report *rep, CgState &h,
+                            const FineHook *fine = nullptr);
 
 // CG with a symmetric positive definite preconditioner: levels = 1 is the
 // block-Jacobi one (unweighted element-local separable solves), levels = 3

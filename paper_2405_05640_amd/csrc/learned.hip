@@ -349,12 +349,6 @@ TrainBufs train_bufs(const Smoother &sm)
     return t;
 }
 
-sem_status check_pair(const Smoother &sm, const Mesh &m)
-{
-    if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "the learned smoother needs order N = 7");
-    if (sm.E != m.E || sm.ng != m.ng) return fail(SEM_ERR_INVALID_ARG, "smoother was created for another mesh");
-    return SEM_OK;
-}
 
 // dinv (assembled, 0 on Dirichlet nodes) into t.dinv, using t.w as scratch,
 // unless the buffer already holds it for this mesh and h1, h2 (force = true
@@ -382,9 +376,11 @@ sem_status loss_forward(const Smoother &sm, const Mesh &m, double h1, double h2,
     // r = S e, partial (e, S e)
     SEM_HIP_TRY(launch_ax_f64_gather(m, h1, h2, t.e, t.w, nullptr, s));
     hipLaunchKernelGGL(lk::assemble_dot_kernel, dim3(nbn), dim3(kBS), 0, s, t.w, t.e, t.r, m.lat, sm.part);
-    // z = M(r) (FP32 network)
+    // z = M(r) (FP32 network), plus the coarser levels' part C(r) when
+    // training in the context of the learned multigrid
+    if (sm.mg_context) SEM_HIP_TRY(hsmg_coarse_part(m, h1, h2, t.r, sm.mg, kWeightAvg, s));
     SEM_HIP_TRY(nn_infer32(sm, m, t.r, t.dinv, sm.c_local, s));
-    SEM_HIP_TRY(nn_assemble_z<double>(m, t.r, t.dinv, sm.c_local, t.z, s, nullptr));
+    SEM_HIP_TRY(nn_assemble_z<double>(m, t.r, t.dinv, sm.c_local, t.z, s, nullptr, sm.mg_context ? sm.mg.zp : nullptr));
     // d = e - z, sd = S d, partial (d, S d)
     hipLaunchKernelGGL(lk::sub_kernel, dim3(nb), dim3(kBS), 0, s, t.e, t.z, t.d, m.ng);
     SEM_HIP_TRY(launch_ax_f64_gather(m, h1, h2, t.d, t.w, nullptr, s));
@@ -405,6 +401,16 @@ sem_status gather_local(const Mesh &m, const double *u_local, double *ug, hipStr
 }
 
 }  // namespace
+
+sem_status check_pair(const Smoother &sm, const Mesh &m)
+{
+    if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "the learned smoother needs order N = 7");
+    if (sm.E != m.E || sm.ng != m.ng) return fail(SEM_ERR_INVALID_ARG, "smoother was created for another mesh");
+    if (sm.mg_context && !m.hsmg)
+        return fail(SEM_ERR_INVALID_ARG, "a smoother trained in the multigrid context needs a mesh created with "
+                                         "SEM_PREP_HSMG");
+    return SEM_OK;
+}
 
 // queue the flexible-CG direction update after r changed (initial, restart)
 static sem_status fcg_direction(const Mesh &m, const Smoother &sm, const CgVecs<double> &v, double *z, CgState *st,
@@ -609,6 +615,11 @@ sem_status sem_smoother_create(const sem_mesh *mesh, const sem_smoother_desc *de
         if (desc->eps > 0) sm.eps = desc->eps;
         if (desc->stall_window > 0) sm.stall_window = desc->stall_window;
         sm.stall_rate = desc->stall_rate;
+        sm.mg_context = desc->mg_context != 0;
+    }
+    if (sm.mg_context && !m.hsmg) {
+        delete h;
+        return fail(SEM_ERR_INVALID_ARG, "mg_context needs a mesh created with SEM_PREP_HSMG");
     }
     struct Alloc { void **p; size_t bytes; } allocs[] = {
         {(void **)&sm.W, kParams * 4}, {(void **)&sm.m, kParams * 4}, {(void **)&sm.v, kParams * 4},
@@ -616,14 +627,16 @@ sem_status sem_smoother_create(const sem_mesh *mesh, const sem_smoother_desc *de
         {(void **)&sm.dW_elem, (size_t)m.E * kParams * 4}, {(void **)&sm.c_local, (size_t)m.nl * 4},
         {(void **)&sm.buf, (size_t)(6 * m.ng + m.nl) * 8},
         {(void **)&sm.part, (size_t)part_capacity(m.lat, m.E) * 2 * 8}, {(void **)&sm.stage, (size_t)kStage * 2 * 8},
-        {(void **)&sm.scal, 64}};
+        {(void **)&sm.scal, 64}, {(void **)&sm.mg_ws, sm.mg_context ? hsmg_bufs_bytes(m) : 0}};
     for (auto &a : allocs) {
+        if (a.bytes == 0) continue;
         if (hipMalloc(a.p, a.bytes) != hipSuccess) {
             sem_smoother_destroy(h);
             return fail(SEM_ERR_OUT_OF_MEMORY, "hipMalloc for the smoother");
         }
         sm.device_bytes += a.bytes;
     }
+    if (sm.mg_context) sm.mg = hsmg_bufs_carve(m, sm.mg_ws);
     std::vector<float> w(kParams);
     he_init(w, seed);
     sem_status st = sem_smoother_set_weights(h, w.data(), kParams);
@@ -639,7 +652,7 @@ sem_status sem_smoother_destroy(sem_smoother *sm)
 {
     if (!sm) return SEM_OK;
     Smoother &s = sm->s;
-    void *ps[] = {s.W, s.m, s.v, s.grad, s.W2b, s.dW_elem, s.c_local, s.buf, s.part, s.stage, s.scal};
+    void *ps[] = {s.W, s.m, s.v, s.grad, s.W2b, s.dW_elem, s.c_local, s.buf, s.part, s.stage, s.scal, s.mg_ws};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete sm;
@@ -716,6 +729,30 @@ sem_status sem_smoother_apply(const sem_smoother *sm, const sem_mesh *mesh, doub
     else
         SEM_HIP_TRY(nn_infer<double>(s, m, t.r, t.dinv, s.c_local, st, nullptr));
     SEM_HIP_TRY(nn_assemble_z<double>(m, t.r, t.dinv, s.c_local, t.z, st, nullptr));
+    SEM_HIP_TRY(cg_scatter<double>(m, t.z, z_local, st));
+    return SEM_OK;
+}
+
+sem_status sem_smoother_mg_apply(const sem_smoother *sm, const sem_mesh *mesh, double h1, double h2, int fp32,
+                                 const double *r_local, double *z_local, void *workspace, size_t ws_bytes,
+                                 void *stream)
+{
+    if (!sm || !mesh || !r_local || !z_local || !workspace) return fail(SEM_ERR_INVALID_ARG, "null argument");
+    const Smoother &s = sm->s;
+    const Mesh &m = mesh->m;
+    SEM_TRY(check_pair(s, m));
+    if (!m.hsmg) return fail(SEM_ERR_INVALID_ARG, "the learned multigrid needs a mesh created with SEM_PREP_HSMG");
+    if (!(h1 > 0.0) || !(h2 >= 0.0) || !std::isfinite(h1) || !std::isfinite(h2))
+        return fail(SEM_ERR_INVALID_ARG, "the learned multigrid needs h1 > 0 and h2 >= 0");
+    if (ws_bytes < hsmg_bufs_bytes(m))
+        return fail(SEM_ERR_INVALID_ARG, "workspace too small: need " + std::to_string(hsmg_bufs_bytes(m)) + " bytes");
+    hipStream_t st = (hipStream_t)stream;
+    TrainBufs t = train_bufs(s);
+    const HsmgBufs hb = hsmg_bufs_carve(m, (char *)workspace);
+    SEM_HIP_TRY(make_dinv(s, m, h1, h2, t, st, true));
+    SEM_TRY(gather_local(m, r_local, t.r, st));
+    const FineHook hook{&s, t.dinv, s.c_local, fp32 ? 1 : 0};
+    SEM_HIP_TRY(hsmg_apply(m, h1, h2, t.r, t.z, hb, 3, kWeightAvg, st, &hook));
     SEM_HIP_TRY(cg_scatter<double>(m, t.z, z_local, st));
     return SEM_OK;
 }

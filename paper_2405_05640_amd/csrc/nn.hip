@@ -372,11 +372,12 @@ __global__ void pack_w2_kernel(const float *__restrict__ W, unsigned short *__re
     W2b[(tap * 16 + o) * 16 + c] = f2bf(W[kW1 + w]);
 }
 
-// z = dinv r + sum_copies c / mult (0 on Dirichlet nodes), assembled
+// z = dinv r + sum_copies c / mult (+ zp[g] if zp: the learned multigrid's
+// coarser-level part), 0 on Dirichlet nodes, assembled
 template <typename TR>
 __global__ void __launch_bounds__(kBS)
 assemble_z_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const float *__restrict__ c, Lattice L,
-                  TR *__restrict__ z, const int32_t *__restrict__ use_c)
+                  TR *__restrict__ z, const int32_t *__restrict__ use_c, const TR *__restrict__ zp)
 {
     const bool with_c = !use_c || *use_c;
     SEM_FOR_EACH_NODE(L, gi, gj, gk, g)
@@ -392,6 +393,7 @@ assemble_z_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const
             for (int q = 0; q < n; ++q) s += c[loc[q]];
             zz += (double)s / n;
         }
+        if (zp) zz += (double)zp[g];
         z[g] = (TR)zz;
     }
 }
@@ -411,10 +413,10 @@ hipError_t nn_infer(const Smoother &sm, const Mesh &m, const TR *rg, const TR *d
 
 template <typename TR>
 hipError_t nn_assemble_z(const Mesh &m, const TR *rg, const TR *dinvg, const float *c_local, TR *z, hipStream_t s,
-                         const int32_t *use_c)
+                         const int32_t *use_c, const TR *zp)
 {
     hipLaunchKernelGGL((nn::assemble_z_kernel<TR>), dim3(node_grid(m.lat)), dim3(kBS), 0, s, rg, dinvg, c_local,
-                       m.lat, z, use_c);
+                       m.lat, z, use_c, zp);
     return hipGetLastError();
 }
 
@@ -457,6 +459,6 @@ hipError_t nn_infer32(const Smoother &sm, const Mesh &m, const double *rg, const
 template hipError_t nn_infer<double>(const Smoother &, const Mesh &, const double *, const double *, float *,
                                      hipStream_t, const int32_t *);
 template hipError_t nn_assemble_z<double>(const Mesh &, const double *, const double *, const float *, double *,
-                                          hipStream_t, const int32_t *);
+                                          hipStream_t, const int32_t *, const double *);
 
 }  // namespace sem

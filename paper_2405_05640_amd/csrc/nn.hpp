@@ -2,6 +2,7 @@
 #pragma once
 
 #include "cg.hpp"
+#include "hsmg.hpp"
 #include "sem_internal.hpp"
 
 namespace sem {
@@ -32,8 +33,18 @@ struct Smoother {
     // h1, h2 (every call that rebuilds it updates the key)
     mutable uint64_t dinv_serial = 0;
     mutable double dinv_h1 = -1.0, dinv_h2 = -1.0;
+    // training in the context of the learned multigrid: the loss adds the
+    // coarser levels' part of the cycle to the smoother output (work
+    // buffers of one cycle in mg_ws)
+    int mg_context = 0;
+    char *mg_ws = nullptr;
+    HsmgBufs mg{};
     size_t device_bytes = 0;
 };
+
+// the smoother was created for a mesh of this size and order N = 7 (and,
+// if trained in the multigrid context, the mesh has SEM_PREP_HSMG)
+sem_status check_pair(const Smoother &sm, const Mesh &m);
 
 // flexible CG with the learned smoother (learned.hip)
 // v: x, r, p, dinv (assembled), w (local); z, q: assembled scratch; the
@@ -54,7 +65,7 @@ hipError_t nn_infer(const Smoother &sm, const Mesh &m, const TR *rg, const TR *d
                     const int32_t *skip);
 template <typename TR>
 hipError_t nn_assemble_z(const Mesh &m, const TR *rg, const TR *dinvg, const float *c_local, TR *z, hipStream_t s,
-                         const int32_t *use_c);
+                         const int32_t *use_c, const TR *zp = nullptr);
 hipError_t nn_grad(const Smoother &sm, const Mesh &m, const double *rg, const double *dinvg, const double *gz,
                    float *dW_elem, double scale, float *grad, hipStream_t s);
 hipError_t nn_adam(Smoother &sm, const float *grad, hipStream_t s);

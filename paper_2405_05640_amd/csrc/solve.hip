@@ -106,7 +106,7 @@ Workspace carve(const Mesh &m, const sem_solve_opts &o, int hist_len, char *base
         ws.v32.part_b = ws.v64.part_b;
         ws.v32.stage = ws.v64.stage;
     }
-    if (form == SEM_FORM_GMRES_HSMG) {
+    if (form == SEM_FORM_GMRES_HSMG || form == SEM_FORM_GMRES_LEARNED_MG) {
         const int mres = gmres_restart(o);
         char *p = take(gmres_bufs_bytes(m, mres));
         if (base) ws.gm = gmres_bufs_carve(m, mres, p);
@@ -178,6 +178,15 @@ sem_status check_opts(const Mesh &m, const sem_solve_opts *o)
     case SEM_FORM_FCG_LEARNED:
         if (!o->smoother) return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_FCG_LEARNED needs opts.smoother");
         if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "the learned smoother needs order N = 7");
+        return SEM_OK;
+    case SEM_FORM_GMRES_LEARNED_MG:
+        if (!o->smoother) return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_GMRES_LEARNED_MG needs opts.smoother");
+        if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "the learned smoother needs order N = 7");
+        if (!m.hsmg) return fail(SEM_ERR_INVALID_ARG, "this form needs a mesh created with SEM_PREP_HSMG");
+        if (!(o->h1 > 0.0)) return fail(SEM_ERR_INVALID_ARG, "the multigrid forms need h1 > 0");
+        if (o->h2 < 0.0) return fail(SEM_ERR_INVALID_ARG, "h2 must be >= 0");
+        if (o->restart < 0 || o->restart > kGmresMaxRestart)
+            return fail(SEM_ERR_INVALID_ARG, "restart must be in 0.." + std::to_string(kGmresMaxRestart));
         return SEM_OK;
     default:
         return fail(SEM_ERR_UNSUPPORTED, "solver form " + std::to_string(o->form) + " not available");
@@ -540,6 +549,12 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
         SEM_TRY(solve_reliable(m, *opts, ws, hist_len, s, check_every, rep, h));
     else if (opts->form == SEM_FORM_GMRES_HSMG)
         SEM_TRY(solve_gmres_hsmg(m, *opts, ws.v64, ws.b64, ws.st64, ws.gm, s, rep, h));
+    else if (opts->form == SEM_FORM_GMRES_LEARNED_MG) {
+        const Smoother &sm = opts->smoother->s;
+        SEM_TRY(check_pair(sm, m));
+        const FineHook hook{&sm, ws.v64.dinv, sm.c_local, 0};
+        SEM_TRY(solve_gmres_hsmg(m, *opts, ws.v64, ws.b64, ws.st64, ws.gm, s, rep, h, &hook));
+    }
     else if (opts->form == SEM_FORM_PCG_BLOCK_JACOBI || opts->form == SEM_FORM_PCG_HSMG)
         SEM_TRY(solve_pcg_precond(m, *opts, ws.v64, ws.b64, ws.z, ws.st64, ws.hb,
                                   opts->form == SEM_FORM_PCG_HSMG ? 3 : 1, ws.hist, hist_len, check_every, s, rep, h));

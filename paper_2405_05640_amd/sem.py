@@ -24,7 +24,7 @@ SEM_PREP_F32, SEM_PREP_BF16, SEM_PREP_HSMG = 1, 2, 4
 FIELD_GLO_NUM, FIELD_MULT, FIELD_MASK, FIELD_G, FIELD_B, FIELD_XYZ, FIELD_GLL, FIELD_DERIV = range(8)
 (FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED, FORM_FCG_INNER_FP32, FORM_FCG_INNER_BF16,
  FORM_RELIABLE_FP32, FORM_RELIABLE_BF16, FORM_PCG_1RED, FORM_GMRES_HSMG, FORM_PCG_BLOCK_JACOBI,
- FORM_PCG_HSMG) = range(12)
+ FORM_PCG_HSMG, FORM_GMRES_LEARNED_MG) = range(13)
 PRECOND_HSMG, PRECOND_SCHWARZ, PRECOND_BLOCK_JACOBI, PRECOND_HSMG_SYM = 0, 1, 2, 3
 SMOOTHER_PARAMS = 8208
 NOALLOC_SCRATCH_BYTES = 32 << 20    # SEM_NOALLOC_SCRATCH_BYTES
@@ -36,7 +36,7 @@ EXPORTED_SYMBOLS = [
     "sem_smoother_set_weights", "sem_smoother_get_weights", "sem_smoother_apply", "sem_smoother_loss_grad",
     "sem_smoother_train_step", "sem_pcg_snapshots", "sem_pcg_solve_batched", "sem_solve_workspace_bytes_batched",
     "sem_smoother_get_state", "sem_smoother_set_state", "sem_pcg_solve_noalloc", "sem_precond_workspace_bytes",
-    "sem_precond_apply",
+    "sem_precond_apply", "sem_smoother_mg_apply",
 ]
 
 
@@ -72,7 +72,7 @@ class SolveOpts(ctypes.Structure):
 class SmootherDesc(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("stall_window", ctypes.c_int32),
-                ("stall_rate", ctypes.c_double)]
+                ("stall_rate", ctypes.c_double), ("mg_context", ctypes.c_int32)]
 
 
 class SolveReport(ctypes.Structure):
@@ -123,6 +123,7 @@ def lib():
             "sem_smoother_get_state": [vp, vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(i32)],
             "sem_smoother_set_state": [vp, vp, vp, vp, ctypes.c_size_t, i32],
             "sem_smoother_apply": [vp, vp, dbl, dbl, ctypes.c_int, vp, vp, vp],
+            "sem_smoother_mg_apply": [vp, vp, dbl, dbl, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp],
             "sem_smoother_loss_grad": [vp, vp, dbl, dbl, vp, ctypes.POINTER(dbl), vp, vp],
             "sem_smoother_train_step": [vp, vp, dbl, dbl, vp, vp, vp],
             "sem_pcg_snapshots": [vp, ctypes.POINTER(SolveOpts), vp, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t,
@@ -355,8 +356,9 @@ class Mesh:
 class Smoother:
     """Learned per-element smoother (``sem_smoother``) bound to one N = 7 mesh."""
 
-    def __init__(self, mesh, seed=0, lr=1e-3, stall_window=25, stall_rate=0.0, beta1=0.9, beta2=0.999, eps=1e-8):
-        d = SmootherDesc(seed, lr, beta1, beta2, eps, stall_window, stall_rate)
+    def __init__(self, mesh, seed=0, lr=1e-3, stall_window=25, stall_rate=0.0, beta1=0.9, beta2=0.999, eps=1e-8,
+                 mg_context=False):
+        d = SmootherDesc(seed, lr, beta1, beta2, eps, stall_window, stall_rate, 1 if mg_context else 0)
         h = ctypes.c_void_p()
         _check(lib().sem_smoother_create(mesh._h, ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -404,6 +406,22 @@ class Smoother:
         m = self.mesh
         _check(lib().sem_smoother_apply(self._h, m._h, float(h1), float(h2), 1 if fp32 else 0,
                                         _want(r, "f64", m.n_local, "r"), _want(z, "f64", m.n_local, "z"), _stream()))
+        return z
+
+    def mg_apply(self, r, z, h1=1.0, h2=0.0, fp32=False, workspace=None):
+        """z = the learned multigrid applied to r (sem_smoother_mg_apply)."""
+        import torch
+        m = self.mesh
+        n = ctypes.c_size_t()
+        _check(lib().sem_precond_workspace_bytes(m._h, ctypes.byref(n)))
+        if workspace is None:
+            workspace = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        if workspace.numel() * workspace.element_size() < n.value:
+            raise ValueError("workspace too small")
+        _check(lib().sem_smoother_mg_apply(self._h, m._h, float(h1), float(h2), 1 if fp32 else 0,
+                                           _want(r, "f64", m.n_local, "r"), _want(z, "f64", m.n_local, "z"),
+                                           ctypes.c_void_p(workspace.data_ptr()),
+                                           workspace.numel() * workspace.element_size(), _stream()))
         return z
 
     def loss_grad(self, e, h1=1.0, h2=0.0, mesh=None):

@@ -382,3 +382,121 @@ def test_smoother_checkpoint_resume(mp):
     b.train_step(pairs[2][0])
     for x, y in zip(a.get_state(), b.get_state()):
         assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
+# ---------------------------------------------------------------- learned multigrid
+
+
+@pytest.fixture(scope="module")
+def mpg():
+    from oracle import hsmg
+    spec = wl.random_deformed_box(3, 2, 3, 7, seed=4, amp=0.15, periodic=(1, 0, 0),
+                                  dirichlet=wl.DIRICHLET_Y_WALLS | 0x30)
+    om, gm = pair(spec, prepare=sem.SEM_PREP_HSMG)
+    return om, gm, hsmg.HSMG(om)
+
+
+def test_learned_multigrid_apply_matches_oracle(mpg):
+    # the learned smoother on the fine level plus the hybrid Schwarz
+    # multigrid's middle and coarse levels: the network part within the
+    # element-wise rounding bounds of the plain smoother, the coarser levels
+    # to the conditioning of their factorisations (1e-10 of their size)
+    import torch
+    om, gm, pc = mpg
+    net, flat = _net_weights(1)
+    sm = sem.Smoother(gm)
+    sm.set_weights(flat)
+    rng = np.random.default_rng(31)
+    r = om.rhs(rng.standard_normal(om.shape))
+    dinv = om.jacobi_inv()
+    cp = pc.coarse_part(r)
+    z_ref = cnn.smoother(om, net, r, dinv) + cp
+    ref_fine = pc.apply(r, fine=lambda q: cnn.smoother(om, net, q, dinv))
+    assert np.allclose(z_ref, ref_fine, rtol=0, atol=1e-14 * np.max(np.abs(z_ref)))
+    z = torch.empty(gm.shape, dtype=torch.float64, device="cuda")
+    floor = 1e-10 * np.max(np.abs(cp)) + 1e-14 * np.abs(z_ref)
+    for fp32, rel in ((True, 1024 * 2.0 ** -24), (False, 2.0 ** -8 + 1024 * 2.0 ** -24)):
+        sm.mg_apply(dev(r), z, fp32=fp32)
+        zh = host(z)
+        bound = _abs_net_bound(om, net, r, dinv, rel) + floor
+        err = np.abs(zh - z_ref)
+        print("learned multigrid (%s network): max error / bound = %.3g" %
+              ("FP32" if fp32 else "BF16", np.max(err / np.maximum(bound, 1e-300))))
+        assert np.all(err <= bound)
+        assert np.array_equal(zh, om.gather_global(zh)[om.glo])
+        assert np.all(zh[om.mask == 1] == 0)
+    # zero network: Jacobi on the fine level
+    zero = flat.copy()
+    zero[864 + 6912:] = 0
+    sm.set_weights(zero)
+    sm.mg_apply(dev(r), z)
+    assert np.allclose(host(z), dinv * r + cp, rtol=0, atol=1e-10 * np.max(np.abs(dinv * r + cp)))
+
+
+@pytest.mark.parametrize("which", ["zero", "random"])
+def test_gmres_learned_multigrid_matches_oracle(mpg, which):
+    import torch
+    from oracle import hsmg
+    om, gm, pc = mpg
+    net, flat = _net_weights(5, scale3=0.0 if which == "zero" else 0.05)
+    sm = sem.Smoother(gm)
+    sm.set_weights(flat)
+    dinv = om.jacobi_inv()
+    rng = np.random.default_rng(32)
+    b = om.rhs(rng.standard_normal(om.shape))
+    xo, info = hsmg.fgmres(om, b, lambda q: pc.apply(q, fine=lambda t: cnn.smoother(om, net, t, dinv)),
+                           tol=1e-10, restart=30)
+    x = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
+    rep = gm.pcg_solve(dev(b), x, form=sem.FORM_GMRES_LEARNED_MG, smoother=sm, restart=30)
+    true_rel = _true_rel(om, b, host(x))
+    _, pinfo = om.pcg(b)
+    print("%s network: learned-multigrid GMRES %d iterations (oracle %d), Jacobi-PCG %d, true rel res %.2e" %
+          (which, rep.iterations, info["iterations"], pinfo["iterations"], true_rel))
+    assert true_rel <= 1.05e-10
+    assert abs(rep.true_rel_res - true_rel) <= 1e-3 * true_rel + 2e-13
+    # zero network: the same linear preconditioner on both sides; a random
+    # one runs its middle layer in BF16 on the GPU
+    tol = 1 if which == "zero" else max(2, info["iterations"] // 10)
+    assert abs(rep.iterations - info["iterations"]) <= tol
+    assert rep.iterations < pinfo["iterations"]
+
+
+@pytest.mark.parametrize("h2", [0.0, 0.1])
+def test_mg_context_loss_gradient(mpg, h2):
+    # training in the multigrid context: the loss of M(r) + C(r), C the
+    # coarser levels' part, and its FP32 gradient against the oracle
+    om, gm, pc = mpg
+    from tests import brute
+    net, flat = _net_weights(3, scale3=0.1)
+    sm = sem.Smoother(gm, mg_context=True)
+    sm.set_weights(flat)
+    rng = np.random.default_rng(33)
+    e = brute.continuous_random(om, rng)
+    r = om.apply_S(e, 1.0, h2)
+    L_ref, g_ref = cnn.loss_and_grad(om, net, r, e, om.jacobi_inv(1.0, h2), 1.0, h2, extra=pc.coarse_part(r, 1.0, h2))
+    L, g = sm.loss_grad(dev(e), 1.0, h2)
+    gr = np.concatenate([x.ravel() for x in g_ref])
+    print("multigrid-context loss %.6f (oracle %.6f), gradient norm-wise relative error %.3g" %
+          (L, L_ref, np.linalg.norm(g - gr) / np.linalg.norm(gr)))
+    assert abs(L - L_ref) <= 1e-5 * abs(L_ref)
+    assert np.linalg.norm(g - gr) <= 1e-5 * np.linalg.norm(gr)
+
+
+def test_learned_multigrid_argument_checks(mp, mpg):
+    import torch
+    om, gm = mp
+    _, gmh, _ = mpg
+    with pytest.raises(sem.SemError):
+        sem.Smoother(gm, mg_context=True)            # mesh without SEM_PREP_HSMG
+    sm = sem.Smoother(gm)
+    b = torch.ones(gm.shape, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    with pytest.raises(sem.SemError):
+        gm.pcg_solve(b, x, form=sem.FORM_GMRES_LEARNED_MG, smoother=sm)
+    with pytest.raises(sem.SemError):
+        gmh.pcg_solve(b, x, form=sem.FORM_GMRES_LEARNED_MG)    # no smoother
+    smh = sem.Smoother(gmh)
+    with pytest.raises(sem.SemError):
+        smh.mg_apply(b, x, h1=0.0)
+    with pytest.raises(sem.SemError):
+        sm.mg_apply(b, x)                             # mesh without SEM_PREP_HSMG
