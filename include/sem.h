@@ -208,12 +208,17 @@ typedef enum {
                                     the same preconditioner family as SEM_FORM_GMRES_HSMG at CG's
                                     cost per iteration (no growing Krylov basis).  Needs
                                     SEM_PREP_HSMG and h1 > 0. */
-    SEM_FORM_GMRES_LEARNED_MG = 12 /* flexible GMRES(m) as SEM_FORM_GMRES_HSMG with the learned
+    SEM_FORM_GMRES_LEARNED_MG = 12, /* flexible GMRES(m) as SEM_FORM_GMRES_HSMG with the learned
                                     multigrid: the learned smoother (opts.smoother, BF16
                                     inference) in place of the fine Schwarz level, the paper's
                                     middle and coarse levels kept (not in the paper).  A zero
                                     network makes the fine level Jacobi.  Needs SEM_PREP_HSMG,
                                     N = 7 and h1 > 0. */
+    SEM_FORM_FCG_LEARNED_MG = 13 /* SEM_FORM_FCG_LEARNED with the learned multigrid of
+                                    SEM_FORM_GMRES_LEARNED_MG as its preconditioner (flexible CG,
+                                    Polak-Ribiere, Jacobi-PCG fallback and stall test as there);
+                                    CG's cost per iteration.  Needs SEM_PREP_HSMG, N = 7 and
+                                    h1 > 0. */
 } sem_form;
 
 /* Hybrid Schwarz multigrid (SEM_FORM_GMRES_HSMG), for an assembled fine

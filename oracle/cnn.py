@@ -203,11 +203,18 @@ def train_step(mesh, net, opt, e, dinv, h1=1.0, h2=0.0):
 
 
 def fcg(mesh, net, b, h1=1.0, h2=0.0, tol=1e-10, max_iter=20000, window=25, rho=None,
-        force_fallback_at=None):
+        force_fallback_at=None, coarse=None):
     """Flexible CG with the learned smoother; Jacobi-PCG fallback.
     Returns (x, info).  `rho`: per-iteration residual reduction rate of plain
-    Jacobi-PCG used by the stall test (None disables it)."""
+    Jacobi-PCG used by the stall test (None disables it).  coarse: a callable
+    r -> C(r) added to the smoother output (the learned multigrid's middle
+    and coarse levels); the fallback is plain Jacobi-PCG either way."""
     dinv = mesh.jacobi_inv(h1, h2)
+
+    def learned(q):
+        z = smoother(mesh, net, q, dinv)
+        return z if coarse is None else z + coarse(q)
+
     x = np.zeros(mesh.shape)
     bn = np.sqrt(mesh.dot(b, b))
     info = {"iterations": 0, "fallback_at": -1, "status": 0}
@@ -215,7 +222,7 @@ def fcg(mesh, net, b, h1=1.0, h2=0.0, tol=1e-10, max_iter=20000, window=25, rho=
         return x, info
     r = b.copy()
     use_net = True
-    z = smoother(mesh, net, r, dinv)
+    z = learned(r)
     rz = mesh.dot(r, z)
     if not (rz > 0) or not np.isfinite(rz):
         use_net = False
@@ -246,7 +253,7 @@ def fcg(mesh, net, b, h1=1.0, h2=0.0, tol=1e-10, max_iter=20000, window=25, rho=
         if use_net and force_fallback_at is not None and it == force_fallback_at:
             stall = True
         if use_net and not stall:
-            zn = smoother(mesh, net, r, dinv)
+            zn = learned(r)
             rzn = mesh.dot(r, zn)
             if not (rzn > 0) or not np.isfinite(rzn):
                 stall = True

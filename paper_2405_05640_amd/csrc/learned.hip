@@ -174,11 +174,12 @@ fcg_check_kernel(CgState *st, const double *__restrict__ part, int nb, double *h
     }
 }
 
-// z = dinv r + (learned ? Q^T(c / mult) : 0); partials (r, z), (z, q)
+// z = dinv r + (learned ? Q^T(c / mult) + zp : 0), zp (optional) the
+// learned multigrid's coarser-level part; partials (r, z), (z, q)
 __global__ void __launch_bounds__(kBS)
 fcg_z_kernel(const CgState *__restrict__ st, const double *__restrict__ r, const double *__restrict__ dinv,
              const float *__restrict__ c, const double *__restrict__ q, double *__restrict__ z, Lattice L,
-             double *__restrict__ part)
+             double *__restrict__ part, const double *__restrict__ zp)
 {
     if (st->done) return;
     const bool with_c = st->learned != 0;
@@ -196,6 +197,7 @@ fcg_z_kernel(const CgState *__restrict__ st, const double *__restrict__ r, const
                 float s = 0.f;
                 for (int k = 0; k < n; ++k) s += c[loc[k]];
                 zz += (double)s / n;
+                if (zp) zz += zp[g];
             }
         }
         z[g] = zz;
@@ -412,15 +414,25 @@ sem_status check_pair(const Smoother &sm, const Mesh &m)
     return SEM_OK;
 }
 
+// the learned multigrid's coarser-level part of r into mg->zp (queued; mg
+// null: plain learned smoother)
+static sem_status fcg_coarse(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const HsmgBufs *mg,
+                             hipStream_t s)
+{
+    if (mg) SEM_HIP_TRY(hsmg_coarse_part(m, o.h1, o.h2, v.r, *mg, kWeightAvg, s));
+    return SEM_OK;
+}
+
 // queue the flexible-CG direction update after r changed (initial, restart)
-static sem_status fcg_direction(const Mesh &m, const Smoother &sm, const CgVecs<double> &v, double *z, CgState *st,
-                                int first, hipStream_t s)
+static sem_status fcg_direction(const Mesh &m, const sem_solve_opts &o, const Smoother &sm, const CgVecs<double> &v,
+                                double *z, CgState *st, int first, const HsmgBufs *mg, hipStream_t s)
 {
     const int nb = cg_blocks(m.ng);
     const int nbn = node_blocks(m);
+    SEM_TRY(fcg_coarse(m, o, v, mg, s));
     SEM_HIP_TRY(nn_infer<double>(sm, m, v.r, v.dinv, sm.c_local, s, &st->nn_skip));
     hipLaunchKernelGGL(lk::fcg_z_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.r, v.dinv, sm.c_local,
-                       (const double *)nullptr, z, m.lat, v.part_b);
+                       (const double *)nullptr, z, m.lat, v.part_b, mg ? (const double *)mg->zp : nullptr);
     SEM_HIP_TRY(cg_reduce(v.part_b, nbn, 2, v.stage, s));
     hipLaunchKernelGGL(lk::fcg_beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.stage, kStage, first);
     hipLaunchKernelGGL(lk::fcg_p_kernel, dim3(nb), dim3(kBS), 0, s, st, v.p, z, v.r, v.dinv, m.ng, v.part_b);
@@ -431,7 +443,7 @@ static sem_status fcg_direction(const Mesh &m, const Smoother &sm, const CgVecs<
 
 sem_status solve_fcg(const Mesh &m, const Smoother &sm, const sem_solve_opts &o, const CgVecs<double> &v,
                      const double *b64, double *z, double *q, CgState *st, double *hist, int hist_len,
-                     int check_every, hipStream_t s, sem_solve_report *rep, CgState &h)
+                     int check_every, hipStream_t s, sem_solve_report *rep, CgState &h, const HsmgBufs *mg)
 {
     SEM_TRY(check_pair(sm, m));
     const int nb = cg_blocks(m.ng);
@@ -444,7 +456,7 @@ sem_status solve_fcg(const Mesh &m, const Smoother &sm, const sem_solve_opts &o,
     SEM_HIP_TRY(hipMemcpyAsync(st, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
     SEM_HIP_TRY(cg_init<double>(m, v, b64, st, o.rel_tol, hist, s));
     hipLaunchKernelGGL(lk::zero_kernel, dim3(nb), dim3(kBS), 0, s, v.p, m.ng);
-    SEM_TRY(fcg_direction(m, sm, v, z, st, 1, s));
+    SEM_TRY(fcg_direction(m, o, sm, v, z, st, 1, mg, s));
     int restarts = 0;
     for (;;) {
         for (;;) {
@@ -458,9 +470,10 @@ sem_status solve_fcg(const Mesh &m, const Smoother &sm, const sem_solve_opts &o,
                 SEM_HIP_TRY(cg_reduce(v.part_b, nbn, 1, v.stage, s));
                 hipLaunchKernelGGL(lk::fcg_check_kernel, dim3(1), dim3(kBS), 0, s, st, v.stage, kStage, hist,
                                    sm.stall_window, sm.stall_rate);
+                SEM_TRY(fcg_coarse(m, o, v, mg, s));
                 SEM_HIP_TRY(nn_infer<double>(sm, m, v.r, v.dinv, sm.c_local, s, &st->nn_skip));
                 hipLaunchKernelGGL(lk::fcg_z_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.r, v.dinv, sm.c_local,
-                                   (const double *)q, z, m.lat, v.part_b);
+                                   (const double *)q, z, m.lat, v.part_b, mg ? (const double *)mg->zp : nullptr);
                 SEM_HIP_TRY(cg_reduce(v.part_b, nbn, 2, v.stage, s));
                 hipLaunchKernelGGL(lk::fcg_beta_kernel, dim3(1), dim3(kBS), 0, s, st, v.stage, kStage, 0);
                 hipLaunchKernelGGL(lk::fcg_p_kernel, dim3(nb), dim3(kBS), 0, s, st, v.p, z, v.r, v.dinv, m.ng,
@@ -482,7 +495,7 @@ sem_status solve_fcg(const Mesh &m, const Smoother &sm, const sem_solve_opts &o,
         patch.rr = h.true_rr;
         patch.nn_skip = h.learned ? 0 : 1;
         SEM_HIP_TRY(hipMemcpyAsync(st, &patch, sizeof(CgState), hipMemcpyHostToDevice, s));
-        SEM_TRY(fcg_direction(m, sm, v, z, st, 1, s));
+        SEM_TRY(fcg_direction(m, o, sm, v, z, st, 1, mg, s));
     }
     if (h.done != 1 && h.bb > 0.0) {
         SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.x, v.w, nullptr, s));

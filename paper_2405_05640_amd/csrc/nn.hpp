@@ -48,10 +48,13 @@ sem_status check_pair(const Smoother &sm, const Mesh &m);
 
 // flexible CG with the learned smoother (learned.hip)
 // v: x, r, p, dinv (assembled), w (local); z, q: assembled scratch; the
-// smoother's c_local buffer holds the element outputs.
+// smoother's c_local buffer holds the element outputs.  mg (not null): the
+// learned multigrid, whose coarser-level part (averaged weighting) is added
+// to the smoother output while the network is in use.
 sem_status solve_fcg(const Mesh &m, const Smoother &sm, const sem_solve_opts &o, const CgVecs<double> &v,
                      const double *b64, double *z, double *q, CgState *st, double *hist, int hist_len,
-                     int check_every, hipStream_t s, sem_solve_report *rep, CgState &h);
+                     int check_every, hipStream_t s, sem_solve_report *rep, CgState &h,
+                     const HsmgBufs *mg = nullptr);
 
 // FP64 flexible CG preconditioned by inner_iters steps of FP32-vector
 // Jacobi-PCG with the FP32 or BF16 operator (learned.hip)

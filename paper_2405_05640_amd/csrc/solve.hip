@@ -59,7 +59,8 @@ bool uses_f32(int form)
 }
 bool uses_fcg(int form)
 {
-    return form == SEM_FORM_FCG_LEARNED || form == SEM_FORM_FCG_INNER_FP32 || form == SEM_FORM_FCG_INNER_BF16;
+    return form == SEM_FORM_FCG_LEARNED || form == SEM_FORM_FCG_INNER_FP32 || form == SEM_FORM_FCG_INNER_BF16 ||
+           form == SEM_FORM_FCG_LEARNED_MG;
 }
 // forms that need the two extra assembled FP64 vectors z and q
 bool uses_zq(int form)
@@ -111,7 +112,7 @@ Workspace carve(const Mesh &m, const sem_solve_opts &o, int hist_len, char *base
         char *p = take(gmres_bufs_bytes(m, mres));
         if (base) ws.gm = gmres_bufs_carve(m, mres, p);
     }
-    if (form == SEM_FORM_PCG_BLOCK_JACOBI || form == SEM_FORM_PCG_HSMG) {
+    if (form == SEM_FORM_PCG_BLOCK_JACOBI || form == SEM_FORM_PCG_HSMG || form == SEM_FORM_FCG_LEARNED_MG) {
         char *p = take(hsmg_bufs_bytes(m));
         if (base) ws.hb = hsmg_bufs_carve(m, p);
     }
@@ -180,7 +181,8 @@ sem_status check_opts(const Mesh &m, const sem_solve_opts *o)
         if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "the learned smoother needs order N = 7");
         return SEM_OK;
     case SEM_FORM_GMRES_LEARNED_MG:
-        if (!o->smoother) return fail(SEM_ERR_INVALID_ARG, "SEM_FORM_GMRES_LEARNED_MG needs opts.smoother");
+    case SEM_FORM_FCG_LEARNED_MG:
+        if (!o->smoother) return fail(SEM_ERR_INVALID_ARG, "the learned multigrid forms need opts.smoother");
         if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "the learned smoother needs order N = 7");
         if (!m.hsmg) return fail(SEM_ERR_INVALID_ARG, "this form needs a mesh created with SEM_PREP_HSMG");
         if (!(o->h1 > 0.0)) return fail(SEM_ERR_INVALID_ARG, "the multigrid forms need h1 > 0");
@@ -561,6 +563,9 @@ sem_status sem_pcg_solve(const sem_mesh *mesh, const sem_solve_opts *opts, const
     else if (opts->form == SEM_FORM_FCG_LEARNED)
         SEM_TRY(solve_fcg(m, opts->smoother->s, *opts, ws.v64, ws.b64, ws.z, ws.q, ws.st64, ws.hist, hist_len,
                           check_every, s, rep, h));
+    else if (opts->form == SEM_FORM_FCG_LEARNED_MG)
+        SEM_TRY(solve_fcg(m, opts->smoother->s, *opts, ws.v64, ws.b64, ws.z, ws.q, ws.st64, ws.hist, hist_len,
+                          check_every, s, rep, h, &ws.hb));
     else
         SEM_TRY(solve_pcg64(m, *opts, ws, hist_len, s, check_every, rep, h));
     SEM_HIP_TRY(cg_scatter<double>(m, ws.v64.x, x, s));

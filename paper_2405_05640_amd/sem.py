@@ -24,7 +24,7 @@ SEM_PREP_F32, SEM_PREP_BF16, SEM_PREP_HSMG = 1, 2, 4
 FIELD_GLO_NUM, FIELD_MULT, FIELD_MASK, FIELD_G, FIELD_B, FIELD_XYZ, FIELD_GLL, FIELD_DERIV = range(8)
 (FORM_JACOBI_PCG, FORM_DC_FP32, FORM_DC_BF16, FORM_FCG_LEARNED, FORM_FCG_INNER_FP32, FORM_FCG_INNER_BF16,
  FORM_RELIABLE_FP32, FORM_RELIABLE_BF16, FORM_PCG_1RED, FORM_GMRES_HSMG, FORM_PCG_BLOCK_JACOBI,
- FORM_PCG_HSMG, FORM_GMRES_LEARNED_MG) = range(13)
+ FORM_PCG_HSMG, FORM_GMRES_LEARNED_MG, FORM_FCG_LEARNED_MG) = range(14)
 PRECOND_HSMG, PRECOND_SCHWARZ, PRECOND_BLOCK_JACOBI, PRECOND_HSMG_SYM = 0, 1, 2, 3
 SMOOTHER_PARAMS = 8208
 NOALLOC_SCRATCH_BYTES = 32 << 20    # SEM_NOALLOC_SCRATCH_BYTES

@@ -461,6 +461,37 @@ def test_gmres_learned_multigrid_matches_oracle(mpg, which):
     assert rep.iterations < pinfo["iterations"]
 
 
+@pytest.mark.parametrize("which", ["zero", "random"])
+def test_fcg_learned_multigrid_matches_oracle(mpg, which):
+    # flexible CG (Polak-Ribiere) with the learned multigrid
+    import torch
+    om, gm, pc = mpg
+    net, flat = _net_weights(6, scale3=0.0 if which == "zero" else 0.05)
+    sm = sem.Smoother(gm)
+    sm.set_weights(flat)
+    rng = np.random.default_rng(34)
+    b = om.rhs(rng.standard_normal(om.shape))
+    xo, info = cnn.fcg(om, net, b, coarse=lambda q: pc.coarse_part(q))
+    x = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
+    rep = gm.pcg_solve(dev(b), x, form=sem.FORM_FCG_LEARNED_MG, smoother=sm, check_every=4)
+    true_rel = _true_rel(om, b, host(x))
+    _, pinfo = om.pcg(b)
+    print("%s network: learned-multigrid FCG %d iterations (oracle %d, fallback at %d), Jacobi-PCG %d, "
+          "true rel res %.2e" % (which, rep.iterations, info["iterations"], info["fallback_at"], pinfo["iterations"],
+                                 true_rel))
+    assert true_rel <= 1.05e-10
+    assert rep.fallback_used == (1 if info["fallback_at"] >= 0 else 0)
+    if which == "zero":
+        assert rep.iterations < pinfo["iterations"]
+        assert abs(rep.iterations - info["iterations"]) <= 1
+    elif info["fallback_at"] < 0:
+        assert abs(rep.iterations - info["iterations"]) <= max(2, info["iterations"] // 10)
+    # (an untrained network makes flexible CG with one stored direction
+    # stagnate until (r, z) <= 0 hands over to Jacobi-PCG; the iterations
+    # after that depend on the state at the switch, which the BF16 and FP64
+    # networks reach differently)
+
+
 @pytest.mark.parametrize("h2", [0.0, 0.1])
 def test_mg_context_loss_gradient(mpg, h2):
     # training in the multigrid context: the loss of M(r) + C(r), C the

@@ -309,3 +309,22 @@ def test_learned_multigrid_fgmres_converges():
     print("learned multigrid FGMRES %d iterations, Jacobi-PCG %d" % (info["iterations"], pinfo["iterations"]))
     assert np.sqrt(m.dot(res, res) / m.dot(b, b)) <= 1.05e-10
     assert info["iterations"] < 0.6 * pinfo["iterations"]
+
+
+def test_learned_multigrid_fcg_with_a_linear_spd_cycle_is_pcg():
+    # flexible CG with the learned multigrid: with a zero network and the
+    # symmetric middle level the preconditioner is linear and SPD, and the
+    # Polak-Ribiere coefficient then equals the Fletcher-Reeves one, so the
+    # iterates are those of PCG with the same preconditioner
+    m = _mesh(wl.random_deformed_box(3, 2, 2, 4, seed=23, amp=0.1))
+    pc = hsmg.HSMG(m)
+    dinv = m.jacobi_inv()
+    zero = cnn.Net.init(4, seed=0)
+    rng = np.random.default_rng(24)
+    b = m.rhs(rng.standard_normal(m.shape))
+    x, info = cnn.fcg(m, zero, b, coarse=lambda q: pc.coarse_part(q, sym=True))
+    xp, pinfo = hsmg.pcg(m, b, lambda q: dinv * q + pc.coarse_part(q, sym=True), tol=1e-10)
+    print("FCG %d iterations, PCG %d" % (info["iterations"], pinfo["iterations"]))
+    assert info["fallback_at"] == -1
+    assert abs(info["iterations"] - pinfo["iterations"]) <= 1
+    assert np.max(np.abs(x - xp)) <= 1e-8 * np.max(np.abs(xp))
