@@ -185,7 +185,13 @@ def copy_bandwidth():
 def learned_section(args):
     """Train the smoother on the 16^3 channel with right-hand sides generated
     online (each field's Jacobi-PCG iterate errors are used once, in order),
-    then time flexible CG with it against Jacobi-PCG on held-out fields."""
+    then time flexible CG with it against Jacobi-PCG on held-out fields.
+    Two networks: the plain smoother (loss of M(r) alone), and one trained in
+    the context of the learned multigrid (loss of M(r) + C(r), C the
+    multigrid's middle and coarse levels), on the same errors plus two
+    white-noise errors per field; the second is timed inside the learned
+    multigrid against the same cycle with a zero network (Jacobi on the fine
+    level)."""
     import numpy as np
     import torch
 
@@ -193,7 +199,7 @@ def learned_section(args):
     from paper_2405_05640_amd import workloads as wl
 
     spec = wl.config("c3")
-    mesh = sem.Mesh.from_spec(spec)
+    mesh = sem.Mesh.from_spec(spec, prepare=sem.SEM_PREP_HSMG)
     xyz = mesh.export(sem.FIELD_XYZ)
     vm = wl.kolmogorov_velocity(wl.RHS_SEED["c3"])
 
@@ -213,18 +219,28 @@ def learned_section(args):
         return [e[q * mesh.n_global:(q + 1) * mesh.n_global] for q in range(len(iters))]
 
     glo = torch.from_numpy(mesh.export(sem.FIELD_GLO_NUM).ravel()).cuda()
+    free = torch.ones(mesh.n_global, dtype=torch.float32, device="cuda")
+    free[glo[torch.from_numpy(mesh.export(sem.FIELD_MASK).ravel()).cuda().bool()]] = 0.0
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+
+    def noise():
+        return (torch.randn(mesh.n_global, generator=gen, device="cuda") * free).contiguous()
+
     held_err = snapshot_errors(3000) + snapshot_errors(3001)
     b0 = rhs(2500)
     r0, _ = timed_solves(mesh, b0, 1)
     rate = (1e-10) ** (1.0 / max(r0["iterations"], 1))
     sm = sem.Smoother(mesh, seed=0, lr=1e-3, stall_window=25, stall_rate=rate)
+    smg = sem.Smoother(mesh, seed=0, lr=1e-3, stall_window=25, stall_rate=rate, mg_context=True)
+    zero = sem.Smoother(mesh, seed=0, stall_window=25, stall_rate=rate)   # zero last layer: Jacobi
 
-    def held_loss():
-        return float(np.mean([sm.loss_grad(e[glo].reshape(mesh.shape).contiguous())[0] for e in held_err]))
+    def held_loss(s):
+        return float(np.mean([s.loss_grad(e[glo].reshape(mesh.shape).contiguous())[0] for e in held_err]))
 
-    loss_jacobi = held_loss()   # fresh smoother: zero last layer, exactly Jacobi
+    loss_jacobi, loss_jacobi_mg = held_loss(sm), held_loss(smg)
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
-    losses, t_data, t_train = [], 0.0, 0.0
+    losses, losses_mg, t_data, t_train, t_train_mg = [], [], 0.0, 0.0, 0.0
     for t in range(args.train_fields):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -235,36 +251,57 @@ def learned_section(args):
             sm.train_step(e, loss)
             losses.append(loss.clone())
         torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for e in errs + [noise(), noise()]:
+            smg.train_step(e, loss)
+            losses_mg.append(loss.clone())
+        torch.cuda.synchronize()
         t_data += t1 - t0
-        t_train += time.perf_counter() - t1
+        t_train += t2 - t1
+        t_train_mg += time.perf_counter() - t2
     lv = torch.cat(losses).cpu().numpy() if losses else np.zeros(0)
-    nq = max(1, len(lv) // 4)
-    loss_trained = held_loss()
-    res_j, res_l = [], []
+    lvm = torch.cat(losses_mg).cpu().numpy() if losses_mg else np.zeros(0)
+    nq, nqm = max(1, len(lv) // 4), max(1, len(lvm) // 4)
+    loss_trained, loss_trained_mg = held_loss(sm), held_loss(smg)
+    forms = [("jacobi_pcg", {}), ("fcg_learned", dict(form=sem.FORM_FCG_LEARNED, smoother=sm)),
+             ("fcg_learned_mg_zero_net", dict(form=sem.FORM_FCG_LEARNED_MG, smoother=zero, check_every=4)),
+             ("fcg_learned_mg", dict(form=sem.FORM_FCG_LEARNED_MG, smoother=smg, check_every=4)),
+             ("gmres_learned_mg", dict(form=sem.FORM_GMRES_LEARNED_MG, smoother=smg, restart=10))]
+    res = {name: [] for name, _ in forms}
     for h in range(args.heldout):
         b = rhs(2000 + h)
-        rj, _ = timed_solves(mesh, b, 2)
-        rl, _ = timed_solves(mesh, b, 2, form=sem.FORM_FCG_LEARNED, smoother=sm)
-        res_j.append(rj)
-        res_l.append(rl)
-    tj = statistics.mean(r["median_ms"] for r in res_j)
-    tl = statistics.mean(r["median_ms"] for r in res_l)
-    return {"workload": "16^3 tanh-stretched channel, N=7, periodic x/z, Poisson, k^-5/3 divergence RHS",
-            "train_fields": args.train_fields, "pairs": args.train_fields * len(iters), "snapshot_iters": iters,
-            "generation": "online: each field's pairs are generated, used for one Adam step each, and dropped",
-            "loss_first_quarter": round(float(lv[:nq].mean()), 5) if len(lv) else None,
-            "loss_last_quarter": round(float(lv[-nq:].mean()), 5) if len(lv) else None,
-            "data_gen_s": round(t_data, 2), "train_s": round(t_train, 2),
-            "train_ms_per_step": round(t_train / max(len(lv), 1) * 1e3, 3),
-            "heldout_one_step_error": {"jacobi": round(loss_jacobi, 4), "trained": round(loss_trained, 4),
-                                       "what": "A-norm error energy left after one smoother application, "
-                                               "held-out Jacobi-PCG iterate errors"},
-            "heldout": args.heldout,
-            "jacobi_pcg": {"median_ms": round(tj, 3), "iterations": [r["iterations"] for r in res_j]},
-            "fcg_learned": {"median_ms": round(tl, 3), "iterations": [r["iterations"] for r in res_l],
-                            "fallback_used": [r["fallback_used"] for r in res_l],
-                            "true_rel_res_max": max(r["true_rel_res"] for r in res_l)},
-            "speedup_vs_jacobi_pcg": round(tj / tl, 3)}
+        for name, kw in forms:
+            r, _ = timed_solves(mesh, b, 2, **kw)
+            res[name].append(r)
+    mean_ms = {name: statistics.mean(r["median_ms"] for r in rs) for name, rs in res.items()}
+    out = {"workload": "16^3 tanh-stretched channel, N=7, periodic x/z, Poisson, k^-5/3 divergence RHS",
+           "train_fields": args.train_fields, "pairs": args.train_fields * len(iters), "snapshot_iters": iters,
+           "generation": "online: each field's pairs are generated, used for one Adam step each, and dropped",
+           "loss_first_quarter": round(float(lv[:nq].mean()), 5) if len(lv) else None,
+           "loss_last_quarter": round(float(lv[-nq:].mean()), 5) if len(lv) else None,
+           "data_gen_s": round(t_data, 2), "train_s": round(t_train, 2),
+           "train_ms_per_step": round(t_train / max(len(lv), 1) * 1e3, 3),
+           "heldout_one_step_error": {"jacobi": round(loss_jacobi, 4), "trained": round(loss_trained, 4),
+                                      "what": "A-norm error energy left after one smoother application, "
+                                              "held-out Jacobi-PCG iterate errors"},
+           "mg_context_training": {"pairs": len(lvm), "extra": "two white-noise errors per field",
+                                   "loss_first_quarter": round(float(lvm[:nqm].mean()), 5) if len(lvm) else None,
+                                   "loss_last_quarter": round(float(lvm[-nqm:].mean()), 5) if len(lvm) else None,
+                                   "train_s": round(t_train_mg, 2),
+                                   "heldout_one_step_error": {"zero_net": round(loss_jacobi_mg, 4),
+                                                              "trained": round(loss_trained_mg, 4),
+                                                              "what": "A-norm error energy left after one "
+                                                                      "learned-multigrid application"}},
+           "heldout": args.heldout}
+    for name, rs in res.items():
+        out[name] = {"median_ms": round(mean_ms[name], 3), "iterations": [r["iterations"] for r in rs],
+                     "fallback_used": [r["fallback_used"] for r in rs],
+                     "true_rel_res_max": max(r["true_rel_res"] for r in rs)}
+        if name != "jacobi_pcg":
+            out[name]["speedup_vs_jacobi_pcg"] = round(mean_ms["jacobi_pcg"] / mean_ms[name], 3)
+    out["speedup_vs_jacobi_pcg"] = out["fcg_learned"]["speedup_vs_jacobi_pcg"]
+    out["network_gain_in_multigrid"] = round(mean_ms["fcg_learned_mg_zero_net"] / mean_ms["fcg_learned_mg"], 3)
+    return out
 
 
 def channel_rhs(mesh, cfg, nel, t=0):

@@ -307,8 +307,9 @@ sem_status sem_pcg_solve_noalloc(const sem_mesh *mesh, const sem_solve_opts *opt
  *     M(r) = dinv o r + mask(Q^T (c / mult)).
  * A zero last layer gives Jacobi; M(a r) = a M(r) for a > 0.  Weights:
  * W1[16][2][27] | W2[16][16][27] | W3[16][27] (tap = 9 (dk+1) + 3 (dj+1) + di+1),
- * 8208 floats, FP32 master copy; inference runs layer 2 in BF16 on the matrix
- * cores with FP32 accumulation, training runs in FP32.
+ * 8208 floats, FP32 master copy; inference runs every layer on the BF16
+ * matrix cores (inputs and weights rounded to BF16, FP32 accumulation);
+ * training runs in FP32.
  * Training loss of a pair (r = S e, e): L = |e - M(r)|_S^2 / |e|_S^2, Adam. */
 typedef struct {
     uint32_t seed;            /* He-normal init of layers 1-2; layer 3 starts at zero */

@@ -636,7 +636,7 @@ sem_status sem_smoother_create(const sem_mesh *mesh, const sem_smoother_desc *de
     }
     struct Alloc { void **p; size_t bytes; } allocs[] = {
         {(void **)&sm.W, kParams * 4}, {(void **)&sm.m, kParams * 4}, {(void **)&sm.v, kParams * 4},
-        {(void **)&sm.grad, kParams * 4}, {(void **)&sm.W2b, kW2 * 2},
+        {(void **)&sm.grad, kParams * 4}, {(void **)&sm.W2b, kWeightOperands * 2},
         {(void **)&sm.dW_elem, (size_t)m.E * kParams * 4}, {(void **)&sm.c_local, (size_t)m.nl * 4},
         {(void **)&sm.buf, (size_t)(6 * m.ng + m.nl) * 8},
         {(void **)&sm.part, (size_t)part_capacity(m.lat, m.E) * 2 * 8}, {(void **)&sm.stage, (size_t)kStage * 2 * 8},

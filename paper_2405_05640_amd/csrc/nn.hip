@@ -9,14 +9,23 @@
 //   M(r) = dinv o r + mask(Q^T (c / mult))
 // Only N = 7 (8^3 tiles) is supported.
 //
-// Inference layout (one element per 512-thread workgroup, thread = position):
-//  - layer 1 (2 -> 16, 54 MACs per output) and layer 3 (16 -> 1) on the FP32
-//    vector units, weights read as wave-uniform (scalar) loads;
-//  - layer 2 (16 -> 16, 27 taps) on the matrix cores: for each tap a
-//    16x16x16 BF16 MFMA multiplies 16 positions x 16 input channels by the
-//    tap's 16 x 16 weight block, FP32 accumulation.  Activations sit in LDS
-//    channel-last with a zero halo (10^3 x 16 BF16 = 32 KB), so every A
-//    operand is one 8-byte LDS read; the 27 B operands stay in registers.
+// Inference layout (one element per 512-thread workgroup; every layer on
+// the BF16 matrix cores with FP32 accumulation, each wavefront owning four
+// blocks of 16 positions, inputs and weights rounded to BF16):
+//  - layer 1 (2 -> 16): K = (channel, tap) = 54 terms padded to 64, two
+//    16x16x32 MFMAs per block;
+//  - layer 2 (16 -> 16, 27 taps): K = (tap, channel) = 432 padded to 448,
+//    fourteen 16x16x32 MFMAs per block, two taps of 16 channels each.
+//    Activations sit in LDS channel-last with a zero halo (10^3 positions x
+//    16 BF16, 48-byte pitch = 48 KB), so every A operand is one 16-byte LDS
+//    read and every activation store one 32-bit word;
+//  - layer 3 (16 -> 1): the same A operands against a B whose column 0 holds
+//    W3 (15 of 16 columns idle, still far fewer cycles than 432 vector FMAs
+//    per position).
+// (Layers 1 and 3 on the vector units, 16-bit activation stores into a
+// 32-byte pitch and 16x16x16 MFMAs took 178 us per launch on the 16^3
+// channel; rocprofv3 counted 4.8e7 LDS bank-conflict cycles against 1.4e7
+// active LDS cycles.)
 // Training keeps everything in FP32 (the accuracy reference of the BF16
 // inference path); per-element weight gradients are reduced over elements
 // in a fixed order.
@@ -28,6 +37,11 @@ namespace nn {
 
 typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short s16x8;
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
 
 constexpr int NP = 8, P3 = 512, PD = 10, PD3 = 1000;
 
@@ -84,20 +98,81 @@ __device__ __forceinline__ int tap_off(int tap)
 
 // ---------------------------------------------------------------- inference
 
+// value of the neighbouring lane (lane ^ 1), a DPP move (no LDS traffic)
+__device__ __forceinline__ float lane_xor1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// two floats -> packed BF16 pair (round to nearest even, one instruction)
+__device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
+{
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
+}
+
+// LDS row of one position of the BF16 activation tile: 16 channels plus 8
+// halfwords of padding.  The 48-byte pitch keeps the 16-byte operand reads
+// aligned and puts positions 4 apart (the rows a C tile's lanes write
+// together) on different banks; a 32-byte pitch put them on the same eight.
+constexpr int YS = 24;
+// matrix-core weight operands (BF16, built from the FP32 master weights):
+//   layer 2 [tap 0..27][o][c] (tap 27 zero), layer 3 [tap 0..27][c],
+//   layer 1 [o][k], k = 27 c + tap (k = 54..63 zero)
+constexpr int kW2B = 28 * 256, kW3B = 28 * 16, kW1B = 16 * 64;
+
+// Activation store from an MFMA C tile (lane (kq, n): rows 4 kq + q, column
+// n = channel): each even lane packs channels (n, n + 1) of rows q = 0, 1,
+// each odd lane channels (n - 1, n) of rows q = 2, 3, so every store is one
+// 32-bit word (ReLU, then BF16).
+__device__ __forceinline__ void store_tile(unsigned short *Ys, const f4 &acc, int row0, int kq, int n16)
+{
+    float x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = lane_xor1(acc[q]);
+    const bool odd = n16 & 1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = odd ? 2 + h : h;
+        const float own = fmaxf(acc[q], 0.f), other = fmaxf(x[q], 0.f);
+        const int pos = row0 + 4 * kq + q;
+        const int at = pidx(pos >> 6, (pos >> 3) & 7, pos & 7) * YS + (n16 & ~1);
+        *(unsigned *)&Ys[at] = odd ? pack_bf16(other, own) : pack_bf16(own, other);
+    }
+}
+
+// 16 x 16 x 432 contraction of a layer with 16 input channels over the 27
+// taps: 14 MFMAs of K = 32 (two taps of 16 channels; the 28th tap is zero).
+// Lane (g, m): A row m = position pb[b], K group g = tap 2 st + g / 2,
+// channels 8 (g % 2) .. + 7.
+__device__ __forceinline__ void conv16(const unsigned short *Ys, const int (&pb)[4], int g, const bf16x8 (&bop)[14],
+                                       f4 (&acc)[4])
+{
+#pragma unroll
+    for (int st = 0; st < 14; ++st) {
+        const int tap = 2 * st + (g >> 1);
+        const int off = (tap < 27 ? tap_off(tap) : 0) * YS + 8 * (g & 1);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            s16x8 a = *(const s16x8 *)&Ys[pb[b] * YS + off];
+            if (tap >= 27) a = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), bop[st], acc[b], 0, 0, 0);
+        }
+    }
+}
+
 template <typename TR>
 __global__ void __launch_bounds__(512)
-infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L, const float *__restrict__ W1,
-             const unsigned short *__restrict__ W2b, const float *__restrict__ W3, float *__restrict__ c_out,
-             const int32_t *__restrict__ skip)
+infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L, const unsigned short *__restrict__ Wb,
+             float *__restrict__ c_out, const int32_t *__restrict__ skip)
 {
     if (skip && *skip) return;
     __shared__ float Xs[2 * PD3];
-    __shared__ __attribute__((aligned(16))) unsigned short Ys[PD3 * 16];
+    __shared__ __attribute__((aligned(16))) unsigned short Ys[PD3 * YS];
     __shared__ float red[8];
-    const int p = threadIdx.x, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
+    const int p = threadIdx.x;
     const int64_t e = xcd_block();
     for (int q = p; q < 2 * PD3; q += 512) Xs[q] = 0.f;
-    for (int q = p; q < PD3 * 8; q += 512) ((unsigned *)Ys)[q] = 0u;
+    for (int q = p; q < PD3 * YS / 2; q += 512) ((unsigned *)Ys)[q] = 0u;
     float t;
     bool live;
     __syncthreads();
@@ -107,66 +182,88 @@ infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L,
         return;
     }
     __syncthreads();
-    // layer 1: 2 -> 16, FP32
-    {
-        float acc[16];
-#pragma unroll
-        for (int o = 0; o < 16; ++o) acc[o] = 0.f;
-        const int base = pidx(k, j, i);
-        for (int c = 0; c < 2; ++c)
-            for (int tap = 0; tap < 27; ++tap) {
-                const float x = Xs[c * PD3 + base + tap_off(tap)];
-#pragma unroll
-                for (int o = 0; o < 16; ++o) acc[o] += W1[(o * 2 + c) * 27 + tap] * x;
-            }
-        unsigned pk[8];
-#pragma unroll
-        for (int o = 0; o < 8; ++o)
-            pk[o] = (unsigned)f2bf(fmaxf(acc[2 * o], 0.f)) | ((unsigned)f2bf(fmaxf(acc[2 * o + 1], 0.f)) << 16);
-        uint4 *dst = (uint4 *)&Ys[base * 16];
-        dst[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
-        dst[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
-    }
-    __syncthreads();
-    // layer 2: 16 -> 16 on the matrix cores
+    // Each wavefront owns four blocks of 16 positions (rows of the MFMA
+    // tiles); lane = (g, n): A row / C column n = lane & 15, K group g.
     const int lane = p & 63, wave = p >> 6;
-    const int mrow = lane & 15, kq = lane >> 4;   // A: row m, channels 4kq..4kq+3
-    f4 acc[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
-    int abase[4];
+    const int n16 = lane & 15, g = lane >> 4;
+    const unsigned short *W2b = Wb, *W3b = Wb + kW2B, *W1b = Wb + kW2B + kW3B;
+    int pb[4];   // padded-tile index of this lane's A row in each block
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        const int pos = (wave * 4 + b) * 16 + mrow;
-        abase[b] = pidx(pos >> 6, (pos >> 3) & 7, pos & 7) * 16 + 4 * kq;
+        const int pos = (wave * 4 + b) * 16 + n16;
+        pb[b] = pidx(pos >> 6, (pos >> 3) & 7, pos & 7);
     }
-    for (int tap = 0; tap < 27; ++tap) {
-        const bf16x4 bop = *(const bf16x4 *)&W2b[(tap * 16 + (lane & 15)) * 16 + 4 * kq];
-        const int off = tap_off(tap) * 16;
+    // layer 1: 2 -> 16, K = (channel, tap) = 54 terms padded to 64, two
+    // 16x16x32 BF16 MFMAs per block; the lane's 16 K offsets are fixed
+    // (tap offsets can be negative: the padding terms carry kNoTap)
+    {
+        constexpr int kNoTap = -(1 << 20);
+        int koff[16];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const bf16x4 aop = *(const bf16x4 *)&Ys[abase[b] + off];
-            acc[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aop, bop, acc[b], 0, 0, 0);
+        for (int j = 0; j < 16; ++j) {
+            const int k = 32 * (j >> 3) + 8 * g + (j & 7);
+            const int c = k / 27, tap = k - 27 * c;
+            koff[j] = k < 54 ? c * PD3 + tap_off(tap) : kNoTap;
         }
+        f4 acc[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            const bf16x8 bop = *(const bf16x8 *)&W1b[n16 * 64 + 32 * st + 8 * g];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                unsigned w[4];
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const int o0 = koff[8 * st + 2 * h], o1 = koff[8 * st + 2 * h + 1];
+                    w[h] = pack_bf16(o0 != kNoTap ? Xs[pb[b] + o0] : 0.f, o1 != kNoTap ? Xs[pb[b] + o1] : 0.f);
+                }
+                const bf16x8 aop = __builtin_bit_cast(bf16x8, (u32x4){w[0], w[1], w[2], w[3]});
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc[b], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) store_tile(Ys, acc[b], (wave * 4 + b) * 16, g, n16);
+    }
+    __syncthreads();
+    // layer 2: 16 -> 16 (B: the tap's 16 x 16 block, output channel n16)
+    f4 acc[4];
+    {
+        bf16x8 bop[14];
+#pragma unroll
+        for (int st = 0; st < 14; ++st)
+            bop[st] = *(const bf16x8 *)&W2b[((2 * st + (g >> 1)) * 16 + n16) * 16 + 8 * (g & 1)];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
+        conv16(Ys, pb, g, bop, acc);
     }
     __syncthreads();   // every wave has finished reading layer-1 activations
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int pos = (wave * 4 + b) * 16 + 4 * kq + q;   // C: row 4kq+q, column = out channel
-            Ys[pidx(pos >> 6, (pos >> 3) & 7, pos & 7) * 16 + (lane & 15)] = f2bf(fmaxf(acc[b][q], 0.f));
-        }
+    for (int b = 0; b < 4; ++b) store_tile(Ys, acc[b], (wave * 4 + b) * 16, g, n16);
     __syncthreads();
-    // layer 3: 16 -> 1, FP32
-    float y = 0.f;
-    const int base = pidx(k, j, i);
-    for (int tap = 0; tap < 27; ++tap) {
-        const unsigned short *yp = &Ys[(base + tap_off(tap)) * 16];
+    // layer 3: 16 -> 1 as a 16 -> 16 layer whose B has only column 0 (W3)
+    {
+        bf16x8 bop[14];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) y += W3[c * 27 + tap] * bf2f(yp[c]);
+        for (int st = 0; st < 14; ++st) {
+            bop[st] = *(const bf16x8 *)&W3b[(2 * st + (g >> 1)) * 16 + 8 * (g & 1)];
+            if (n16 != 0) bop[st] = __builtin_bit_cast(bf16x8, s16x8{0, 0, 0, 0, 0, 0, 0, 0});
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
+        conv16(Ys, pb, g, bop, acc);
     }
-    c_out[e * P3 + p] = t * y;
+    // column 0 lives in lanes n16 == 0; stage through LDS (Xs is free) so
+    // that the output store is coalesced
+    if (n16 == 0) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Xs[(wave * 4 + b) * 16 + 4 * g + q] = acc[b][q];
+    }
+    __syncthreads();
+    c_out[e * P3 + p] = t * Xs[p];
 }
 
 // ---------------------------------------------------------------- training (FP32)
@@ -363,13 +460,22 @@ __global__ void adam_kernel(float *__restrict__ W, float *__restrict__ m, float 
     W[w] -= lr * (mw / c1) / (sqrtf(vw / c2) + eps);
 }
 
-// W2 (FP32 [o][c][tap]) -> BF16 matrix-core operands [tap][o][c]
-__global__ void pack_w2_kernel(const float *__restrict__ W, unsigned short *__restrict__ W2b)
+// FP32 master weights -> the BF16 matrix-core operands of the inference
+// kernel (layouts at kW2B): W2 [o][c][tap] -> [tap][o][c], W3 [c][tap] ->
+// [tap][c], W1 [o][c][tap] -> [o][27 c + tap]; padding entries are zero
+__global__ void pack_w2_kernel(const float *__restrict__ W, unsigned short *__restrict__ Wb)
 {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= kW2) return;
-    const int o = w / (16 * 27), c = (w / 27) % 16, tap = w % 27;
-    W2b[(tap * 16 + o) * 16 + c] = f2bf(W[kW1 + w]);
+    if (w < kW2B) {
+        const int tap = w / 256, o = (w / 16) % 16, c = w % 16;
+        Wb[w] = tap < 27 ? f2bf(W[kW1 + (o * 16 + c) * 27 + tap]) : 0;
+    } else if (w < kW2B + kW3B) {
+        const int v = w - kW2B, tap = v / 16, c = v % 16;
+        Wb[w] = tap < 27 ? f2bf(W[kW1 + kW2 + c * 27 + tap]) : 0;
+    } else if (w < kW2B + kW3B + kW1B) {
+        const int v = w - kW2B - kW3B, o = v / 64, k = v % 64;
+        Wb[w] = k < 54 ? f2bf(W[o * 54 + k]) : 0;
+    }
 }
 
 // z = dinv r + sum_copies c / mult (+ zp[g] if zp: the learned multigrid's
@@ -406,8 +512,8 @@ template <typename TR>
 hipError_t nn_infer(const Smoother &sm, const Mesh &m, const TR *rg, const TR *dinvg, float *c_local, hipStream_t s,
                     const int32_t *skip)
 {
-    hipLaunchKernelGGL((nn::infer_kernel<TR>), dim3((unsigned)m.E), dim3(512), 0, s, rg, dinvg, m.lat, sm.W,
-                       sm.W2b, sm.W + kW1 + kW2, c_local, skip);
+    hipLaunchKernelGGL((nn::infer_kernel<TR>), dim3((unsigned)m.E), dim3(512), 0, s, rg, dinvg, m.lat, sm.W2b,
+                       c_local, skip);
     return hipGetLastError();
 }
 
@@ -444,7 +550,8 @@ hipError_t nn_adam(Smoother &sm, const float *grad, hipStream_t s)
 
 hipError_t nn_pack(Smoother &sm, hipStream_t s)
 {
-    hipLaunchKernelGGL(nn::pack_w2_kernel, dim3((kW2 + 255) / 256), dim3(256), 0, s, sm.W, sm.W2b);
+    hipLaunchKernelGGL(nn::pack_w2_kernel, dim3((nn::kW2B + nn::kW3B + nn::kW1B + 255) / 256), dim3(256), 0, s, sm.W,
+                       sm.W2b);
     return hipGetLastError();
 }
 

@@ -12,13 +12,14 @@ constexpr int kW1 = kChannels * 2 * 27;          // layer 1: [o][c][tap]
 constexpr int kW2 = kChannels * kChannels * 27;  // layer 2: [o][c][tap]
 constexpr int kW3 = kChannels * 27;              // layer 3: [c][tap]
 constexpr int kParams = kW1 + kW2 + kW3;         // 8208
+constexpr int kWeightOperands = 28 * 256 + 28 * 16 + 16 * 64;   // BF16 operands of layers 2, 3, 1
 
 struct Smoother {
     int64_t E = 0, ng = 0, nl = 0;
     float *W = nullptr;             // FP32 master weights [W1 | W2 | W3]
     float *m = nullptr, *v = nullptr;  // Adam moments
     float *grad = nullptr;          // reduced gradient
-    unsigned short *W2b = nullptr;  // BF16 layer-2 operands [tap][o][c]
+    unsigned short *W2b = nullptr;  // BF16 matrix-core operands of the inference (kWeightOperands)
     float *dW_elem = nullptr;       // [E][kParams] per-element gradients
     float *c_local = nullptr;       // [nl] element outputs
     double *buf = nullptr;          // training vectors: e, r, z, d, sd (5 x ng), w (nl)
