@@ -636,8 +636,9 @@ sem_status sem_smoother_create(const sem_mesh *mesh, const sem_smoother_desc *de
     }
     struct Alloc { void **p; size_t bytes; } allocs[] = {
         {(void **)&sm.W, kParams * 4}, {(void **)&sm.m, kParams * 4}, {(void **)&sm.v, kParams * 4},
-        {(void **)&sm.grad, kParams * 4}, {(void **)&sm.W2b, kWeightOperands * 2},
-        {(void **)&sm.dW_elem, (size_t)m.E * kParams * 4}, {(void **)&sm.c_local, (size_t)m.nl * 4},
+        {(void **)&sm.grad, kParams * 4}, {(void **)&sm.W2b, kWeightOperands * 2}, {(void **)&sm.Wt, kWtFloats * 4},
+        {(void **)&sm.dW_elem, (size_t)m.E * kParams * 4}, {(void **)&sm.gpart, (size_t)kGradChunks * kParams * 8},
+        {(void **)&sm.c_local, (size_t)m.nl * 4},
         {(void **)&sm.buf, (size_t)(6 * m.ng + m.nl) * 8},
         {(void **)&sm.part, (size_t)part_capacity(m.lat, m.E) * 2 * 8}, {(void **)&sm.stage, (size_t)kStage * 2 * 8},
         {(void **)&sm.scal, 64}, {(void **)&sm.mg_ws, sm.mg_context ? hsmg_bufs_bytes(m) : 0}};
@@ -665,7 +666,7 @@ sem_status sem_smoother_destroy(sem_smoother *sm)
 {
     if (!sm) return SEM_OK;
     Smoother &s = sm->s;
-    void *ps[] = {s.W, s.m, s.v, s.grad, s.W2b, s.dW_elem, s.c_local, s.buf, s.part, s.stage, s.scal, s.mg_ws};
+    void *ps[] = {s.W, s.m, s.v, s.grad, s.W2b, s.Wt, s.dW_elem, s.gpart, s.c_local, s.buf, s.part, s.stage, s.scal, s.mg_ws};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete sm;

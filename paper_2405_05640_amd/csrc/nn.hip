@@ -269,8 +269,10 @@ infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L,
 // ---------------------------------------------------------------- training (FP32)
 
 // Forward of element e in FP32; keeps X (Xs), Y1 (Y1s, channel-major padded)
-// and Y2 (Y2s) in LDS.  Returns y3 at this thread's position.
-__device__ float fwd32(const float *__restrict__ W1, const float *__restrict__ W2, const float *__restrict__ W3,
+// and Y2 (Y2s) in LDS.  Returns y3 at this thread's position.  W1t, W2t:
+// layers 1 and 2 as [c][tap][o], so that the 16 output-channel weights of an
+// (input channel, tap) pair are one contiguous wave-uniform load.
+__device__ float fwd32(const float *__restrict__ W1t, const float *__restrict__ W2t, const float *__restrict__ W3,
                        const float *Xs, float *Y1s, float *Y2s)
 {
     const int p = threadIdx.x, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
@@ -282,7 +284,7 @@ __device__ float fwd32(const float *__restrict__ W1, const float *__restrict__ W
         for (int tap = 0; tap < 27; ++tap) {
             const float x = Xs[c * PD3 + base + tap_off(tap)];
 #pragma unroll
-            for (int o = 0; o < 16; ++o) acc[o] += W1[(o * 2 + c) * 27 + tap] * x;
+            for (int o = 0; o < 16; ++o) acc[o] += W1t[(c * 27 + tap) * 16 + o] * x;
         }
 #pragma unroll
     for (int o = 0; o < 16; ++o) Y1s[o * PD3 + base] = fmaxf(acc[o], 0.f);
@@ -293,7 +295,7 @@ __device__ float fwd32(const float *__restrict__ W1, const float *__restrict__ W
         for (int tap = 0; tap < 27; ++tap) {
             const float x = Y1s[c * PD3 + base + tap_off(tap)];
 #pragma unroll
-            for (int o = 0; o < 16; ++o) acc[o] += W2[(o * 16 + c) * 27 + tap] * x;
+            for (int o = 0; o < 16; ++o) acc[o] += W2t[(c * 27 + tap) * 16 + o] * x;
         }
 #pragma unroll
     for (int o = 0; o < 16; ++o) Y2s[o * PD3 + base] = fmaxf(acc[o], 0.f);
@@ -310,8 +312,8 @@ __device__ float fwd32(const float *__restrict__ W1, const float *__restrict__ W
 template <typename TR>
 __global__ void __launch_bounds__(512)
 train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const double *__restrict__ gz, Lattice L,
-             const float *__restrict__ W1, const float *__restrict__ W2, const float *__restrict__ W3,
-             float *__restrict__ dW)
+             const float *__restrict__ W1t, const float *__restrict__ W2t, const float *__restrict__ W3,
+             const float *__restrict__ W2u, float *__restrict__ dW)
 {
     __shared__ float Xs[2 * PD3];
     __shared__ float Y1s[16 * PD3];
@@ -334,7 +336,7 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
         return;
     }
     __syncthreads();
-    fwd32(W1, W2, W3, Xs, Y1s, Bs);
+    fwd32(W1t, W2t, W3, Xs, Y1s, Bs);
     // output gradient
     {
         int ex, ey, ez;
@@ -390,7 +392,7 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
         for (int tap = 0; tap < 27; ++tap) {
             const float gv = Bs[o * PD3 + base - tap_off(tap)];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) g1v[c] += W2[(o * 16 + c) * 27 + tap] * gv;
+            for (int c = 0; c < 16; ++c) g1v[c] += W2u[(o * 27 + tap) * 16 + c] * gv;
         }
 #pragma unroll
     for (int c = 0; c < 16; ++c) g1v[c] = Y1s[c * PD3 + base] > 0.f ? g1v[c] : 0.f;
@@ -413,8 +415,8 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
 // FP32 forward writing c = t y3 (the training-path smoother output)
 template <typename TR>
 __global__ void __launch_bounds__(512)
-infer32_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L, const float *__restrict__ W1,
-               const float *__restrict__ W2, const float *__restrict__ W3, float *__restrict__ c_out)
+infer32_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L, const float *__restrict__ W1t,
+               const float *__restrict__ W2t, const float *__restrict__ W3, float *__restrict__ c_out)
 {
     __shared__ float Xs[2 * PD3];
     __shared__ float Y1s[16 * PD3];
@@ -433,17 +435,34 @@ infer32_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice 
         return;
     }
     __syncthreads();
-    const float y = fwd32(W1, W2, W3, Xs, Y1s, Y2s);
+    const float y = fwd32(W1t, W2t, W3, Xs, Y1s, Y2s);
     c_out[e * P3 + p] = t * y;
 }
 
-// out[w] = scale * sum_e dW[e][w] (fixed order)
-__global__ void reduce_grad_kernel(const float *__restrict__ dW, int64_t E, double scale, float *__restrict__ out)
+// Weight gradient summed over elements in two fixed-order stages: stage 1
+// sums chunk blockIdx.y of the elements for every weight (coalesced rows of
+// dW), stage 2 the kGradChunks chunk sums.  (One thread per weight looping
+// over all elements took 1.06 ms per training step on the 16^3 channel.)
+__global__ void __launch_bounds__(256)
+grad_chunks_kernel(const float *__restrict__ dW, int64_t E, double *__restrict__ part)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= kParams) return;
+    const int64_t chunk = (E + kGradChunks - 1) / kGradChunks;
+    const int64_t lo = blockIdx.y * chunk, hi = lo + chunk < E ? lo + chunk : E;
+    double s = 0.0;
+    for (int64_t e = lo; e < hi; ++e) s += (double)dW[e * kParams + w];
+    part[(int64_t)blockIdx.y * kParams + w] = s;
+}
+
+// out[w] = scale * sum over chunks of part[chunk][w] (fixed order)
+__global__ void __launch_bounds__(256)
+grad_finish_kernel(const double *__restrict__ part, double scale, float *__restrict__ out)
 {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= kParams) return;
     double s = 0.0;
-    for (int64_t e = 0; e < E; ++e) s += (double)dW[e * kParams + w];
+    for (int c = 0; c < kGradChunks; ++c) s += part[(int64_t)c * kParams + w];
     out[w] = (float)(s * scale);
 }
 
@@ -475,6 +494,24 @@ __global__ void pack_w2_kernel(const float *__restrict__ W, unsigned short *__re
     } else if (w < kW2B + kW3B + kW1B) {
         const int v = w - kW2B - kW3B, o = v / 64, k = v % 64;
         Wb[w] = k < 54 ? f2bf(W[o * 54 + k]) : 0;
+    }
+}
+
+// FP32 master weights -> the FP32 layouts of the training loops (at Wt):
+// W1t, W2t [c][tap][o] (the forward's output channels contiguous), W2u
+// [o][tap][c] (the backward's input channels contiguous)
+__global__ void pack_t_kernel(const float *__restrict__ W, float *__restrict__ Wt)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < kW1) {
+        const int c = w / (27 * 16), tap = (w / 16) % 27, o = w % 16;
+        Wt[w] = W[(o * 2 + c) * 27 + tap];
+    } else if (w < kW1 + kW2) {
+        const int v = w - kW1, c = v / (27 * 16), tap = (v / 16) % 27, o = v % 16;
+        Wt[w] = W[kW1 + (o * 16 + c) * 27 + tap];
+    } else if (w < kW1 + 2 * kW2) {
+        const int v = w - kW1 - kW2, o = v / (27 * 16), tap = (v / 16) % 27, c = v % 16;
+        Wt[w] = W[kW1 + (o * 16 + c) * 27 + tap];
     }
 }
 
@@ -529,10 +566,11 @@ hipError_t nn_assemble_z(const Mesh &m, const TR *rg, const TR *dinvg, const flo
 hipError_t nn_grad(const Smoother &sm, const Mesh &m, const double *rg, const double *dinvg, const double *gz,
                    float *dW_elem, double scale, float *grad, hipStream_t s)
 {
-    hipLaunchKernelGGL((nn::train_kernel<double>), dim3((unsigned)m.E), dim3(512), 0, s, rg, dinvg, gz, m.lat, sm.W,
-                       sm.W + kW1, sm.W + kW1 + kW2, dW_elem);
-    hipLaunchKernelGGL(nn::reduce_grad_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, dW_elem, m.E, scale,
-                       grad);
+    hipLaunchKernelGGL((nn::train_kernel<double>), dim3((unsigned)m.E), dim3(512), 0, s, rg, dinvg, gz, m.lat, sm.Wt,
+                       sm.Wt + kW1, sm.W + kW1 + kW2, sm.Wt + kW1 + kW2, dW_elem);
+    hipLaunchKernelGGL(nn::grad_chunks_kernel, dim3((kParams + 255) / 256, kGradChunks), dim3(256), 0, s, dW_elem,
+                       m.E, sm.gpart);
+    hipLaunchKernelGGL(nn::grad_finish_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, sm.gpart, scale, grad);
     return hipGetLastError();
 }
 
@@ -552,14 +590,15 @@ hipError_t nn_pack(Smoother &sm, hipStream_t s)
 {
     hipLaunchKernelGGL(nn::pack_w2_kernel, dim3((nn::kW2B + nn::kW3B + nn::kW1B + 255) / 256), dim3(256), 0, s, sm.W,
                        sm.W2b);
+    hipLaunchKernelGGL(nn::pack_t_kernel, dim3((kWtFloats + 255) / 256), dim3(256), 0, s, sm.W, sm.Wt);
     return hipGetLastError();
 }
 
 hipError_t nn_infer32(const Smoother &sm, const Mesh &m, const double *rg, const double *dinvg, float *c_local,
                       hipStream_t s)
 {
-    hipLaunchKernelGGL((nn::infer32_kernel<double>), dim3((unsigned)m.E), dim3(512), 0, s, rg, dinvg, m.lat, sm.W,
-                       sm.W + kW1, sm.W + kW1 + kW2, c_local);
+    hipLaunchKernelGGL((nn::infer32_kernel<double>), dim3((unsigned)m.E), dim3(512), 0, s, rg, dinvg, m.lat, sm.Wt,
+                       sm.Wt + kW1, sm.W + kW1 + kW2, c_local);
     return hipGetLastError();
 }
 

@@ -12,6 +12,8 @@ constexpr int kW1 = kChannels * 2 * 27;          // layer 1: [o][c][tap]
 constexpr int kW2 = kChannels * kChannels * 27;  // layer 2: [o][c][tap]
 constexpr int kW3 = kChannels * 27;              // layer 3: [c][tap]
 constexpr int kParams = kW1 + kW2 + kW3;         // 8208
+constexpr int kWtFloats = kW1 + 2 * kW2;        // FP32 weight layouts of the training loops
+constexpr int kGradChunks = 64;                  // first-stage chunks of the gradient sum over elements
 constexpr int kWeightOperands = 28 * 256 + 28 * 16 + 16 * 64;   // BF16 operands of layers 2, 3, 1
 
 struct Smoother {
@@ -20,7 +22,9 @@ struct Smoother {
     float *m = nullptr, *v = nullptr;  // Adam moments
     float *grad = nullptr;          // reduced gradient
     unsigned short *W2b = nullptr;  // BF16 matrix-core operands of the inference (kWeightOperands)
+    float *Wt = nullptr;            // FP32 weights in the training loops' layouts (kWtFloats)
     float *dW_elem = nullptr;       // [E][kParams] per-element gradients
+    double *gpart = nullptr;        // [kGradChunks][kParams] chunk sums of the gradient
     float *c_local = nullptr;       // [nl] element outputs
     double *buf = nullptr;          // training vectors: e, r, z, d, sd (5 x ng), w (nl)
     double *part = nullptr;         // partial sums (2 x part_capacity)
