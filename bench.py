@@ -75,7 +75,10 @@ def profile_kernels():
     BF16, a 300-iteration FP64 PCG solve, 300-iteration FP32 and BF16
     reliable-update solves, a 20-iteration GMRES with the multigrid
     preconditioner, and 5 copies of a 1 GiB buffer (exactly 1 GiB read + 1 GiB
-    written each)."""
+    written each); then on the 16^3 channel 5 BF16 and 5 FP32 smoother
+    applications, 5 training steps, 20 iterations of CG with the multigrid
+    and 30 of flexible CG with the learned multigrid."""
+    import numpy as np
     import torch
 
     from paper_2405_05640_amd import sem
@@ -107,6 +110,31 @@ def profile_kernels():
     dst = torch.empty_like(src)
     for _ in range(5):
         dst.copy_(src)
+    torch.cuda.synchronize()
+    del mesh, u, w, u32, w32, b, x, src, dst
+    torch.cuda.empty_cache()
+    mesh = sem.Mesh.from_spec(wl.config("c3"), prepare=sem.SEM_PREP_HSMG)
+    sm = sem.Smoother(mesh, seed=1)
+    wts = sm.get_weights()
+    wts[-432:] = np.random.default_rng(0).standard_normal(432).astype(np.float32) * 0.05
+    sm.set_weights(wts)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    r = torch.randn(mesh.shape, dtype=torch.float64, device="cuda", generator=gen)
+    mesh.dssum(r, mask=True)
+    z = torch.empty_like(r)
+    for fp32 in (False, True):
+        for _ in range(5):
+            sm.apply(r, z, fp32=fp32)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(5):
+        sm.train_step(torch.randn(mesh.n_global, device="cuda", generator=gen), loss)
+    x = torch.zeros_like(r)
+    mesh.pcg_solve(r, x, max_iter=20, raise_on_error=False, form=sem.FORM_PCG_HSMG, check_every=4)
+    x.zero_()
+    zero = sem.Smoother(mesh, seed=1)   # zero last layer: no fallback, so every iteration runs the network
+    mesh.pcg_solve(r, x, max_iter=30, raise_on_error=False, form=sem.FORM_FCG_LEARNED_MG, smoother=zero,
+                   check_every=4)
     torch.cuda.synchronize()
     print("profile-kernels: done", flush=True)
 
