@@ -327,6 +327,7 @@ def learned_section(args):
                      "true_rel_res_max": max(r["true_rel_res"] for r in rs)}
         if name != "jacobi_pcg":
             out[name]["speedup_vs_jacobi_pcg"] = round(mean_ms["jacobi_pcg"] / mean_ms[name], 3)
+    args.learned_weights = smg.get_weights()
     out["speedup_vs_jacobi_pcg"] = out["fcg_learned_mg"]["speedup_vs_jacobi_pcg"]
     out["speedup_vs_jacobi_pcg_plain_smoother"] = out["fcg_learned"]["speedup_vs_jacobi_pcg"]
     out["network_gain_in_multigrid"] = round(mean_ms["fcg_learned_mg_zero_net"] / mean_ms["fcg_learned_mg"], 3)
@@ -376,10 +377,13 @@ def small_section(args):
     return out
 
 
-def large_section(args):
+def large_section(args, learned_weights=None):
     """64^3 channel (262,144 elements, N = 7, Poisson): Ax+dssum rate and time
-    to 1e-10 of FP64 Jacobi-PCG, GMRES with the multigrid preconditioner and
-    the reliable-update FP32 and split-BF16 solvers."""
+    to 1e-10 of FP64 Jacobi-PCG, GMRES and CG with the multigrid
+    preconditioner, the reliable-update FP32 and split-BF16 solvers, and
+    flexible CG with the learned multigrid: a zero network, and the network
+    trained in the multigrid context on the 16^3 channel (learned_weights:
+    the per-element network is the same on any mesh of order 7)."""
     import torch
 
     from paper_2405_05640_amd import sem
@@ -410,7 +414,18 @@ def large_section(args):
              ("reliable_fp32", dict(form=sem.FORM_RELIABLE_FP32, inner_tol=0.1, check_every=32, max_iter=40000)),
              ("reliable_bf16split", dict(form=sem.FORM_RELIABLE_BF16, inner_tol=0.1, check_every=32,
                                          max_iter=40000))]
+    smoothers = []
+    if learned_weights is not None:
+        zero = sem.Smoother(mesh, seed=0)   # zero last layer: Jacobi on the fine level
+        trained = sem.Smoother(mesh, seed=0)
+        trained.set_weights(learned_weights)
+        smoothers = [zero, trained]
+        forms += [("fcg_learned_mg_zero_net", dict(form=sem.FORM_FCG_LEARNED_MG, smoother=zero, check_every=4,
+                                                   max_iter=4000)),
+                  ("fcg_learned_mg", dict(form=sem.FORM_FCG_LEARNED_MG, smoother=trained, check_every=4,
+                                          max_iter=4000))]
     res = run_forms(mesh, b, forms, 1, tag="large")
+    del smoothers
     return {"workload": "64^3 tanh-stretched channel, N=7, periodic x/z, Poisson (134,217,728 local points)",
             "setup_s": round(t_setup, 1), "ax_dssum_gdofs": round(mesh.n_local / dt / 1e9, 2),
             "ax_dssum_us": round(dt * 1e6, 1),
@@ -624,12 +639,13 @@ def main():
     if not args.no_small and not args.no_solve:
         out["small_configs"] = small_section(args)
         torch.cuda.empty_cache()
-    if not args.no_large and not args.no_solve:
-        out["large_single_gpu"] = large_section(args)
-        torch.cuda.empty_cache()
     if not args.no_learned:
         out["learned_smoother"] = learned_section(args)
         print("learned: %s" % json.dumps(out["learned_smoother"]), flush=True)
+        torch.cuda.empty_cache()
+    if not args.no_large and not args.no_solve:
+        out["large_single_gpu"] = large_section(args, getattr(args, "learned_weights", None))
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, h1, h2)
     print(json.dumps(out), flush=True)
