@@ -518,6 +518,90 @@ coarse_axis_kernel(const double *__restrict__ in, double *__restrict__ out, cons
     }
 }
 
+// The coarse solve in three launches instead of six, same arithmetic order
+// per output (bit-identical to coarse_axis_kernel's six passes):
+//  - coarse_plane_kernel: one workgroup per z-plane, the plane in LDS; the
+//    x then the y transform (forward), or y then x (backward), each output
+//    computed into registers, then written back over the plane;
+//  - coarse_column_kernel: whole z-columns in LDS, forward z transform,
+//    division by the eigenvalue sum, backward z transform.
+constexpr int kCoarsePlane = 4352;   // LDS plane capacity (doubles): up to 64 x 68 nodes
+constexpr int kCoarsePer = (kCoarsePlane + kBS - 1) / kBS;
+__global__ void __launch_bounds__(kBS)
+coarse_plane_kernel(double *__restrict__ u, const double *__restrict__ Sx, const double *__restrict__ Sy, int nx, int ny,
+                    int fwd)
+{
+    __shared__ double T[kCoarsePlane];
+    const int np = nx * ny;
+    double *pl = u + (int64_t)blockIdx.x * np;
+    for (int g = threadIdx.x; g < np; g += kBS) T[g] = pl[g];
+    __syncthreads();
+    for (int ph = 0; ph < 2; ++ph) {
+        // forward: x then y; backward: y then x
+        const int ax = fwd ? ph : 1 - ph;
+        const int n = ax == 0 ? nx : ny;
+        const double *S = ax == 0 ? Sx : Sy;
+        double v[kCoarsePer];
+#pragma unroll
+        for (int r = 0; r < kCoarsePer; ++r) {
+            const int g = threadIdx.x + r * kBS;
+            v[r] = 0.0;
+            if (g >= np) continue;
+            const int i = g % nx, j = g / nx;
+            const int idx = ax == 0 ? i : j;
+            const int base = ax == 0 ? j * nx : i, stride = ax == 0 ? 1 : nx;
+            double acc = 0.0;
+            if (fwd)
+                for (int a = 0; a < n; ++a) acc += S[a * n + idx] * T[base + a * stride];
+            else
+                for (int q = 0; q < n; ++q) acc += S[idx * n + q] * T[base + q * stride];
+            v[r] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kCoarsePer; ++r) {
+            const int g = threadIdx.x + r * kBS;
+            if (g < np) T[g] = v[r];
+        }
+        __syncthreads();
+    }
+    for (int g = threadIdx.x; g < np; g += kBS) pl[g] = T[g];
+}
+
+// z-columns (i, j) of the coarse lattice, ncol = kBS / nz per workgroup:
+// forward transform along z, divided by h1 (lx + ly + lz) + h2 (0 where that
+// is not positive), backward transform
+__global__ void __launch_bounds__(kBS)
+coarse_column_kernel(double *__restrict__ u, const double *__restrict__ Sz, int nx, int ny, int nz,
+                     const double *__restrict__ lx, const double *__restrict__ ly, const double *__restrict__ lz,
+                     double h1, double h2)
+{
+    __shared__ double T[kBS];
+    const int ncol = kBS / nz, c = threadIdx.x / nz, k = threadIdx.x % nz;
+    const int64_t col = (int64_t)blockIdx.x * ncol + c;
+    const int64_t plane = (int64_t)nx * ny;
+    const bool on = c < ncol && col < plane;
+    if (on) T[threadIdx.x] = u[col + k * plane];
+    __syncthreads();
+    double v = 0.0;
+    if (on) {
+        const double *t = T + c * nz;
+        for (int a = 0; a < nz; ++a) v += Sz[a * nz + k] * t[a];
+        const int i = (int)(col % nx), j = (int)(col / nx);
+        const double d = h1 * (lx[i] + ly[j] + lz[k]) + h2;
+        v = d > 0.0 ? v / d : 0.0;
+    }
+    __syncthreads();
+    if (on) T[threadIdx.x] = v;
+    __syncthreads();
+    if (on) {
+        const double *t = T + c * nz;
+        double w = 0.0;
+        for (int q = 0; q < nz; ++q) w += Sz[k * nz + q] * t[q];
+        u[col + k * plane] = w;
+    }
+}
+
 // ---------------------------------------------------------------- Krylov kernels
 
 // Block partial sums of NV values per thread: wave butterfly, then the
@@ -966,6 +1050,17 @@ hipError_t coarse_solve(const Mesh &m, double h1, double h2, const HsmgBufs &b, 
 {
     const Hsmg &h = *m.hsmg;
     const int nx = h.cn[0], ny = h.cn[1], nz = h.cn[2];
+    if (nx * ny <= mg::kCoarsePlane && nz <= kBS) {
+        const int ncol = kBS / nz;
+        const unsigned ncb = (unsigned)(((int64_t)nx * ny + ncol - 1) / ncol);
+        hipLaunchKernelGGL(mg::coarse_plane_kernel, dim3((unsigned)nz), dim3(kBS), 0, s, b.rc, h.d_cS[0], h.d_cS[1],
+                           nx, ny, 1);
+        hipLaunchKernelGGL(mg::coarse_column_kernel, dim3(ncb), dim3(kBS), 0, s, b.rc, h.d_cS[2], nx, ny, nz,
+                           h.d_clam[0], h.d_clam[1], h.d_clam[2], h1, h2);
+        hipLaunchKernelGGL(mg::coarse_plane_kernel, dim3((unsigned)nz), dim3(kBS), 0, s, b.rc, h.d_cS[0], h.d_cS[1],
+                           nx, ny, 0);
+        return hipGetLastError();
+    }
     const int nb = cg_blocks(h.ng_c);
     double *in = b.rc, *out = b.tc;
     const int axes[6] = {0, 1, 2, 2, 1, 0};
