@@ -287,6 +287,9 @@ def learned_section(args):
         t_data += t1 - t0
         t_train += t2 - t1
         t_train_mg += time.perf_counter() - t2
+        if (t + 1) % 100 == 0:
+            print("learned: %d fields, data %.1f s, training %.1f + %.1f s" % (t + 1, t_data, t_train, t_train_mg),
+                  flush=True)
     lv = torch.cat(losses).cpu().numpy() if losses else np.zeros(0)
     lvm = torch.cat(losses_mg).cpu().numpy() if losses_mg else np.zeros(0)
     nq, nqm = max(1, len(lv) // 4), max(1, len(lvm) // 4)

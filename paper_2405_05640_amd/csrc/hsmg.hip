@@ -63,6 +63,31 @@ __device__ __forceinline__ int node_count(const Lattice &L, int gi, int gj, int 
            axis_copies_t<NPC>(gk, L.nelz, L.N, L.per[2] != 0, X);
 }
 
+// Block partial sums of NV values per thread: wave butterfly, then the
+// waves of the block in order (deterministic); part[q * nb + block].
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&acc)[NV], int nv, double *__restrict__ part, int nb)
+{
+    __shared__ double red[kBS / 64][NV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        if (q < nv) {
+            double v = acc[q];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) red[wv][q] = v;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nv; q += kBS) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBS / 64; ++w) s += red[w][q];
+        part[(int64_t)q * nb + blockIdx.x] = s;
+    }
+}
+
 // ---------------------------------------------------------------- level kernels
 
 // Element Schwarz solve (and, NPC > 0, restriction of r / mult to the
@@ -370,12 +395,16 @@ schwarz_pencil_kernel(const double *__restrict__ rg, Lattice L, const double *__
 // zp[g], W = 1, 1 / mult or 1 / sqrt(mult); zp (optional) is the
 // prolongated coarser-level correction, one value per node.  kRowsPerBlock
 // lattice rows per workgroup, every load issued before the arithmetic.
+//
+// part (optional): block partials of (r, out), for the CG that applies the
+// preconditioner (saves its separate inner-product pass over r and z).
 template <int NPC>
 __global__ void __launch_bounds__(kBS)
 assemble_fine_kernel(const double *__restrict__ rows, Lattice L, int weighted, const double *__restrict__ zp,
-                     double *__restrict__ out)
+                     double *__restrict__ out, const double *__restrict__ r, double *__restrict__ part)
 {
     const int nrows = (int)(L.ny * L.nz), ny = (int)L.ny, nx = (int)L.nx, row0 = (int)blockIdx.x * kRowsPerBlock;
+    double acc[1] = {0.0};
     for (int gi = threadIdx.x; gi < nx; gi += kBS) {
         double v[kRowsPerBlock], a[kRowsPerBlock];
         int64_t g[kRowsPerBlock];
@@ -400,8 +429,10 @@ assemble_fine_kernel(const double *__restrict__ rows, Lattice L, int weighted, c
                 z += a[q];
             }
             out[g[q]] = z;
+            if (part) acc[0] += r[g[q]] * z;
         }
     }
+    if (part) block_partials<1>(acc, 1, part, gridDim.x);
 }
 
 // zp = J (x) J (x) J zm (the mid level's assembled correction interpolated
@@ -604,31 +635,6 @@ coarse_column_kernel(double *__restrict__ u, const double *__restrict__ Sz, int 
 
 // ---------------------------------------------------------------- Krylov kernels
 
-// Block partial sums of NV values per thread: wave butterfly, then the
-// waves of the block in order (deterministic); part[q * nb + block].
-template <int NV>
-__device__ __forceinline__ void block_partials(double (&acc)[NV], int nv, double *__restrict__ part, int nb)
-{
-    __shared__ double red[kBS / 64][NV];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        if (q < nv) {
-            double v = acc[q];
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-            if (lane == 0) red[wv][q] = v;
-        }
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < nv; q += kBS) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kBS / 64; ++w) s += red[w][q];
-        part[(int64_t)q * nb + blockIdx.x] = s;
-    }
-}
-
 constexpr int kMaxDots = kGmresMaxRestart + 2;   // (V_i, w) for i <= j, plus (w, w)
 
 // w = mask(Q^T rows) -> wout; partials of (V_i, w), i <= j, and (w, w).
@@ -795,16 +801,6 @@ bj_init_kernel(const double *__restrict__ b, const double *__restrict__ dinv, do
     block_partials<1>(acc, 1, part, gridDim.x);
 }
 
-// partial (r, z)
-__global__ void __launch_bounds__(kBS) bj_dot_kernel(const CgState *st, const double *__restrict__ r,
-                                                     const double *__restrict__ z, int64_t ng, double *__restrict__ part)
-{
-    if (st->done) return;
-    double acc[1] = {0.0};
-    GRID_STRIDE(g, ng) acc[0] += r[g] * z[g];
-    block_partials<1>(acc, 1, part, gridDim.x);
-}
-
 // (r, z) from nb partials (per workgroup, or the stage sums): beta = (r, z) / rz_old (0 on the
 // first call), rz = (r, z); a breakdown if (r, z) is not positive
 __global__ void __launch_bounds__(kWide) bj_rz_finalize(CgState *st, const double *__restrict__ part, int nb, int first)
@@ -949,13 +945,13 @@ HsmgBufs hsmg_bufs_carve(const Mesh &m, char *base)
 namespace {
 
 void launch_assemble_fine(const Lattice &L, const double *rows, int weighted, const double *zp, double *out,
-                          hipStream_t s)
+                          hipStream_t s, const double *r = nullptr, double *part = nullptr)
 {
     const dim3 grid((unsigned)((L.ny * L.nz + mg::kRowsPerBlock - 1) / mg::kRowsPerBlock)), block(kBS);
     if (L.NP == 8)
-        hipLaunchKernelGGL(mg::assemble_fine_kernel<8>, grid, block, 0, s, rows, L, weighted, zp, out);
+        hipLaunchKernelGGL(mg::assemble_fine_kernel<8>, grid, block, 0, s, rows, L, weighted, zp, out, r, part);
     else
-        hipLaunchKernelGGL(mg::assemble_fine_kernel<0>, grid, block, 0, s, rows, L, weighted, zp, out);
+        hipLaunchKernelGGL(mg::assemble_fine_kernel<0>, grid, block, 0, s, rows, L, weighted, zp, out, r, part);
 }
 
 void launch_assemble(const Lattice &L, const double *rows, int weighted, double *out, const double *zc,
@@ -1124,7 +1120,7 @@ hipError_t hsmg_coarse_part(const Mesh &m, double h1, double h2, const double *r
 }
 
 hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, double *z, const HsmgBufs &b, int levels,
-                      int weight, hipStream_t s, const FineHook *fine)
+                      int weight, hipStream_t s, const FineHook *fine, double *part_rz)
 {
     const Hsmg &h = *m.hsmg;
     const int sym = weight == kWeightSym ? 1 : 0;
@@ -1139,7 +1135,7 @@ hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, doub
     }
     if (levels == 1) {
         if ((e = fine_schwarz(m, r, h1, h2, b, false, sym, s)) != hipSuccess) return e;
-        launch_assemble_fine(m.lat, b.rows_f, weight, nullptr, z, s);
+        launch_assemble_fine(m.lat, b.rows_f, weight, nullptr, z, s, r, part_rz);
         return hipGetLastError();
     }
     if ((e = fine_schwarz(m, r, h1, h2, b, true, sym, s)) != hipSuccess) return e;
@@ -1149,7 +1145,7 @@ hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, doub
     if ((e = coarse_solve(m, h1, h2, b, s)) != hipSuccess) return e;
     launch_assemble(h.lat_m, b.rows_m, weight, b.zm, b.rc, h.lat_c, h.d_Jmc, s);
     if ((e = prolong_fine(m, b, s)) != hipSuccess) return e;
-    launch_assemble_fine(m.lat, b.rows_f, weight, b.zp, z, s);
+    launch_assemble_fine(m.lat, b.rows_f, weight, b.zp, z, s, r, part_rz);
     return hipGetLastError();
 }
 
@@ -1374,10 +1370,11 @@ sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVec
         SEM_HIP_TRY(hipStreamSynchronize(s));
     }
     auto direction = [&](int first) -> sem_status {
-        SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, v.r, z, hb, levels, weight, s));
-        hipLaunchKernelGGL(mg::bj_dot_kernel, dim3(nbf), dim3(kBS), 0, s, st, v.r, z, ng, v.part_b);
+        // (r, z) partials come from the preconditioner's last kernel, one per
+        // workgroup of nbu
+        SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, v.r, z, hb, levels, weight, s, nullptr, v.part_b));
         const double *in;
-        int64_t n = nbf;
+        int64_t n = nbu;
         SEM_HIP_TRY(finalize_input(v.part_b, n, 1, v.stage, s, &in));
         hipLaunchKernelGGL(mg::bj_rz_finalize, dim3(1), dim3(kWide), 0, s, st, in, (int)n, first);
         if (first)

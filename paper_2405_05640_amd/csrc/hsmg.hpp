@@ -73,9 +73,12 @@ struct FineHook {
 // Dirichlet nodes).  levels: 1 = fine Schwarz only, 3 = the full
 // three-level cycle; weight applies to the fine and mid levels.  fine (not
 // null): the three-level cycle with the learned smoother in place of the
-// fine Schwarz level (levels is then ignored).
+// fine Schwarz level (levels is then ignored).  part_rz (not null, and fine
+// null): block partials of (r, z), one per workgroup of the last kernel
+// (ceil(ny nz / 4) of them, lattice rows of the fine level).
 hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, double *z, const HsmgBufs &b,
-                      int levels, int weight, hipStream_t s, const FineHook *fine = nullptr);
+                      int levels, int weight, hipStream_t s, const FineHook *fine = nullptr,
+                      double *part_rz = nullptr);
 
 // The mid and coarse levels' part alone: b.zp = P_01 [Sw_1(R_10 r) +
 // P_12 C^-1 R_21 R_10 r] (what the cycle adds to its fine level).
