@@ -381,7 +381,7 @@ sem_status loss_forward(const Smoother &sm, const Mesh &m, double h1, double h2,
     // z = M(r) (FP32 network), plus the coarser levels' part C(r) when
     // training in the context of the learned multigrid
     if (sm.mg_context) SEM_HIP_TRY(hsmg_coarse_part(m, h1, h2, t.r, sm.mg, kWeightAvg, s));
-    SEM_HIP_TRY(nn_infer32(sm, m, t.r, t.dinv, sm.c_local, s));
+    SEM_HIP_TRY(nn_infer32(sm, m, t.r, t.dinv, sm.c_local, s, sm.act));
     SEM_HIP_TRY(nn_assemble_z<double>(m, t.r, t.dinv, sm.c_local, t.z, s, nullptr, sm.mg_context ? sm.mg.zp : nullptr));
     // d = e - z, sd = S d, partial (d, S d)
     hipLaunchKernelGGL(lk::sub_kernel, dim3(nb), dim3(kBS), 0, s, t.e, t.z, t.d, m.ng);
@@ -638,6 +638,7 @@ sem_status sem_smoother_create(const sem_mesh *mesh, const sem_smoother_desc *de
         {(void **)&sm.W, kParams * 4}, {(void **)&sm.m, kParams * 4}, {(void **)&sm.v, kParams * 4},
         {(void **)&sm.grad, kParams * 4}, {(void **)&sm.W2b, kWeightOperands * 2}, {(void **)&sm.Wt, kWtFloats * 4},
         {(void **)&sm.dW_elem, (size_t)m.E * kParams * 4}, {(void **)&sm.gpart, (size_t)kGradChunks * kParams * 8},
+        {(void **)&sm.act, (size_t)m.E * 32 * 512 * 4},
         {(void **)&sm.c_local, (size_t)m.nl * 4},
         {(void **)&sm.buf, (size_t)(6 * m.ng + m.nl) * 8},
         {(void **)&sm.part, (size_t)part_capacity(m.lat, m.E) * 2 * 8}, {(void **)&sm.stage, (size_t)kStage * 2 * 8},
@@ -666,7 +667,7 @@ sem_status sem_smoother_destroy(sem_smoother *sm)
 {
     if (!sm) return SEM_OK;
     Smoother &s = sm->s;
-    void *ps[] = {s.W, s.m, s.v, s.grad, s.W2b, s.Wt, s.dW_elem, s.gpart, s.c_local, s.buf, s.part, s.stage, s.scal, s.mg_ws};
+    void *ps[] = {s.W, s.m, s.v, s.grad, s.W2b, s.Wt, s.dW_elem, s.gpart, s.act, s.c_local, s.buf, s.part, s.stage, s.scal, s.mg_ws};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete sm;
@@ -783,7 +784,7 @@ sem_status sem_smoother_loss_grad(sem_smoother *sm, const sem_mesh *mesh, double
     SEM_HIP_TRY(make_dinv(s, m, h1, h2, t, st, true));
     SEM_TRY(gather_local(m, e_local, t.e, st));
     SEM_TRY(loss_forward(s, m, h1, h2, t, st));
-    SEM_HIP_TRY(nn_grad(s, m, t.r, t.dinv, t.d, s.dW_elem, 1.0, s.grad, st));
+    SEM_HIP_TRY(nn_grad(s, m, t.r, t.dinv, t.d, s.dW_elem, 1.0, s.grad, st, s.act));
     double scal[2];
     SEM_HIP_TRY(hipMemcpyAsync(scal, s.scal, 16, hipMemcpyDeviceToHost, st));
     SEM_HIP_TRY(hipMemcpyAsync(grad_host, s.grad, kParams * 4, hipMemcpyDeviceToHost, st));
@@ -804,7 +805,7 @@ sem_status sem_smoother_train_step(sem_smoother *sm, const sem_mesh *mesh, doubl
     SEM_HIP_TRY(make_dinv(s, m, h1, h2, t, st, false));
     hipLaunchKernelGGL(lk::f32_to_f64_kernel, dim3(cg_blocks(m.ng)), dim3(kBS), 0, st, e_global, t.e, m.ng);
     SEM_TRY(loss_forward(s, m, h1, h2, t, st));
-    SEM_HIP_TRY(nn_grad(s, m, t.r, t.dinv, t.d, s.dW_elem, 1.0, s.grad, st));
+    SEM_HIP_TRY(nn_grad(s, m, t.r, t.dinv, t.d, s.dW_elem, 1.0, s.grad, st, s.act));
     SEM_HIP_TRY(nn_adam(s, s.grad, st));
     if (loss_dev) SEM_HIP_TRY(hipMemcpyAsync(loss_dev, s.scal + 1, 8, hipMemcpyDeviceToDevice, st));
     return SEM_OK;

@@ -44,6 +44,10 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
 
 constexpr int NP = 8, P3 = 512, PD = 10, PD3 = 1000;
+// channel stride of the FP32 channel-major activation tiles of the training
+// path: 1001 floats, so that 16 channels at one position fall on 16
+// different banks (with 1000, channels 4 apart share a bank)
+constexpr int CS = 1001;
 
 __device__ __forceinline__ unsigned short f2bf(float f)
 {
@@ -287,22 +291,22 @@ __device__ float fwd32(const float *__restrict__ W1t, const float *__restrict__ 
             for (int o = 0; o < 16; ++o) acc[o] += W1t[(c * 27 + tap) * 16 + o] * x;
         }
 #pragma unroll
-    for (int o = 0; o < 16; ++o) Y1s[o * PD3 + base] = fmaxf(acc[o], 0.f);
+    for (int o = 0; o < 16; ++o) Y1s[o * CS + base] = fmaxf(acc[o], 0.f);
     __syncthreads();
 #pragma unroll
     for (int o = 0; o < 16; ++o) acc[o] = 0.f;
     for (int c = 0; c < 16; ++c)
         for (int tap = 0; tap < 27; ++tap) {
-            const float x = Y1s[c * PD3 + base + tap_off(tap)];
+            const float x = Y1s[c * CS + base + tap_off(tap)];
 #pragma unroll
             for (int o = 0; o < 16; ++o) acc[o] += W2t[(c * 27 + tap) * 16 + o] * x;
         }
 #pragma unroll
-    for (int o = 0; o < 16; ++o) Y2s[o * PD3 + base] = fmaxf(acc[o], 0.f);
+    for (int o = 0; o < 16; ++o) Y2s[o * CS + base] = fmaxf(acc[o], 0.f);
     __syncthreads();
     float y = 0.f;
     for (int c = 0; c < 16; ++c)
-        for (int tap = 0; tap < 27; ++tap) y += W3[c * 27 + tap] * Y2s[c * PD3 + base + tap_off(tap)];
+        for (int tap = 0; tap < 27; ++tap) y += W3[c * 27 + tap] * Y2s[c * CS + base + tap_off(tap)];
     return y;
 }
 
@@ -313,11 +317,11 @@ template <typename TR>
 __global__ void __launch_bounds__(512)
 train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const double *__restrict__ gz, Lattice L,
              const float *__restrict__ W1t, const float *__restrict__ W2t, const float *__restrict__ W3,
-             const float *__restrict__ W2u, float *__restrict__ dW)
+             const float *__restrict__ W2u, float *__restrict__ dW, const float *__restrict__ act)
 {
     __shared__ float Xs[2 * PD3];
-    __shared__ float Y1s[16 * PD3];
-    __shared__ float Bs[16 * PD3];   // Y2, then g2, then g1
+    __shared__ float Y1s[16 * CS];
+    __shared__ float Bs[16 * CS];   // Y2, then g2, then g1
     __shared__ float g3s[PD3];
     __shared__ float red[8];
     const int p = threadIdx.x, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
@@ -325,7 +329,7 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
     const int64_t e = xcd_block();
     float *dWe = dW + e * kParams;
     for (int q = p; q < 2 * PD3; q += 512) Xs[q] = 0.f;
-    for (int q = p; q < 16 * PD3; q += 512) { Y1s[q] = 0.f; Bs[q] = 0.f; }
+    for (int q = p; q < 16 * CS; q += 512) { Y1s[q] = 0.f; Bs[q] = 0.f; }
     for (int q = p; q < PD3; q += 512) g3s[q] = 0.f;
     float t;
     bool live;
@@ -336,7 +340,17 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
         return;
     }
     __syncthreads();
-    fwd32(W1t, W2t, W3, Xs, Y1s, Bs);
+    if (act) {   // the forward activations the loss's forward pass stored
+        const float *a = act + e * (32 * P3);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            Y1s[c * CS + base] = a[c * P3 + p];
+            Bs[c * CS + base] = a[(16 + c) * P3 + p];
+        }
+        __syncthreads();
+    } else {
+        fwd32(W1t, W2t, W3, Xs, Y1s, Bs);
+    }
     // output gradient
     {
         int ex, ey, ez;
@@ -358,7 +372,7 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
         float s = 0.f;
         for (int q = 0; q < P3; ++q) {
             const int b = pidx(q >> 6, (q >> 3) & 7, q & 7);
-            s += g3s[b] * Bs[c * PD3 + b + off];
+            s += g3s[b] * Bs[c * CS + b + off];
         }
         dWe[kW1 + kW2 + w] = s;
     }
@@ -368,21 +382,31 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
     for (int c = 0; c < 16; ++c) {
         float s = 0.f;
         for (int tap = 0; tap < 27; ++tap) s += W3[c * 27 + tap] * g3s[base - tap_off(tap)];
-        g2v[c] = Bs[c * PD3 + base] > 0.f ? s : 0.f;
+        g2v[c] = Bs[c * CS + base] > 0.f ? s : 0.f;
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 16; ++c) Bs[c * PD3 + base] = g2v[c];
+    for (int c = 0; c < 16; ++c) Bs[c * CS + base] = g2v[c];
     __syncthreads();
-    // dW2[o][c][tap] = sum_pos g2[o][pos] Y1[c][pos+tap]
-    for (int w = p; w < 16 * 16 * 27; w += 512) {
-        const int o = w / (16 * 27), c = (w / 27) % 16, off = tap_off(w % 27);
-        float s = 0.f;
-        for (int q = 0; q < P3; ++q) {
-            const int b = pidx(q >> 6, (q >> 3) & 7, q & 7);
-            s += Bs[o * PD3 + b] * Y1s[c * PD3 + b + off];
+    // dW2[o][c][tap] = sum_pos g2[o][pos] Y1[c][pos+tap] on the FP32 matrix
+    // cores: per tap a 16 x 16 x 512 product, 128 16x16x4 MFMAs (A = g2:
+    // row o, K = position; B = the shifted Y1: K = position, column c); wave
+    // w takes taps w, w + 8, ... (the per-weight loop over 512 positions it
+    // replaces issued 13,824 LDS reads per thread)
+    {
+        const int lane = p & 63, wave = p >> 6, n16 = lane & 15, kq = lane >> 4;
+        for (int tap = wave; tap < 27; tap += 8) {
+            const int off = tap_off(tap);
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+            for (int st = 0; st < 128; ++st) {
+                const int pos = 4 * st + kq;
+                const int b = pidx(pos >> 6, (pos >> 3) & 7, pos & 7);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Bs[n16 * CS + b], Y1s[n16 * CS + b + off], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dWe[kW1 + ((4 * kq + q) * 16 + n16) * 27 + tap] = acc[q];
         }
-        dWe[kW1 + w] = s;
     }
     // g1[c][pos] = (sum_o sum_tap W2[o][c][tap] g2[o][pos - tap]) * (Y1 > 0)
     float g1v[16];
@@ -390,15 +414,15 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
     for (int c = 0; c < 16; ++c) g1v[c] = 0.f;
     for (int o = 0; o < 16; ++o)
         for (int tap = 0; tap < 27; ++tap) {
-            const float gv = Bs[o * PD3 + base - tap_off(tap)];
+            const float gv = Bs[o * CS + base - tap_off(tap)];
 #pragma unroll
             for (int c = 0; c < 16; ++c) g1v[c] += W2u[(o * 27 + tap) * 16 + c] * gv;
         }
 #pragma unroll
-    for (int c = 0; c < 16; ++c) g1v[c] = Y1s[c * PD3 + base] > 0.f ? g1v[c] : 0.f;
+    for (int c = 0; c < 16; ++c) g1v[c] = Y1s[c * CS + base] > 0.f ? g1v[c] : 0.f;
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 16; ++c) Bs[c * PD3 + base] = g1v[c];
+    for (int c = 0; c < 16; ++c) Bs[c * CS + base] = g1v[c];
     __syncthreads();
     // dW1[o][c][tap] = sum_pos g1[o][pos] X[c][pos+tap]
     for (int w = p; w < kW1; w += 512) {
@@ -406,7 +430,7 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
         float s = 0.f;
         for (int q = 0; q < P3; ++q) {
             const int b = pidx(q >> 6, (q >> 3) & 7, q & 7);
-            s += Bs[o * PD3 + b] * Xs[c * PD3 + b + off];
+            s += Bs[o * CS + b] * Xs[c * PD3 + b + off];
         }
         dWe[w] = s;
     }
@@ -416,16 +440,17 @@ train_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const doub
 template <typename TR>
 __global__ void __launch_bounds__(512)
 infer32_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L, const float *__restrict__ W1t,
-               const float *__restrict__ W2t, const float *__restrict__ W3, float *__restrict__ c_out)
+               const float *__restrict__ W2t, const float *__restrict__ W3, float *__restrict__ c_out,
+               float *__restrict__ act)
 {
     __shared__ float Xs[2 * PD3];
-    __shared__ float Y1s[16 * PD3];
-    __shared__ float Y2s[16 * PD3];
+    __shared__ float Y1s[16 * CS];
+    __shared__ float Y2s[16 * CS];
     __shared__ float red[8];
     const int p = threadIdx.x;
     const int64_t e = xcd_block();
     for (int q = p; q < 2 * PD3; q += 512) Xs[q] = 0.f;
-    for (int q = p; q < 16 * PD3; q += 512) { Y1s[q] = 0.f; Y2s[q] = 0.f; }
+    for (int q = p; q < 16 * CS; q += 512) { Y1s[q] = 0.f; Y2s[q] = 0.f; }
     float t;
     bool live;
     __syncthreads();
@@ -437,6 +462,15 @@ infer32_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice 
     __syncthreads();
     const float y = fwd32(W1t, W2t, W3, Xs, Y1s, Y2s);
     c_out[e * P3 + p] = t * y;
+    if (act) {   // Y1 and Y2 at this thread's position, for the training kernel
+        const int base = pidx(p >> 6, (p >> 3) & 7, p & 7);
+        float *a = act + e * (32 * P3);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            a[c * P3 + p] = Y1s[c * CS + base];
+            a[(16 + c) * P3 + p] = Y2s[c * CS + base];
+        }
+    }
 }
 
 // Weight gradient summed over elements in two fixed-order stages: stage 1
@@ -564,10 +598,10 @@ hipError_t nn_assemble_z(const Mesh &m, const TR *rg, const TR *dinvg, const flo
 }
 
 hipError_t nn_grad(const Smoother &sm, const Mesh &m, const double *rg, const double *dinvg, const double *gz,
-                   float *dW_elem, double scale, float *grad, hipStream_t s)
+                   float *dW_elem, double scale, float *grad, hipStream_t s, const float *act)
 {
     hipLaunchKernelGGL((nn::train_kernel<double>), dim3((unsigned)m.E), dim3(512), 0, s, rg, dinvg, gz, m.lat, sm.Wt,
-                       sm.Wt + kW1, sm.W + kW1 + kW2, sm.Wt + kW1 + kW2, dW_elem);
+                       sm.Wt + kW1, sm.W + kW1 + kW2, sm.Wt + kW1 + kW2, dW_elem, act);
     hipLaunchKernelGGL(nn::grad_chunks_kernel, dim3((kParams + 255) / 256, kGradChunks), dim3(256), 0, s, dW_elem,
                        m.E, sm.gpart);
     hipLaunchKernelGGL(nn::grad_finish_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, sm.gpart, scale, grad);
@@ -595,10 +629,10 @@ hipError_t nn_pack(Smoother &sm, hipStream_t s)
 }
 
 hipError_t nn_infer32(const Smoother &sm, const Mesh &m, const double *rg, const double *dinvg, float *c_local,
-                      hipStream_t s)
+                      hipStream_t s, float *act)
 {
     hipLaunchKernelGGL((nn::infer32_kernel<double>), dim3((unsigned)m.E), dim3(512), 0, s, rg, dinvg, m.lat, sm.Wt,
-                       sm.Wt + kW1, sm.W + kW1 + kW2, c_local);
+                       sm.Wt + kW1, sm.W + kW1 + kW2, c_local, act);
     return hipGetLastError();
 }
 

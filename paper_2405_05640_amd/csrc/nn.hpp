@@ -25,6 +25,7 @@ struct Smoother {
     float *Wt = nullptr;            // FP32 weights in the training loops' layouts (kWtFloats)
     float *dW_elem = nullptr;       // [E][kParams] per-element gradients
     double *gpart = nullptr;        // [kGradChunks][kParams] chunk sums of the gradient
+    float *act = nullptr;           // [E][32][512] forward activations (Y1, Y2) kept from the loss for the backward
     float *c_local = nullptr;       // [nl] element outputs
     double *buf = nullptr;          // training vectors: e, r, z, d, sd (5 x ng), w (nl)
     double *part = nullptr;         // partial sums (2 x part_capacity)
@@ -75,11 +76,13 @@ template <typename TR>
 hipError_t nn_assemble_z(const Mesh &m, const TR *rg, const TR *dinvg, const float *c_local, TR *z, hipStream_t s,
                          const int32_t *use_c, const TR *zp = nullptr);
 hipError_t nn_grad(const Smoother &sm, const Mesh &m, const double *rg, const double *dinvg, const double *gz,
-                   float *dW_elem, double scale, float *grad, hipStream_t s);
+                   float *dW_elem, double scale, float *grad, hipStream_t s,
+                   const float *act = nullptr);
 hipError_t nn_adam(Smoother &sm, const float *grad, hipStream_t s);
 hipError_t nn_pack(Smoother &sm, hipStream_t s);
 hipError_t nn_infer32(const Smoother &sm, const Mesh &m, const double *rg, const double *dinvg, float *c_local,
-                      hipStream_t s);
+                      hipStream_t s,
+                      float *act = nullptr);
 
 }  // namespace sem
 
