@@ -164,3 +164,36 @@ def test_gmres_hsmg_edge_cases_and_checks():
     with pytest.raises(sem.SemError):
         sem.Mesh.from_spec(wl.random_deformed_box(1, 2, 2, 5, seed=1, amp=0.0, periodic=(1, 0, 0)),
                            prepare=sem.SEM_PREP_HSMG)
+
+
+@pytest.mark.parametrize("spec", [
+    # 261 coarse planes along z (more than one workgroup's 256 threads) and a
+    # 67 x 67 coarse plane (more than the 4,352 nodes a plane kernel holds in
+    # LDS): both take the six single-axis coarse passes
+    wl.box(2, 2, 260, 3, extent=(1.0, 1.0, 130.0), dirichlet=0x01 | 0x04 | 0x10 | 0x20),
+    wl.box(66, 66, 1, 3, extent=(66.0, 66.0, 1.0), dirichlet=0x0F),
+], ids=["column_2x2x260_N3", "plate_66x66x1_N3"])
+def test_coarse_solve_without_plane_kernels(spec):
+    import torch
+    print("mesh", spec.name, flush=True)
+    om, gm = pair(spec, prepare=sem.SEM_PREP_HSMG)
+    pc = hsmg.HSMG(om)
+    rng = np.random.default_rng(17)
+    r = brute.continuous_random(om, rng)
+    z = torch.empty(gm.shape, dtype=torch.float64, device="cuda")
+    for kind, sym in ((sem.PRECOND_HSMG, False), (sem.PRECOND_HSMG_SYM, True)):
+        ref = pc.apply(r, 1.0, 0.0, sym=sym)
+        gm.precond(dev(r), z, kind=kind)
+        err = np.max(np.abs(host(z) - ref)) / np.max(np.abs(ref))
+        print("%s kind %d: max relative difference %.2e" % (spec.name, kind, err))
+        assert err <= 1e-10
+    b = om.rhs(rng.standard_normal(om.shape))
+    xo, info = hsmg.pcg(om, b, lambda q: pc.apply(q, sym=True), tol=1e-10)
+    x = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
+    rep = gm.pcg_solve(dev(b), x, rel_tol=1e-10, form=sem.FORM_PCG_HSMG)
+    res = b - om.apply_S(host(x))
+    true_rel = np.sqrt(om.dot(res, res) / om.dot(b, b))
+    print("%s: CG + symmetric HSMG %d iterations (oracle %d), true rel res %.2e" %
+          (spec.name, rep.iterations, info["iterations"], true_rel))
+    assert true_rel <= 1.05e-10
+    assert abs(rep.iterations - info["iterations"]) <= max(1, info["iterations"] // 20)
