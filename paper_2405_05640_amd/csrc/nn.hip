@@ -124,6 +124,42 @@ constexpr int YS = 24;
 //   layer 1 [o][k], k = 27 c + tap (k = 54..63 zero)
 constexpr int kW2B = 28 * 256, kW3B = 28 * 16, kW1B = 16 * 64;
 
+// Point (i + 8 j + 64 k) of MFMA row pos of the inference tiles.  A block of
+// 16 rows is i = 0..7 on two lines j0 and j0 + 4 of one k-plane (not two
+// adjacent lines): with the 48-byte pitch, the 16 operand reads of a lane
+// group then cover 64 distinct banks, where lines j0 and j0 + 1 overlap on
+// two rows.
+__device__ __forceinline__ int row_point(int pos)
+{
+    const int bl = pos >> 4, m = pos & 15;
+    return (m & 7) + 8 * ((bl & 3) + 4 * (m >> 3)) + 64 * (bl >> 2);
+}
+__device__ __forceinline__ int row_pidx(int pos)
+{
+    const int pt = row_point(pos);
+    return pidx(pt >> 6, (pt >> 3) & 7, pt & 7);
+}
+
+// Padded-tile index of halo position h (0..487): the k = 0 and k = 9 planes,
+// then per interior plane the j = 0 and j = 9 lines and the i = 0, 9 ends of
+// the interior lines.
+constexpr int kHalo = PD3 - P3;
+__device__ __forceinline__ int halo_index(int h)
+{
+    if (h < PD * PD) return h;
+    if (h < 2 * PD * PD) return (PD - 1) * PD * PD + (h - PD * PD);
+    const int q = h - 2 * PD * PD, k = 1 + q / 36, r = q % 36;
+    int j, i;
+    if (r < PD) {
+        j = 0; i = r;
+    } else if (r < 2 * PD) {
+        j = PD - 1; i = r - PD;
+    } else {
+        j = 1 + ((r - 2 * PD) >> 1); i = ((r - 2 * PD) & 1) * (PD - 1);
+    }
+    return (k * PD + j) * PD + i;
+}
+
 // Activation store from an MFMA C tile (lane (kq, n): rows 4 kq + q, column
 // n = channel): each even lane packs channels (n, n + 1) of rows q = 0, 1,
 // each odd lane channels (n - 1, n) of rows q = 2, 3, so every store is one
@@ -138,8 +174,7 @@ __device__ __forceinline__ void store_tile(unsigned short *Ys, const f4 &acc, in
     for (int h = 0; h < 2; ++h) {
         const int q = odd ? 2 + h : h;
         const float own = fmaxf(acc[q], 0.f), other = fmaxf(x[q], 0.f);
-        const int pos = row0 + 4 * kq + q;
-        const int at = pidx(pos >> 6, (pos >> 3) & 7, pos & 7) * YS + (n16 & ~1);
+        const int at = row_pidx(row0 + 4 * kq + q) * YS + (n16 & ~1);
         *(unsigned *)&Ys[at] = odd ? pack_bf16(other, own) : pack_bf16(own, other);
     }
 }
@@ -175,8 +210,16 @@ infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L,
     __shared__ float red[8];
     const int p = threadIdx.x;
     const int64_t e = xcd_block();
-    for (int q = p; q < 2 * PD3; q += 512) Xs[q] = 0.f;
-    for (int q = p; q < PD3 * YS / 2; q += 512) ((unsigned *)Ys)[q] = 0u;
+    // zero halo (the interior is written before it is read: features by
+    // load_features, every activation channel by store_tile)
+    if (p < kHalo) {
+        const int h = halo_index(p);
+        Xs[h] = 0.f;
+        Xs[PD3 + h] = 0.f;
+        u32x4 *y = (u32x4 *)&Ys[h * YS];   // channels 0..15 (the 8 padding halfwords are never read)
+        y[0] = u32x4{0u, 0u, 0u, 0u};
+        y[1] = u32x4{0u, 0u, 0u, 0u};
+    }
     float t;
     bool live;
     __syncthreads();
@@ -193,10 +236,7 @@ infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L,
     const unsigned short *W2b = Wb, *W3b = Wb + kW2B, *W1b = Wb + kW2B + kW3B;
     int pb[4];   // padded-tile index of this lane's A row in each block
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int pos = (wave * 4 + b) * 16 + n16;
-        pb[b] = pidx(pos >> 6, (pos >> 3) & 7, pos & 7);
-    }
+    for (int b = 0; b < 4; ++b) pb[b] = row_pidx((wave * 4 + b) * 16 + n16);
     // layer 1: 2 -> 16, K = (channel, tap) = 54 terms padded to 64, two
     // 16x16x32 BF16 MFMAs per block; the lane's 16 K offsets are fixed
     // (tap offsets can be negative: the padding terms carry kNoTap)
@@ -264,7 +304,7 @@ infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L,
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Xs[(wave * 4 + b) * 16 + 4 * g + q] = acc[b][q];
+            for (int q = 0; q < 4; ++q) Xs[row_point((wave * 4 + b) * 16 + 4 * g + q)] = acc[b][q];
     }
     __syncthreads();
     c_out[e * P3 + p] = t * Xs[p];
