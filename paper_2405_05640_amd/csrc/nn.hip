@@ -74,11 +74,12 @@ __device__ float block_max512(float v, float *red)
     return m;
 }
 
-// Features of element e from assembled r and dinv: Xs[2][PD3] (zero halo
-// must already be in place).  Returns t_e and whether the element is live.
+// The two features at this thread's point of element e from assembled r and
+// dinv (r / max|r| and dinv r / max|dinv r| over the element), t_e, and
+// whether the element is live (both maxima positive).
 template <typename TR>
-__device__ void load_features(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const Lattice &L,
-                              int64_t e, float *Xs, float *red, float &t_out, bool &live)
+__device__ void feature_values(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const Lattice &L, int64_t e,
+                               float *red, float &x0, float &x1, float &t_out, bool &live)
 {
     const int p = threadIdx.x, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
     const int64_t g = lattice_glo(L, e, i, j, k);
@@ -87,11 +88,23 @@ __device__ void load_features(const TR *__restrict__ rg, const TR *__restrict__ 
     const float s = block_max512((float)fabs(r), red);
     const float t = block_max512((float)fabs(q), red);
     live = (s > 0.f) && (t > 0.f);
-    if (live) {
-        Xs[pidx(k, j, i)] = (float)(r / (double)s);
-        Xs[PD3 + pidx(k, j, i)] = (float)(q / (double)t);
-    }
+    x0 = live ? (float)(r / (double)s) : 0.f;
+    x1 = live ? (float)(q / (double)t) : 0.f;
     t_out = t;
+}
+
+// Features of element e into Xs[2][PD3] (zero halo must already be in place).
+template <typename TR>
+__device__ void load_features(const TR *__restrict__ rg, const TR *__restrict__ dinvg, const Lattice &L,
+                              int64_t e, float *Xs, float *red, float &t_out, bool &live)
+{
+    const int p = threadIdx.x, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
+    float x0, x1;
+    feature_values(rg, dinvg, L, e, red, x0, x1, t_out, live);
+    if (live) {
+        Xs[pidx(k, j, i)] = x0;
+        Xs[PD3 + pidx(k, j, i)] = x1;
+    }
 }
 
 __device__ __forceinline__ int tap_off(int tap)
@@ -121,7 +134,7 @@ __device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
 constexpr int YS = 24;
 // matrix-core weight operands (BF16, built from the FP32 master weights):
 //   layer 2 [tap 0..27][o][c] (tap 27 zero), layer 3 [tap 0..27][c],
-//   layer 1 [o][k], k = 27 c + tap (k = 54..63 zero)
+//   layer 1 [o][k], k = 2 tap + c (k = 54..63 zero)
 constexpr int kW2B = 28 * 256, kW3B = 28 * 16, kW1B = 16 * 64;
 
 // Point (i + 8 j + 64 k) of MFMA row pos of the inference tiles.  A block of
@@ -205,29 +218,30 @@ infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L,
              float *__restrict__ c_out, const int32_t *__restrict__ skip)
 {
     if (skip && *skip) return;
-    __shared__ float Xs[2 * PD3];
+    // features as BF16 pairs (x0 in the low half), one word per position
+    __shared__ unsigned Xp[PD3];
     __shared__ __attribute__((aligned(16))) unsigned short Ys[PD3 * YS];
     __shared__ float red[8];
     const int p = threadIdx.x;
     const int64_t e = xcd_block();
-    // zero halo (the interior is written before it is read: features by
-    // load_features, every activation channel by store_tile)
+    // zero halo (the interior is written before it is read: features here,
+    // every activation channel by store_tile)
     if (p < kHalo) {
         const int h = halo_index(p);
-        Xs[h] = 0.f;
-        Xs[PD3 + h] = 0.f;
+        Xp[h] = 0u;
         u32x4 *y = (u32x4 *)&Ys[h * YS];   // channels 0..15 (the 8 padding halfwords are never read)
         y[0] = u32x4{0u, 0u, 0u, 0u};
         y[1] = u32x4{0u, 0u, 0u, 0u};
     }
-    float t;
+    float t, x0, x1;
     bool live;
     __syncthreads();
-    load_features(rg, dinvg, L, e, Xs, red, t, live);
+    feature_values(rg, dinvg, L, e, red, x0, x1, t, live);
     if (!live) {   // uniform across the block
         c_out[e * P3 + p] = 0.f;
         return;
     }
+    Xp[pidx(p >> 6, (p >> 3) & 7, p & 7)] = pack_bf16(x0, x1);
     __syncthreads();
     // Each wavefront owns four blocks of 16 positions (rows of the MFMA
     // tiles); lane = (g, n): A row / C column n = lane & 15, K group g.
@@ -237,17 +251,16 @@ infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L,
     int pb[4];   // padded-tile index of this lane's A row in each block
 #pragma unroll
     for (int b = 0; b < 4; ++b) pb[b] = row_pidx((wave * 4 + b) * 16 + n16);
-    // layer 1: 2 -> 16, K = (channel, tap) = 54 terms padded to 64, two
-    // 16x16x32 BF16 MFMAs per block; the lane's 16 K offsets are fixed
-    // (tap offsets can be negative: the padding terms carry kNoTap)
+    // layer 1: 2 -> 16, K = (tap, channel) = 54 terms padded to 64, two
+    // 16x16x32 BF16 MFMAs per block: the lane's K entries 8 g .. 8 g + 7 of
+    // step st are taps 16 st + 4 g + h (h < 4), each one feature word.  The
+    // padding taps (27..31) read tap 0 again; their weights are zero.
     {
-        constexpr int kNoTap = -(1 << 20);
-        int koff[16];
+        int koff[8];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int k = 32 * (j >> 3) + 8 * g + (j & 7);
-            const int c = k / 27, tap = k - 27 * c;
-            koff[j] = k < 54 ? c * PD3 + tap_off(tap) : kNoTap;
+        for (int q = 0; q < 8; ++q) {
+            const int tap = 16 * (q >> 2) + 4 * g + (q & 3);
+            koff[q] = tap_off(tap < 27 ? tap : 0);
         }
         f4 acc[4];
 #pragma unroll
@@ -259,10 +272,7 @@ infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L,
             for (int b = 0; b < 4; ++b) {
                 unsigned w[4];
 #pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    const int o0 = koff[8 * st + 2 * h], o1 = koff[8 * st + 2 * h + 1];
-                    w[h] = pack_bf16(o0 != kNoTap ? Xs[pb[b] + o0] : 0.f, o1 != kNoTap ? Xs[pb[b] + o1] : 0.f);
-                }
+                for (int h = 0; h < 4; ++h) w[h] = Xp[pb[b] + koff[4 * st + h]];
                 const bf16x8 aop = __builtin_bit_cast(bf16x8, (u32x4){w[0], w[1], w[2], w[3]});
                 acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc[b], 0, 0, 0);
             }
@@ -298,16 +308,17 @@ infer_kernel(const TR *__restrict__ rg, const TR *__restrict__ dinvg, Lattice L,
         for (int b = 0; b < 4; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
         conv16(Ys, pb, g, bop, acc);
     }
-    // column 0 lives in lanes n16 == 0; stage through LDS (Xs is free) so
-    // that the output store is coalesced
+    // column 0 lives in lanes n16 == 0; stage through LDS (the feature tile
+    // is free) so that the output store is coalesced
+    float *Xo = (float *)Xp;
     if (n16 == 0) {
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Xs[row_point((wave * 4 + b) * 16 + 4 * g + q)] = acc[b][q];
+            for (int q = 0; q < 4; ++q) Xo[row_point((wave * 4 + b) * 16 + 4 * g + q)] = acc[b][q];
     }
     __syncthreads();
-    c_out[e * P3 + p] = t * Xs[p];
+    c_out[e * P3 + p] = t * Xo[p];
 }
 
 // ---------------------------------------------------------------- training (FP32)
@@ -567,7 +578,7 @@ __global__ void pack_w2_kernel(const float *__restrict__ W, unsigned short *__re
         Wb[w] = tap < 27 ? f2bf(W[kW1 + kW2 + c * 27 + tap]) : 0;
     } else if (w < kW2B + kW3B + kW1B) {
         const int v = w - kW2B - kW3B, o = v / 64, k = v % 64;
-        Wb[w] = k < 54 ? f2bf(W[o * 54 + k]) : 0;
+        Wb[w] = k < 54 ? f2bf(W[o * 54 + 27 * (k & 1) + (k >> 1)]) : 0;
     }
 }
 
