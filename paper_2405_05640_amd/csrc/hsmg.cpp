@@ -290,6 +290,15 @@ sem_status hsmg_setup(const sem_mesh_desc &ds, Mesh &m)
         SEM_TRY(put(&h->d_clam[d], lam, acc));
     }
     h->bytes = acc;
+    if (hipHostMalloc((void **)&h->h_flag, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        h->h_flag = nullptr;
+        return fail(SEM_ERR_OUT_OF_MEMORY, "pinned host flag of the GMRES solve");
+    }
+    for (hipEvent_t &e : h->ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            e = nullptr;
+            return fail(SEM_ERR_HIP, "event creation for the GMRES solve");
+        }
     return SEM_OK;
 }
 
@@ -301,6 +310,9 @@ void hsmg_release(Mesh &m)
                     h->d_clam[0], h->d_clam[1], h->d_clam[2]};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (h->h_flag) (void)hipHostFree(h->h_flag);
+    for (hipEvent_t e : h->ev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
     m.hsmg = nullptr;
 }

@@ -44,6 +44,22 @@
 #include "reduce.hpp"
 
 namespace sem {
+
+// Device-resident state of one GMRES restart cycle: the Hessenberg matrix
+// (row-major, row stride kGmresMaxRestart), the Givens rotations, the
+// rotated right-hand side g, |g[j+1]| after each step, the coefficients the
+// normalisation subtracts, and the flags the skipping kernels read.
+struct GmresDev {
+    double H[(kGmresMaxRestart + 1) * kGmresMaxRestart];
+    double cs[kGmresMaxRestart], sn[kGmresMaxRestart], g[kGmresMaxRestart + 1];
+    double res[kGmresMaxRestart];
+    double coef[kGmresMaxRestart + 2];
+    double beta2, inv_bj, tol_abs;
+    int skip_re;   // no second Gram-Schmidt pass in this step (or stopped)
+    int stop;      // 0 running; 1 converged, at max_it or lucky breakdown; 2 non-finite
+    int k, it, max_it, pad;
+};
+
 namespace mg {
 
 #define GRID_STRIDE(g, n) for (int64_t g = (int64_t)blockIdx.x * kBS + threadIdx.x; g < (n); g += (int64_t)gridDim.x * kBS)
@@ -693,8 +709,10 @@ dots_kernel(const double *__restrict__ w, const double *__restrict__ V, int64_t 
 }
 
 // h[q] = sum of stage[q * kStage ...] for q < nv
-__global__ void __launch_bounds__(kBS) sums_finalize(const double *__restrict__ stage, int nv, double *__restrict__ h)
+__global__ void __launch_bounds__(kBS) sums_finalize(const double *__restrict__ stage, int nv, double *__restrict__ h,
+                                                     const int *__restrict__ skip = nullptr)
 {
+    if (skip && *skip) return;   // uniform across the block
     for (int q = 0; q < nv; ++q) {
         __shared__ double red[kBS];
         red[threadIdx.x] = stage[q * kStage + threadIdx.x];
@@ -708,11 +726,13 @@ __global__ void __launch_bounds__(kBS) sums_finalize(const double *__restrict__ 
     }
 }
 
-// w = (w - sum_{i <= j} h_i V_i) * scale
+// w = (w - sum_{i <= j} h_i V_i) * scale (scale from device memory)
 __global__ void __launch_bounds__(kBS)
 orth_kernel(double *__restrict__ w, const double *__restrict__ V, int64_t ng, int j, const double *__restrict__ h,
-            double scale)
+            const double *__restrict__ scale_p, const int *__restrict__ skip)
 {
+    if (*skip) return;   // uniform across the grid
+    const double scale = *scale_p;
     double hq[kMaxDots];
 #pragma unroll
     for (int q = 0; q < kMaxDots - 1; ++q) hq[q] = q <= j ? h[q] : 0.0;
@@ -731,8 +751,9 @@ orth_kernel(double *__restrict__ w, const double *__restrict__ V, int64_t ng, in
 // with the second pass's inner products from the same read of V
 __global__ void __launch_bounds__(kBS)
 orth_dots_kernel(double *__restrict__ w, const double *__restrict__ V, int64_t ng, int j, const double *__restrict__ h,
-                 double *__restrict__ part)
+                 double *__restrict__ part, const int *__restrict__ skip)
 {
+    if (*skip) return;   // uniform across the grid
     double hq[kMaxDots - 1], acc[kMaxDots];
 #pragma unroll
     for (int q = 0; q < kMaxDots - 1; ++q) hq[q] = q <= j ? h[q] : 0.0;
@@ -781,6 +802,86 @@ __global__ void __launch_bounds__(kBS) scale_kernel(const double *__restrict__ i
                                                     double s)
 {
     GRID_STRIDE(g, ng) out[g] = in[g] * s;
+}
+
+// GMRES cycle start: g = (beta, 0, ...), flags cleared
+__global__ void gmres_start_kernel(GmresDev *d, double beta, double tol_abs, int it, int max_it)
+{
+    if (threadIdx.x != 0) return;
+    for (int q = 0; q <= kGmresMaxRestart; ++q) d->g[q] = 0.0;
+    d->g[0] = beta;
+    d->tol_abs = tol_abs;
+    d->it = it;
+    d->max_it = max_it;
+    d->k = 0;
+    d->stop = 0;
+    d->skip_re = 1;
+}
+
+// Step j, after the first pass's sums hv[0..j] = (V_i, w), hv[j+1] = (w, w):
+// column j of H, ||w - V h||^2 = (w, w) - |h|^2, and whether a second
+// classical Gram-Schmidt pass is needed ("twice is enough": the new
+// direction kept less than 1/sqrt(2) of its norm)
+__global__ void gmres_column_kernel(GmresDev *d, const double *__restrict__ hv, int j)
+{
+    if (threadIdx.x != 0) return;
+    if (d->stop) {
+        d->skip_re = 1;
+        return;
+    }
+    const double ww = hv[j + 1];
+    double hh = 0.0;
+    for (int i = 0; i <= j; ++i) {
+        d->H[i * kGmresMaxRestart + j] = hv[i];
+        d->coef[i] = hv[i];
+        hh += hv[i] * hv[i];
+    }
+    d->beta2 = ww - hh;
+    d->skip_re = d->beta2 >= 0.5 * ww ? 1 : 0;
+}
+
+// Step j, after the optional second pass (h2v as hv): the column finished,
+// the previous rotations applied to it, the new rotation, g rotated, and the
+// stop test |g[j+1]| <= tol_abs, it >= max_it or a zero new direction
+__global__ void gmres_givens_kernel(GmresDev *d, const double *__restrict__ h2v, int j)
+{
+    if (threadIdx.x != 0) return;
+    if (d->stop) return;
+    double *H = d->H;
+    auto Hs = [&](int r, int c) -> double & { return H[r * kGmresMaxRestart + c]; };
+    double beta2 = d->beta2;
+    if (!d->skip_re) {
+        double h2 = 0.0;
+        for (int i = 0; i <= j; ++i) {
+            Hs(i, j) += h2v[i];
+            d->coef[i] = h2v[i];
+            h2 += h2v[i] * h2v[i];
+        }
+        beta2 = h2v[j + 1] - h2;
+    }
+    if (!isfinite(beta2)) {
+        d->stop = 2;
+        return;
+    }
+    const double bj = beta2 > 0.0 ? sqrt(beta2) : 0.0;
+    d->inv_bj = bj > 0.0 ? 1.0 / bj : 0.0;
+    Hs(j + 1, j) = bj;
+    for (int i = 0; i < j; ++i) {
+        const double a = Hs(i, j), c = Hs(i + 1, j);
+        Hs(i, j) = d->cs[i] * a + d->sn[i] * c;
+        Hs(i + 1, j) = -d->sn[i] * a + d->cs[i] * c;
+    }
+    const double den = hypot(Hs(j, j), Hs(j + 1, j));
+    d->cs[j] = Hs(j, j) / den;
+    d->sn[j] = Hs(j + 1, j) / den;
+    Hs(j, j) = den;
+    Hs(j + 1, j) = 0.0;
+    d->g[j + 1] = -d->sn[j] * d->g[j];
+    d->g[j] = d->cs[j] * d->g[j];
+    d->res[j] = fabs(d->g[j + 1]);
+    d->it += 1;
+    d->k = j + 1;
+    if (fabs(d->g[j + 1]) <= d->tol_abs || d->it >= d->max_it || bj == 0.0) d->stop = 1;
 }
 
 // ---------------------------------------------------------------- block-Jacobi CG kernels
@@ -1164,10 +1265,19 @@ sem_status read_st(CgState &h, const CgState *d, hipStream_t s)
 }
 
 // sums of nv quantities from block partials part[q * nb + b] into host out
+// sums of nv quantities from block partials into device h (skipped when *skip)
+hipError_t reduce_to_dev(const double *part, int nb, int nv, double *stage, double *h, const int *skip, hipStream_t s)
+{
+    hipError_t e = cg_reduce(part, nb, nv, stage, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mg::sums_finalize, dim3(1), dim3(kBS), 0, s, stage, nv, h, skip);
+    return hipGetLastError();
+}
+
 sem_status reduce_to_host(const double *part, int nb, int nv, double *stage, double *hdev, double *out, hipStream_t s)
 {
     SEM_HIP_TRY(cg_reduce(part, nb, nv, stage, s));
-    hipLaunchKernelGGL(mg::sums_finalize, dim3(1), dim3(kBS), 0, s, stage, nv, hdev);
+    hipLaunchKernelGGL(mg::sums_finalize, dim3(1), dim3(kBS), 0, s, stage, nv, hdev, nullptr);
     SEM_HIP_TRY(hipGetLastError());
     SEM_HIP_TRY(hipMemcpyAsync(out, hdev, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
     SEM_HIP_TRY(hipStreamSynchronize(s));
@@ -1188,7 +1298,7 @@ size_t gmres_bufs_bytes(const Mesh &m, int mres)
     const size_t ng = (size_t)m.ng;
     const size_t nb = (size_t)std::max<int64_t>(node_grid(m.lat), cg_blocks(m.ng));
     return a((size_t)(mres + 1) * ng * 8) + a((size_t)mres * ng * 8) + a(nb * mg::kMaxDots * 8) +
-           a((size_t)mg::kMaxDots * kStage * 8) + 2 * a(mg::kMaxDots * 8) + hsmg_bufs_bytes(m);
+           a((size_t)mg::kMaxDots * kStage * 8) + 3 * a(mg::kMaxDots * 8) + a(sizeof(GmresDev)) + hsmg_bufs_bytes(m);
 }
 
 GmresBufs gmres_bufs_carve(const Mesh &m, int mres, char *base)
@@ -1208,7 +1318,9 @@ GmresBufs gmres_bufs_carve(const Mesh &m, int mres, char *base)
     g.part = (double *)take(nb * mg::kMaxDots * 8);
     g.stage = (double *)take((size_t)mg::kMaxDots * kStage * 8);
     g.hdev = (double *)take(mg::kMaxDots * 8);
+    g.h2dev = (double *)take(mg::kMaxDots * 8);
     g.ydev = (double *)take(mg::kMaxDots * 8);
+    g.gd = (GmresDev *)take(sizeof(GmresDev));
     g.hb = hsmg_bufs_carve(m, base + off);
     return g;
 }
@@ -1221,9 +1333,8 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
     const int64_t ng = m.ng;
     const int nbf = cg_blocks(ng);
     const int nbd = (int)((node_grid(m.lat) + mg::kDotRows - 1) / mg::kDotRows);
-    double hv[mg::kMaxDots], h2v[mg::kMaxDots];
-    std::vector<double> H((size_t)(mres + 1) * mres), cs(mres), sn(mres), g(mres + 1), y(mres);
-    auto Hs = [&](int r, int c) -> double & { return H[(size_t)r * mres + c]; };
+    double hv[mg::kMaxDots];
+    std::vector<double> y(mres);
     h = CgState{};
     h.max_it = o.max_iter;
     // x = 0, r = b, |b|
@@ -1246,12 +1357,18 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
     const double bn = std::sqrt(h.bb), tol_abs = o.rel_tol * bn;
     double beta = bn;
     int it = 0, restarts = 0;
+    const Hsmg &hs = *m.hsmg;
+    GmresDev gh;   // host copy of the cycle's device state
     for (;;) {
         hipLaunchKernelGGL(mg::scale_kernel, dim3(nbf), dim3(kBS), 0, s, v.r, gb.V, ng, 1.0 / beta);
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int k = 0;
-        bool stop = false;
+        hipLaunchKernelGGL(mg::gmres_start_kernel, dim3(1), dim3(64), 0, s, gb.gd, beta, tol_abs, it, o.max_iter);
+        SEM_HIP_TRY(hipGetLastError());
+        // The Hessenberg column, the second-pass decision, the rotations and
+        // the stop test run on the device; kernels of a stopped cycle return
+        // at once.  The host reads step j's stop flag (copied to pinned
+        // memory) after queueing step j + 1, so the stream never drains
+        // inside a cycle; a cycle that stopped at step j has at most step
+        // j + 1 queued after it, whose state-changing kernels skip.
         for (int j = 0; j < mres; ++j) {
             double *Vj = gb.V + (size_t)j * ng, *Vn = gb.V + (size_t)(j + 1) * ng, *Zj = gb.Z + (size_t)j * ng;
             SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, Vj, Zj, gb.hb, 3, kWeightAvg, s, fine));
@@ -1263,58 +1380,40 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
                 hipLaunchKernelGGL(mg::assemble_dots_kernel<0>, dim3(nbd), dim3(kBS), 0, s, v.w, m.lat, Vn, gb.V, ng,
                                    j, gb.part);
             SEM_HIP_TRY(hipGetLastError());
-            SEM_TRY(reduce_to_host(gb.part, nbd, j + 2, gb.stage, gb.hdev, hv, s));
-            double ww = hv[j + 1], hh = 0.0;
-            for (int i = 0; i <= j; ++i) hh += hv[i] * hv[i];
-            double beta2 = ww - hh;
-            for (int i = 0; i <= j; ++i) Hs(i, j) = hv[i];
-            if (!(beta2 >= 0.5 * ww)) {
-                // second classical Gram-Schmidt pass ("twice is enough"): the
-                // new direction kept less than 1/sqrt(2) of its norm; the
-                // first update and the second pass's inner products share
-                // one read of V
-                hipLaunchKernelGGL(mg::orth_dots_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.hdev, gb.part);
-                SEM_HIP_TRY(hipGetLastError());
-                SEM_TRY(reduce_to_host(gb.part, nbf, j + 2, gb.stage, gb.hdev, h2v, s));
-                double h2 = 0.0;
-                for (int i = 0; i <= j; ++i) {
-                    Hs(i, j) += h2v[i];
-                    h2 += h2v[i] * h2v[i];
-                }
-                beta2 = h2v[j + 1] - h2;
-            }
-            if (!std::isfinite(beta2)) {
-                h.done = 2;
-                rep->iterations = it;
-                return SEM_OK;
-            }
-            const double bj = beta2 > 0.0 ? std::sqrt(beta2) : 0.0;
-            if (bj > 0.0)
-                hipLaunchKernelGGL(mg::orth_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.hdev, 1.0 / bj);
-            Hs(j + 1, j) = bj;
-            for (int i = 0; i < j; ++i) {
-                const double a = Hs(i, j), c = Hs(i + 1, j);
-                Hs(i, j) = cs[i] * a + sn[i] * c;
-                Hs(i + 1, j) = -sn[i] * a + cs[i] * c;
-            }
-            const double den = std::hypot(Hs(j, j), Hs(j + 1, j));
-            cs[j] = Hs(j, j) / den;
-            sn[j] = Hs(j + 1, j) / den;
-            Hs(j, j) = den;
-            Hs(j + 1, j) = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            ++it;
-            k = j + 1;
-            if (o.history && hist_written < o.history_len) o.history[hist_written++] = std::fabs(g[j + 1]) / bn;
-            if (std::fabs(g[j + 1]) <= tol_abs || it >= o.max_iter || bj == 0.0) {
-                stop = true;
-                break;
+            SEM_HIP_TRY(reduce_to_dev(gb.part, nbd, j + 2, gb.stage, gb.hdev, nullptr, s));
+            hipLaunchKernelGGL(mg::gmres_column_kernel, dim3(1), dim3(64), 0, s, gb.gd, gb.hdev, j);
+            // second pass: the first update and its inner products share one read of V
+            hipLaunchKernelGGL(mg::orth_dots_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.hdev, gb.part,
+                               &gb.gd->skip_re);
+            SEM_HIP_TRY(hipGetLastError());
+            SEM_HIP_TRY(reduce_to_dev(gb.part, nbf, j + 2, gb.stage, gb.h2dev, &gb.gd->skip_re, s));
+            hipLaunchKernelGGL(mg::gmres_givens_kernel, dim3(1), dim3(64), 0, s, gb.gd, gb.h2dev, j);
+            hipLaunchKernelGGL(mg::orth_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.gd->coef,
+                               &gb.gd->inv_bj, &gb.gd->stop);
+            SEM_HIP_TRY(hipGetLastError());
+            SEM_HIP_TRY(hipMemcpyAsync(hs.h_flag + (j & 1), &gb.gd->stop, sizeof(int), hipMemcpyDeviceToHost, s));
+            SEM_HIP_TRY(hipEventRecord(hs.ev[j & 1], s));
+            if (j > 0) {
+                SEM_HIP_TRY(hipEventSynchronize(hs.ev[(j - 1) & 1]));
+                if (hs.h_flag[(j - 1) & 1] != 0) break;
             }
         }
+        SEM_HIP_TRY(hipMemcpyAsync(&gh, gb.gd, sizeof(GmresDev), hipMemcpyDeviceToHost, s));
+        SEM_HIP_TRY(hipStreamSynchronize(s));
+        const int k = gh.k;
+        for (int j = 0; j < k; ++j)
+            if (o.history && hist_written < o.history_len) o.history[hist_written++] = gh.res[j] / bn;
+        it = gh.it;
+        if (gh.stop == 2) {
+            h.done = 2;
+            rep->iterations = it;
+            rep->history_written = hist_written;
+            return SEM_OK;
+        }
+        auto Hs = [&](int r, int c) -> double { return gh.H[r * kGmresMaxRestart + c]; };
         // x += Z y, y from the triangular system H y = g
         for (int i = k - 1; i >= 0; --i) {
-            double acc = g[i];
+            double acc = gh.g[i];
             for (int c = i + 1; c < k; ++c) acc -= Hs(i, c) * y[c];
             y[i] = acc / Hs(i, i);
         }
@@ -1338,7 +1437,6 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
             h.done = 3;
             break;
         }
-        (void)stop;
         ++restarts;
         beta = std::sqrt(h.true_rr);
     }

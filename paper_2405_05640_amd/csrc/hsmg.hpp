@@ -31,6 +31,11 @@ struct Hsmg {
     double *d_clam[3] = {nullptr, nullptr, nullptr};
     int cn[3] = {0, 0, 0};
     size_t bytes = 0;
+    // GMRES stop flags read one iteration behind (pinned host words, two
+    // slots) and the events that mark their copies; made at setup so that a
+    // solve allocates nothing
+    int *h_flag = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
 // host setup from the mesh description (vertices) and the built mesh
@@ -87,8 +92,10 @@ hipError_t hsmg_coarse_part(const Mesh &m, double h1, double h2, const double *r
 
 // Flexible GMRES work buffers: V [(m+1) ng], Z [m ng], block partials,
 // reduction stage, device vectors of inner products and of y.
+struct GmresDev;   // device-resident state of one restart cycle
 struct GmresBufs {
-    double *V, *Z, *part, *stage, *hdev, *ydev;
+    double *V, *Z, *part, *stage, *hdev, *h2dev, *ydev;
+    GmresDev *gd;
     HsmgBufs hb;
 };
 size_t gmres_bufs_bytes(const Mesh &m, int mres);
