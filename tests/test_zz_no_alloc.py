@@ -34,7 +34,9 @@ def _solve_both(spec, form, prepare=0, **kw):
 @pytest.mark.parametrize("form,prepare,kw", [
     (sem.FORM_JACOBI_PCG, 0, {"h2": 0.1}),
     (sem.FORM_RELIABLE_FP32, sem.SEM_PREP_F32, {"inner_tol": 0.1}),
-], ids=["fp64_pcg", "reliable_fp32"])
+    (sem.FORM_GMRES_HSMG, sem.SEM_PREP_HSMG, {"restart": 10}),
+    (sem.FORM_PCG_HSMG, sem.SEM_PREP_HSMG, {"h2": 0.1}),
+], ids=["fp64_pcg", "reliable_fp32", "gmres_hsmg", "pcg_hsmg"])
 def test_noalloc_matches_workspace_solve_twice(form, prepare, kw):
     # first a larger mesh, then a smaller one on the same scratch
     r1 = _solve_both(wl.random_deformed_box(6, 5, 4, 7, seed=3, amp=0.1), form, prepare, **kw)
