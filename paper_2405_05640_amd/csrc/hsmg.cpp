@@ -294,11 +294,15 @@ sem_status hsmg_setup(const sem_mesh_desc &ds, Mesh &m)
         h->h_flag = nullptr;
         return fail(SEM_ERR_OUT_OF_MEMORY, "pinned host flag of the GMRES solve");
     }
-    for (hipEvent_t &e : h->ev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            e = nullptr;
-            return fail(SEM_ERR_HIP, "event creation for the GMRES solve");
+    for (hipEvent_t *e : {&h->ev[0], &h->ev[1], &h->fork, &h->join})
+        if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+            *e = nullptr;
+            return fail(SEM_ERR_HIP, "event creation for the multigrid solves");
         }
+    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+        h->side = nullptr;
+        return fail(SEM_ERR_HIP, "side stream creation for the learned multigrid");
+    }
     return SEM_OK;
 }
 
@@ -311,8 +315,9 @@ void hsmg_release(Mesh &m)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->h_flag) (void)hipHostFree(h->h_flag);
-    for (hipEvent_t e : h->ev)
+    for (hipEvent_t e : {h->ev[0], h->ev[1], h->fork, h->join})
         if (e) (void)hipEventDestroy(e);
+    if (h->side) (void)hipStreamDestroy(h->side);
     delete h;
     m.hsmg = nullptr;
 }

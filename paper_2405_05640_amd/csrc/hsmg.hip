@@ -1220,6 +1220,22 @@ hipError_t hsmg_coarse_part(const Mesh &m, double h1, double h2, const double *r
     return coarser_levels(m, h1, h2, b, weight, s);
 }
 
+hipError_t hsmg_coarse_part_fork(const Mesh &m, double h1, double h2, const double *r, const HsmgBufs &b, int weight,
+                                 hipStream_t s)
+{
+    const Hsmg &h = *m.hsmg;
+    hipError_t e;
+    if ((e = hipEventRecord(h.fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(h.side, h.fork, 0)) != hipSuccess) return e;
+    if ((e = hsmg_coarse_part(m, h1, h2, r, b, weight, h.side)) != hipSuccess) return e;
+    return hipEventRecord(h.join, h.side);
+}
+
+hipError_t hsmg_coarse_part_join(const Mesh &m, hipStream_t s)
+{
+    return hipStreamWaitEvent(s, m.hsmg->join, 0);
+}
+
 hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, double *z, const HsmgBufs &b, int levels,
                       int weight, hipStream_t s, const FineHook *fine, double *part_rz)
 {
@@ -1227,11 +1243,13 @@ hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, doub
     const int sym = weight == kWeightSym ? 1 : 0;
     hipError_t e;
     if (fine) {
-        // learned multigrid: the coarser levels, then z = M_learned(r) + zp
-        if ((e = hsmg_coarse_part(m, h1, h2, r, b, weight, s)) != hipSuccess) return e;
+        // learned multigrid: the coarser levels (side stream) beside the
+        // network, then z = M_learned(r) + zp
+        if ((e = hsmg_coarse_part_fork(m, h1, h2, r, b, weight, s)) != hipSuccess) return e;
         e = fine->fp32 ? nn_infer32(*fine->sm, m, r, fine->dinv, fine->c_local, s)
                        : nn_infer<double>(*fine->sm, m, r, fine->dinv, fine->c_local, s, nullptr);
         if (e != hipSuccess) return e;
+        if ((e = hsmg_coarse_part_join(m, s)) != hipSuccess) return e;
         return nn_assemble_z<double>(m, r, fine->dinv, fine->c_local, z, s, nullptr, b.zp);
     }
     if (levels == 1) {

@@ -36,6 +36,10 @@ struct Hsmg {
     // solve allocates nothing
     int *h_flag = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // side stream (default priority) on which the learned multigrid's
+    // coarser levels run beside the network, and its fork / join events
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 // host setup from the mesh description (vertices) and the built mesh
@@ -87,6 +91,12 @@ hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, doub
 
 // The mid and coarse levels' part alone: b.zp = P_01 [Sw_1(R_10 r) +
 // P_12 C^-1 R_21 R_10 r] (what the cycle adds to its fine level).
+// The coarser-level part queued on the mesh's side stream after the work
+// queued so far on s (fork), and s made to wait for it (join): the learned
+// multigrid's network and coarser levels are independent terms of z.
+hipError_t hsmg_coarse_part_fork(const Mesh &m, double h1, double h2, const double *r, const HsmgBufs &b, int weight,
+                                 hipStream_t s);
+hipError_t hsmg_coarse_part_join(const Mesh &m, hipStream_t s);
 hipError_t hsmg_coarse_part(const Mesh &m, double h1, double h2, const double *r, const HsmgBufs &b, int weight,
                             hipStream_t s);
 

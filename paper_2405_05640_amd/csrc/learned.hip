@@ -414,12 +414,18 @@ sem_status check_pair(const Smoother &sm, const Mesh &m)
     return SEM_OK;
 }
 
-// the learned multigrid's coarser-level part of r into mg->zp (queued; mg
-// null: plain learned smoother)
+// the learned multigrid's coarser-level part of r into mg->zp, queued on the
+// mesh's side stream so that it runs beside the network (mg null: plain
+// learned smoother); fcg_join makes s wait for it before z is formed
 static sem_status fcg_coarse(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const HsmgBufs *mg,
                              hipStream_t s)
 {
-    if (mg) SEM_HIP_TRY(hsmg_coarse_part(m, o.h1, o.h2, v.r, *mg, kWeightAvg, s));
+    if (mg) SEM_HIP_TRY(hsmg_coarse_part_fork(m, o.h1, o.h2, v.r, *mg, kWeightAvg, s));
+    return SEM_OK;
+}
+static sem_status fcg_join(const Mesh &m, const HsmgBufs *mg, hipStream_t s)
+{
+    if (mg) SEM_HIP_TRY(hsmg_coarse_part_join(m, s));
     return SEM_OK;
 }
 
@@ -431,6 +437,7 @@ static sem_status fcg_direction(const Mesh &m, const sem_solve_opts &o, const Sm
     const int nbn = node_blocks(m);
     SEM_TRY(fcg_coarse(m, o, v, mg, s));
     SEM_HIP_TRY(nn_infer<double>(sm, m, v.r, v.dinv, sm.c_local, s, &st->nn_skip));
+    SEM_TRY(fcg_join(m, mg, s));
     hipLaunchKernelGGL(lk::fcg_z_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.r, v.dinv, sm.c_local,
                        (const double *)nullptr, z, m.lat, v.part_b, mg ? (const double *)mg->zp : nullptr);
     SEM_HIP_TRY(cg_reduce(v.part_b, nbn, 2, v.stage, s));
@@ -472,6 +479,7 @@ sem_status solve_fcg(const Mesh &m, const Smoother &sm, const sem_solve_opts &o,
                                    sm.stall_window, sm.stall_rate);
                 SEM_TRY(fcg_coarse(m, o, v, mg, s));
                 SEM_HIP_TRY(nn_infer<double>(sm, m, v.r, v.dinv, sm.c_local, s, &st->nn_skip));
+                SEM_TRY(fcg_join(m, mg, s));
                 hipLaunchKernelGGL(lk::fcg_z_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.r, v.dinv, sm.c_local,
                                    (const double *)q, z, m.lat, v.part_b, mg ? (const double *)mg->zp : nullptr);
                 SEM_HIP_TRY(cg_reduce(v.part_b, nbn, 2, v.stage, s));
