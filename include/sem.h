@@ -372,17 +372,20 @@ sem_status sem_pcg_snapshots(const sem_mesh *mesh, const sem_solve_opts *opts, c
                              const int32_t *iters, int32_t n_iters, double *e_out, void *workspace,
                              size_t ws_bytes, sem_solve_report *rep, void *stream);
 
-/* Batched FP64 Jacobi-PCG for nrhs (1..4) right-hand sides that share the
- * operator and h1/h2, e.g. the three velocity components of a time step
- * (the paper's velocity solves, section 3.1).  N = 7 only.  b, x: DEVICE
+/* Batched FP64 CG for nrhs (1..4) right-hand sides that share the operator
+ * and h1/h2, e.g. the three velocity components of a time step (the
+ * paper's velocity solves: CG with a block-Jacobi preconditioner, section
+ * 3.1).  N = 7 only.  opts.form: SEM_FORM_JACOBI_PCG or
+ * SEM_FORM_PCG_BLOCK_JACOBI (the latter on a mesh prepared with
+ * SEM_PREP_HSMG; the element solves run per field).  b, x: DEVICE
  * [nrhs][E][P] local fields (layout as sem_pcg_solve, one block per field);
  * reps: HOST array of nrhs reports.  Each field runs its own CG (own alpha,
  * beta, convergence) but every iteration streams the geometric factors
  * once for all fields.  The batched operator kernel sums in another order
  * than the single-field one, so each field matches a separate sem_pcg_solve
  * to rounding (the same 1e-10 true residual, iteration counts within one),
- * not bit for bit.  opts.form must be SEM_FORM_JACOBI_PCG; history is
- * ignored. */
+ * not bit for bit.  Other forms are refused with SEM_ERR_UNSUPPORTED;
+ * history is ignored. */
 sem_status sem_pcg_solve_batched(const sem_mesh *mesh, const sem_solve_opts *opts, int32_t nrhs, const double *b,
                                  double *x, void *workspace, size_t ws_bytes, sem_solve_report *reps, void *stream);
 sem_status sem_solve_workspace_bytes_batched(const sem_mesh *mesh, const sem_solve_opts *opts, int32_t nrhs,

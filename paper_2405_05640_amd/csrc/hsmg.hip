@@ -1466,41 +1466,79 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
     return SEM_OK;
 }
 
-sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
-                             double *z, CgState *st, const HsmgBufs &hb, int levels, double *hist, int hist_len,
-                             int check_every, hipStream_t s, sem_solve_report *rep, CgState &h)
+namespace {
+
+// The next search direction of preconditioned CG after r changed: z = M r
+// with the (r, z) partials from the preconditioner's last kernel, beta, and
+// p = z (first) or z + beta p.
+sem_status pc_direction(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, double *z, CgState *st,
+                        const HsmgBufs &hb, int levels, int first, hipStream_t s)
 {
     const int weight = levels == 1 ? kWeightNone : kWeightSym;
     const int64_t ng = m.ng;
     const int nbf = cg_blocks(ng);
     const int nbu = (int)((node_grid(m.lat) + mg::kRowsPerBlock - 1) / mg::kRowsPerBlock);
+    SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, v.r, z, hb, levels, weight, s, nullptr, v.part_b));
+    const double *in;
+    int64_t n = nbu;
+    SEM_HIP_TRY(finalize_input(v.part_b, n, 1, v.stage, s, &in));
+    hipLaunchKernelGGL(mg::bj_rz_finalize, dim3(1), dim3(kWide), 0, s, st, in, (int)n, first);
+    if (first)
+        hipLaunchKernelGGL(mg::scale_kernel, dim3(nbf), dim3(kBS), 0, s, z, v.p, ng, 1.0);
+    else
+        hipLaunchKernelGGL(mg::bj_p_kernel, dim3(nbf), dim3(kBS), 0, s, st, v.p, z, ng);
+    SEM_HIP_TRY(hipGetLastError());
+    return SEM_OK;
+}
+
+// The rest of an iteration once w = A_L p is in v.w and the (p, w) partials
+// in v.part_e: alpha, x += alpha p and r -= alpha Q^T w (fused assembly),
+// the convergence test, and the next direction.
+sem_status pc_after_ax(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, double *z, CgState *st,
+                       const HsmgBufs &hb, int levels, double *hist, hipStream_t s)
+{
+    const int nbu = (int)((node_grid(m.lat) + mg::kRowsPerBlock - 1) / mg::kRowsPerBlock);
+    SEM_HIP_TRY(cg_alpha(m, v.part_e, v.stage, st, s));
+    if (m.NP == 8)
+        hipLaunchKernelGGL(mg::bj_update_kernel<8>, dim3(nbu), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv, m.lat,
+                           v.part_b);
+    else
+        hipLaunchKernelGGL(mg::bj_update_kernel<0>, dim3(nbu), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv, m.lat,
+                           v.part_b);
+    const double *in;
+    int64_t n = nbu;
+    SEM_HIP_TRY(finalize_input(v.part_b, n, 1, v.stage, s, &in));
+    hipLaunchKernelGGL(mg::bj_check_finalize, dim3(1), dim3(kWide), 0, s, st, in, (int)n, hist);
+    return pc_direction(m, o, v, z, st, hb, levels, 0, s);
+}
+
+// x = 0, r = b, the first direction
+sem_status pc_start(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b, double *z,
+                    CgState *st, const HsmgBufs &hb, int levels, double *hist, int hist_len, hipStream_t s)
+{
+    const int nbf = cg_blocks(m.ng);
     CgState init{};
     init.max_it = o.max_iter;
     init.hist_len = hist_len;
     SEM_HIP_TRY(hipMemcpyAsync(st, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(mg::bj_init_kernel, dim3(nbf), dim3(kBS), 0, s, b, v.dinv, v.x, v.r, ng, v.part_b);
+    hipLaunchKernelGGL(mg::bj_init_kernel, dim3(nbf), dim3(kBS), 0, s, b, v.dinv, v.x, v.r, m.ng, v.part_b);
     hipLaunchKernelGGL(mg::bj_start_finalize, dim3(1), dim3(kBS), 0, s, st, v.part_b, nbf, o.rel_tol);
     if (hist && hist_len > 0) {
         const double one = 1.0;
         SEM_HIP_TRY(hipMemcpyAsync(hist, &one, sizeof(double), hipMemcpyHostToDevice, s));
         SEM_HIP_TRY(hipStreamSynchronize(s));
     }
-    auto direction = [&](int first) -> sem_status {
-        // (r, z) partials come from the preconditioner's last kernel, one per
-        // workgroup of nbu
-        SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, v.r, z, hb, levels, weight, s, nullptr, v.part_b));
-        const double *in;
-        int64_t n = nbu;
-        SEM_HIP_TRY(finalize_input(v.part_b, n, 1, v.stage, s, &in));
-        hipLaunchKernelGGL(mg::bj_rz_finalize, dim3(1), dim3(kWide), 0, s, st, in, (int)n, first);
-        if (first)
-            hipLaunchKernelGGL(mg::scale_kernel, dim3(nbf), dim3(kBS), 0, s, z, v.p, ng, 1.0);
-        else
-            hipLaunchKernelGGL(mg::bj_p_kernel, dim3(nbf), dim3(kBS), 0, s, st, v.p, z, ng);
-        SEM_HIP_TRY(hipGetLastError());
-        return SEM_OK;
-    };
-    SEM_TRY(direction(1));
+    return pc_direction(m, o, v, z, st, hb, levels, 1, s);
+}
+
+// Iterate one field until its recursive residual converges, then let the
+// FP64 true residual decide (up to three restarts from x with the true
+// residual when the recursive one drifted).  A field whose device state is
+// already done goes straight to that check.
+sem_status pc_run(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b, double *z,
+                  CgState *st, const HsmgBufs &hb, int levels, double *hist, int check_every, hipStream_t s,
+                  sem_solve_report *rep, CgState &h)
+{
     int restarts = 0;
     for (;;) {
         for (;;) {
@@ -1508,18 +1546,7 @@ sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVec
             if (h.done) break;
             for (int q = 0; q < check_every; ++q) {
                 SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.p, v.w, v.part_e, s, &st->done));
-                SEM_HIP_TRY(cg_alpha(m, v.part_e, v.stage, st, s));
-                if (m.NP == 8)
-                    hipLaunchKernelGGL(mg::bj_update_kernel<8>, dim3(nbu), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
-                                       v.dinv, m.lat, v.part_b);
-                else
-                    hipLaunchKernelGGL(mg::bj_update_kernel<0>, dim3(nbu), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p,
-                                       v.dinv, m.lat, v.part_b);
-                const double *in;
-                int64_t n = nbu;
-                SEM_HIP_TRY(finalize_input(v.part_b, n, 1, v.stage, s, &in));
-                hipLaunchKernelGGL(mg::bj_check_finalize, dim3(1), dim3(kWide), 0, s, st, in, (int)n, hist);
-                SEM_TRY(direction(0));
+                SEM_TRY(pc_after_ax(m, o, v, z, st, hb, levels, hist, s));
             }
         }
         if (h.done != 1 || h.bb == 0.0) break;
@@ -1532,7 +1559,7 @@ sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVec
         patch.done = 0;
         patch.rr = h.true_rr;
         SEM_HIP_TRY(hipMemcpyAsync(st, &patch, sizeof(CgState), hipMemcpyHostToDevice, s));
-        SEM_TRY(direction(1));
+        SEM_TRY(pc_direction(m, o, v, z, st, hb, levels, 1, s));
     }
     if (h.done != 1 && h.bb > 0.0) {
         SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.x, v.w, nullptr, s));
@@ -1541,6 +1568,44 @@ sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVec
     }
     rep->iterations = h.it;
     rep->restarts = restarts;
+    return SEM_OK;
+}
+
+}  // namespace
+
+sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
+                             double *z, CgState *st, const HsmgBufs &hb, int levels, double *hist, int hist_len,
+                             int check_every, hipStream_t s, sem_solve_report *rep, CgState &h)
+{
+    SEM_TRY(pc_start(m, o, v, b, z, st, hb, levels, hist, hist_len, s));
+    return pc_run(m, o, v, b, z, st, hb, levels, hist, check_every, s, rep, h);
+}
+
+sem_status solve_pcg_precond_batched(const Mesh &m, const sem_solve_opts &o, int nrhs, const CgVecs<double> *v,
+                                     const double *b, double *z, CgState *st, const HsmgBufs &hb, int levels,
+                                     int check_every, hipStream_t s, sem_solve_report *reps, CgState *h)
+{
+    const int64_t ng = m.ng;
+    for (int c = 0; c < nrhs; ++c)
+        SEM_TRY(pc_start(m, o, v[c], b + c * ng, z + c * ng, st + c, hb, levels, nullptr, 0, s));
+    for (;;) {
+        bool all = true;
+        for (int c = 0; c < nrhs; ++c) {
+            SEM_TRY(read_st(h[c], st + c, s));
+            all = all && h[c].done != 0;
+        }
+        if (all) break;
+        for (int q = 0; q < check_every; ++q) {
+            // one operator launch for every field (the geometric factors are
+            // streamed once); fields already done skip inside it
+            SEM_HIP_TRY(launch_ax_f64_gather_batched(m, nrhs, o.h1, o.h2, v[0].p, ng, v[0].w, v[0].part_e, &st->done,
+                                                     (int)(sizeof(CgState) / sizeof(int32_t)), s));
+            for (int c = 0; c < nrhs; ++c)
+                if (!h[c].done) SEM_TRY(pc_after_ax(m, o, v[c], z + c * ng, st + c, hb, levels, nullptr, s));
+        }
+    }
+    for (int c = 0; c < nrhs; ++c)
+        SEM_TRY(pc_run(m, o, v[c], b + c * ng, z + c * ng, st + c, hb, levels, nullptr, check_every, s, reps + c, h[c]));
     return SEM_OK;
 }
 

@@ -129,5 +129,12 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
 sem_status solve_pcg_precond(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &v, const double *b,
                              double *z, CgState *st, const HsmgBufs &hb, int levels, double *hist, int hist_len,
                              int check_every, hipStream_t s, sem_solve_report *rep, CgState &h);
+// The same for nrhs fields that share the operator and h1/h2 (fields c at
+// v[c], b + c ng, z + c ng, st + c): one batched operator launch per
+// iteration, every other step per field; each field then gets its own true
+// residual check (and restarts) as in the single-field solve.
+sem_status solve_pcg_precond_batched(const Mesh &m, const sem_solve_opts &o, int nrhs, const CgVecs<double> *v,
+                                     const double *b, double *z, CgState *st, const HsmgBufs &hb, int levels,
+                                     int check_every, hipStream_t s, sem_solve_report *reps, CgState *h);
 
 }  // namespace sem

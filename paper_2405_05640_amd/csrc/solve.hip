@@ -654,8 +654,8 @@ sem_status sem_pcg_snapshots(const sem_mesh *mesh, const sem_solve_opts *opts, c
 }
 
 
-static Workspace carve_batched(const Mesh &m, int nrhs, char *base, std::vector<CgVecs<double>> &vc, CgState **states,
-                               double **b64)
+static Workspace carve_batched(const Mesh &m, int nrhs, int form, char *base, std::vector<CgVecs<double>> &vc,
+                               CgState **states, double **b64)
 {
     Workspace ws{};
     size_t off = 0;
@@ -673,6 +673,12 @@ static Workspace carve_batched(const Mesh &m, int nrhs, char *base, std::vector<
     double *PB = (double *)take((size_t)part_capacity(m.lat, m.E) * 3 * 8);
     double *ST = (double *)take((size_t)kStage * 3 * 8);
     *states = (CgState *)take(sizeof(CgState) * nrhs);
+    if (form == SEM_FORM_PCG_BLOCK_JACOBI && m.hsmg) {
+        // block-Jacobi: one z per field and one set of preconditioner buffers
+        ws.z = (double *)take(nrhs * ng * 8);
+        char *hbase = take(hsmg_bufs_bytes(m));
+        if (base) ws.hb = hsmg_bufs_carve(m, hbase);
+    }
     vc.resize(nrhs);
     for (int c = 0; c < nrhs; ++c) {
         vc[c].x = X + c * ng;
@@ -696,7 +702,7 @@ sem_status sem_solve_workspace_bytes_batched(const sem_mesh *mesh, const sem_sol
     std::vector<CgVecs<double>> vc;
     CgState *st;
     double *b64;
-    *bytes = carve_batched(mesh->m, nrhs, nullptr, vc, &st, &b64).bytes;
+    *bytes = carve_batched(mesh->m, nrhs, opts->form, nullptr, vc, &st, &b64).bytes;
     return SEM_OK;
 }
 
@@ -708,12 +714,13 @@ sem_status sem_pcg_solve_batched(const sem_mesh *mesh, const sem_solve_opts *opt
     if (nrhs < 1 || nrhs > 4) return fail(SEM_ERR_INVALID_ARG, "nrhs must be in 1..4");
     const Mesh &m = mesh->m;
     if (m.N != 7) return fail(SEM_ERR_UNSUPPORTED, "batched solves need order N = 7");
-    if (opts->form != SEM_FORM_JACOBI_PCG) return fail(SEM_ERR_UNSUPPORTED, "batched solves use SEM_FORM_JACOBI_PCG");
+    if (opts->form != SEM_FORM_JACOBI_PCG && opts->form != SEM_FORM_PCG_BLOCK_JACOBI)
+        return fail(SEM_ERR_UNSUPPORTED, "batched solves use SEM_FORM_JACOBI_PCG or SEM_FORM_PCG_BLOCK_JACOBI");
     SEM_TRY(check_opts(m, opts));
     std::vector<CgVecs<double>> vc;
     CgState *st;
     double *b64;
-    Workspace ws = carve_batched(m, nrhs, (char *)workspace, vc, &st, &b64);
+    Workspace ws = carve_batched(m, nrhs, opts->form, (char *)workspace, vc, &st, &b64);
     if (ws_bytes < ws.bytes)
         return fail(SEM_ERR_INVALID_ARG, "workspace too small: need " + std::to_string(ws.bytes) + " bytes");
     hipStream_t s = (hipStream_t)stream;
@@ -721,6 +728,34 @@ sem_status sem_pcg_solve_batched(const sem_mesh *mesh, const sem_solve_opts *opt
     const sem_solve_opts &o = *opts;
     SEM_HIP_TRY(launch_diag(m, o.h1, o.h2, vc[0].w, s));
     SEM_HIP_TRY(cg_dinv<double>(m, vc[0].w, vc[0].dinv, s));
+    if (o.form == SEM_FORM_PCG_BLOCK_JACOBI) {
+        // the velocity solves' method: CG with the element block-Jacobi
+        // preconditioner, the operator batched over the fields
+        for (int c = 0; c < nrhs; ++c)
+            SEM_HIP_TRY(cg_gather<double>(m, b + (size_t)c * m.nl, b64 + (size_t)c * m.ng, s));
+        std::vector<CgState> hb(nrhs);
+        std::vector<sem_solve_report> rb(nrhs);
+        for (auto &r : rb) std::memset(&r, 0, sizeof(r));
+        SEM_TRY(solve_pcg_precond_batched(m, o, nrhs, vc.data(), b64, ws.z, st, ws.hb, 1, check_every, s, rb.data(),
+                                          hb.data()));
+        sem_status worst = SEM_OK;
+        for (int c = 0; c < nrhs; ++c) {
+            SEM_HIP_TRY(cg_scatter<double>(m, vc[c].x, x + (size_t)c * m.nl, s));
+            const CgState &hc = hb[c];
+            sem_solve_report &r = reps[c];
+            r = rb[c];
+            r.rel_res = hc.bb > 0 ? std::sqrt(hc.rr / hc.bb) : 0.0;
+            r.true_rel_res = hc.bb > 0 ? std::sqrt(hc.true_rr / hc.bb) : 0.0;
+            r.status = hc.done == 2 ? SEM_ERR_BREAKDOWN
+                                    : ((hc.bb > 0.0 && !(hc.true_rr <= hc.tol2)) ? SEM_ERR_NOT_CONVERGED : SEM_OK);
+            if (r.status != SEM_OK && worst == SEM_OK) worst = (sem_status)r.status;
+        }
+        SEM_HIP_TRY(hipStreamSynchronize(s));
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (int c = 0; c < nrhs; ++c) reps[c].elapsed_ms = ms;
+        if (worst != SEM_OK) return fail(worst, "a batched field did not converge");
+        return SEM_OK;
+    }
     for (int c = 0; c < nrhs; ++c) {
         SEM_HIP_TRY(cg_gather<double>(m, b + (size_t)c * m.nl, b64 + (size_t)c * m.ng, s));
         SEM_TRY(reset_state(st + c, o.max_iter, 0, s));

@@ -463,8 +463,10 @@ def pcg_snapshots(mesh, b, iters, e_out, workspace=None, **kw):
 
 
 def pcg_solve_batched(mesh, b, x, workspace=None, raise_on_error=True, **kw):
-    """Jacobi-PCG for nrhs = b.shape[0] fields sharing the operator (one pass
-    over the geometric factors per iteration).  b, x: (nrhs, E, n, n, n)."""
+    """Jacobi-PCG (form=FORM_JACOBI_PCG, the default) or block-Jacobi CG
+    (form=FORM_PCG_BLOCK_JACOBI, a mesh prepared with SEM_PREP_HSMG) for
+    nrhs = b.shape[0] fields sharing the operator (one pass over the
+    geometric factors per iteration).  b, x: (nrhs, E, n, n, n)."""
     import torch
     nrhs = b.shape[0]
     if b.shape != x.shape or nrhs < 1 or nrhs > 4:

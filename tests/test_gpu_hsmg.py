@@ -197,3 +197,34 @@ def test_coarse_solve_without_plane_kernels(spec):
           (spec.name, rep.iterations, info["iterations"], true_rel))
     assert true_rel <= 1.05e-10
     assert abs(rep.iterations - info["iterations"]) <= max(1, info["iterations"] // 20)
+
+
+@pytest.mark.parametrize("spec,h2", [(wl.deformed_cube(3, 7), 5.0), (wl.channel(3, 7), 0.0)],
+                         ids=["deformed3_N7_helm", "channel3_N7"])
+def test_batched_block_jacobi_matches_single_solves(spec, h2):
+    # the velocity solves' form: three fields through one batched operator,
+    # each with its own block-Jacobi CG, against separate solves and the oracle
+    import torch
+    om, gm = pair(spec, prepare=sem.SEM_PREP_HSMG)
+    pc = hsmg.HSMG(om)
+    rng = np.random.default_rng(27)
+    bs = np.stack([om.rhs(rng.standard_normal(om.shape)) for _ in range(3)])
+    X = torch.zeros(bs.shape, dtype=torch.float64, device="cuda")
+    reps = sem.pcg_solve_batched(gm, dev(bs), X, h1=1.0, h2=h2, rel_tol=1e-10, form=sem.FORM_PCG_BLOCK_JACOBI)
+    Xh = host(X)
+    for c in range(3):
+        xs = torch.zeros(gm.shape, dtype=torch.float64, device="cuda")
+        rs = gm.pcg_solve(dev(bs[c]), xs, h1=1.0, h2=h2, rel_tol=1e-10, form=sem.FORM_PCG_BLOCK_JACOBI)
+        _, info = hsmg.pcg(om, bs[c], lambda q: hsmg.block_jacobi(pc.sw_f, q, 1.0, h2), 1.0, h2, tol=1e-10)
+        r = bs[c] - om.apply_S(Xh[c], 1.0, h2)
+        true_rel = np.sqrt(om.dot(r, r) / om.dot(bs[c], bs[c]))
+        print("%s field %d: batched block-Jacobi CG %d iterations, single %d, oracle %d, true rel res %.2e" %
+              (spec.name, c, reps[c].iterations, rs.iterations, info["iterations"], true_rel))
+        assert reps[c].status == 0 and true_rel <= 1.05e-10
+        assert abs(reps[c].iterations - rs.iterations) <= 1
+        assert abs(reps[c].iterations - info["iterations"]) <= max(1, info["iterations"] // 50)
+        assert np.linalg.norm(Xh[c] - host(xs)) <= 1e-8 * np.linalg.norm(host(xs))
+    # a plain (not multigrid-prepared) mesh cannot take the block-Jacobi form
+    plain = sem.Mesh.from_spec(spec)
+    with pytest.raises(sem.SemError):
+        sem.pcg_solve_batched(plain, dev(bs), X, form=sem.FORM_PCG_BLOCK_JACOBI)
