@@ -188,6 +188,54 @@ def run_forms(mesh, b, forms, reps, ref_name="fp64_jacobi_pcg", tag=""):
     return out
 
 
+def velocity_section(mesh, b0, spec):
+    """The velocity solves' form on the c1 mesh: three Helmholtz fields (h1 = 1,
+    h2 = 5, a velocity-like mass shift; right-hand sides b0 and two more
+    Gaussian Fourier fields) with block-Jacobi CG, solved together by
+    sem_pcg_solve_batched (one batched operator launch per iteration) and,
+    for comparison, as three single solves."""
+    import torch
+
+    from paper_2405_05640_amd import sem
+    from paper_2405_05640_amd import workloads as wl
+    h1, h2 = 1.0, 5.0
+    xyz = torch.from_numpy(mesh.export(sem.FIELD_XYZ)).cuda()
+    B = torch.empty((3,) + tuple(b0.shape), dtype=torch.float64, device="cuda")
+    B[0].copy_(b0)
+    for c in (1, 2):
+        f = wl.fourier_eval(wl.gaussian_fourier(wl.RHS_SEED["c1"] + c), xyz[0], xyz[1], xyz[2]).contiguous()
+        mesh.rhs(f, B[c])
+        del f
+    del xyz
+    X = torch.zeros_like(B)
+    kw = dict(h1=h1, h2=h2, rel_tol=1e-10, form=sem.FORM_PCG_BLOCK_JACOBI, check_every=32)
+    sem.pcg_solve_batched(mesh, B, X, **kw)
+    X.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = sem.pcg_solve_batched(mesh, B, X, **kw)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t) * 1e3
+    its, ts = [], 0.0
+    for c in range(3):
+        x = torch.zeros_like(B[c])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = mesh.pcg_solve(B[c], x, **kw)
+        torch.cuda.synchronize()
+        ts += (time.perf_counter() - t) * 1e3
+        its.append(r.iterations)
+    out = {"fields": 3, "h1": h1, "h2": h2, "batched_ms": round(tb, 2),
+           "batched_iterations": [r.iterations for r in reps],
+           "true_rel_res_max": max(r.true_rel_res for r in reps),
+           "three_single_solves_ms": round(ts, 2), "single_iterations": its,
+           "speedup_vs_single_solves": round(ts / tb, 3)}
+    print("velocity fields, block-Jacobi CG: batched %.1f ms (%s), three single solves %.1f ms" %
+          (tb, out["batched_iterations"], ts), flush=True)
+    del B, X
+    return out
+
+
 def copy_bandwidth():
     """Measured bandwidth of a plain 1 GiB device-to-device copy (read + write)."""
     import torch
@@ -637,6 +685,7 @@ def main():
                       ("reliable_bf16split", dict(form=sem.FORM_RELIABLE_BF16, inner_tol=0.1, check_every=32))]
         forms = [(n, dict(kw, h1=h1, h2=h2, rel_tol=1e-10)) for n, kw in forms]
         out["time_to_1e-10_ms"] = run_forms(mesh, b, forms, args.solve_reps, tag="c1")
+        out["velocity_batched_block_jacobi"] = velocity_section(mesh, b, spec)
     del mesh, b
     torch.cuda.empty_cache()
     if not args.no_small and not args.no_solve:
