@@ -573,15 +573,19 @@ coarse_axis_kernel(const double *__restrict__ in, double *__restrict__ out, cons
 //  - coarse_column_kernel: whole z-columns in LDS, forward z transform,
 //    division by the eigenvalue sum, backward z transform.
 constexpr int kCoarsePlane = 4352;   // LDS plane capacity (doubles): up to 64 x 68 nodes
-constexpr int kCoarsePer = (kCoarsePlane + kBS - 1) / kBS;
-__global__ void __launch_bounds__(kBS)
+// 1024 threads per plane: at 32^3 the lattice has 33 planes of 1,089 nodes, so
+// the grid is small and each thread's outputs (length-n dot products) are
+// the critical path
+constexpr int kPlaneThreads = 1024;
+constexpr int kCoarsePer = (kCoarsePlane + kPlaneThreads - 1) / kPlaneThreads;
+__global__ void __launch_bounds__(kPlaneThreads)
 coarse_plane_kernel(double *__restrict__ u, const double *__restrict__ Sx, const double *__restrict__ Sy, int nx, int ny,
                     int fwd)
 {
     __shared__ double T[kCoarsePlane];
     const int np = nx * ny;
     double *pl = u + (int64_t)blockIdx.x * np;
-    for (int g = threadIdx.x; g < np; g += kBS) T[g] = pl[g];
+    for (int g = threadIdx.x; g < np; g += kPlaneThreads) T[g] = pl[g];
     __syncthreads();
     for (int ph = 0; ph < 2; ++ph) {
         // forward: x then y; backward: y then x
@@ -591,7 +595,7 @@ coarse_plane_kernel(double *__restrict__ u, const double *__restrict__ Sx, const
         double v[kCoarsePer];
 #pragma unroll
         for (int r = 0; r < kCoarsePer; ++r) {
-            const int g = threadIdx.x + r * kBS;
+            const int g = threadIdx.x + r * kPlaneThreads;
             v[r] = 0.0;
             if (g >= np) continue;
             const int i = g % nx, j = g / nx;
@@ -607,12 +611,12 @@ coarse_plane_kernel(double *__restrict__ u, const double *__restrict__ Sx, const
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kCoarsePer; ++r) {
-            const int g = threadIdx.x + r * kBS;
+            const int g = threadIdx.x + r * kPlaneThreads;
             if (g < np) T[g] = v[r];
         }
         __syncthreads();
     }
-    for (int g = threadIdx.x; g < np; g += kBS) pl[g] = T[g];
+    for (int g = threadIdx.x; g < np; g += kPlaneThreads) pl[g] = T[g];
 }
 
 // z-columns (i, j) of the coarse lattice, ncol = kBS / nz per workgroup:
@@ -1150,12 +1154,12 @@ hipError_t coarse_solve(const Mesh &m, double h1, double h2, const HsmgBufs &b, 
     if (nx * ny <= mg::kCoarsePlane && nz <= kBS) {
         const int ncol = kBS / nz;
         const unsigned ncb = (unsigned)(((int64_t)nx * ny + ncol - 1) / ncol);
-        hipLaunchKernelGGL(mg::coarse_plane_kernel, dim3((unsigned)nz), dim3(kBS), 0, s, b.rc, h.d_cS[0], h.d_cS[1],
-                           nx, ny, 1);
+        hipLaunchKernelGGL(mg::coarse_plane_kernel, dim3((unsigned)nz), dim3(mg::kPlaneThreads), 0, s, b.rc, h.d_cS[0],
+                           h.d_cS[1], nx, ny, 1);
         hipLaunchKernelGGL(mg::coarse_column_kernel, dim3(ncb), dim3(kBS), 0, s, b.rc, h.d_cS[2], nx, ny, nz,
                            h.d_clam[0], h.d_clam[1], h.d_clam[2], h1, h2);
-        hipLaunchKernelGGL(mg::coarse_plane_kernel, dim3((unsigned)nz), dim3(kBS), 0, s, b.rc, h.d_cS[0], h.d_cS[1],
-                           nx, ny, 0);
+        hipLaunchKernelGGL(mg::coarse_plane_kernel, dim3((unsigned)nz), dim3(mg::kPlaneThreads), 0, s, b.rc, h.d_cS[0],
+                           h.d_cS[1], nx, ny, 0);
         return hipGetLastError();
     }
     const int nb = cg_blocks(h.ng_c);
