@@ -422,7 +422,7 @@ assemble_fine_kernel(const double *__restrict__ rows, Lattice L, int weighted, c
     const int nrows = (int)(L.ny * L.nz), ny = (int)L.ny, nx = (int)L.nx, row0 = (int)blockIdx.x * kRowsPerBlock;
     double acc[1] = {0.0};
     for (int gi = threadIdx.x; gi < nx; gi += kBS) {
-        double v[kRowsPerBlock], a[kRowsPerBlock];
+        double v[kRowsPerBlock], a[kRowsPerBlock], rv[kRowsPerBlock];
         int64_t g[kRowsPerBlock];
         int gj[kRowsPerBlock], gk[kRowsPerBlock];
 #pragma unroll
@@ -433,6 +433,7 @@ assemble_fine_kernel(const double *__restrict__ rows, Lattice L, int weighted, c
             g[q] = gi + (int64_t)nx * row;
             v[q] = node_assemble_rows<NPC>(L, rows, gi, gj[q], gk[q]);
             a[q] = zp ? zp[g[q]] : 0.0;
+            rv[q] = part ? r[g[q]] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < kRowsPerBlock; ++q) {
@@ -445,7 +446,7 @@ assemble_fine_kernel(const double *__restrict__ rows, Lattice L, int weighted, c
                 z += a[q];
             }
             out[g[q]] = z;
-            if (part) acc[0] += r[g[q]] * z;
+            acc[0] += rv[q] * z;
         }
     }
     if (part) block_partials<1>(acc, 1, part, gridDim.x);
