@@ -658,40 +658,6 @@ coarse_column_kernel(double *__restrict__ u, const double *__restrict__ Sz, int 
 
 constexpr int kMaxDots = kGmresMaxRestart + 2;   // (V_i, w) for i <= j, plus (w, w)
 
-// w = mask(Q^T rows) -> wout; partials of (V_i, w), i <= j, and (w, w).
-// RPB lattice rows per workgroup (the partial-sum reduction of up to 32
-// quantities is paid once per RPB rows); NPC = N + 1 fixed at compile time
-// (0: any order).
-constexpr int kDotRows = 8;
-template <int NPC>
-__global__ void __launch_bounds__(kBS)
-assemble_dots_kernel(const double *__restrict__ rows, Lattice L, double *__restrict__ wout,
-                     const double *__restrict__ V, int64_t ng, int j, double *__restrict__ part)
-{
-    double acc[kMaxDots];
-#pragma unroll
-    for (int q = 0; q < kMaxDots; ++q) acc[q] = 0.0;
-    const int nrows = (int)(L.ny * L.nz), ny = (int)L.ny, nx = (int)L.nx;
-    for (int rr = 0; rr < kDotRows; ++rr) {
-        const int row = (int)blockIdx.x * kDotRows + rr;
-        if (row >= nrows) break;
-        const int gj = row % ny, gk = row / ny;
-        for (int gi = threadIdx.x; gi < nx; gi += kBS) {
-            const int64_t g = gi + (int64_t)nx * row;
-            const double w = node_masked(L, gi, gj, gk) ? 0.0 : node_assemble_rows<NPC>(L, rows, gi, gj, gk);
-            wout[g] = w;
-#pragma unroll
-            for (int q = 0; q < kMaxDots - 1; ++q)
-                if (q <= j) acc[q] += V[q * ng + g] * w;
-            const double ww = w * w;
-#pragma unroll
-            for (int q = 0; q < kMaxDots; ++q)
-                if (q == j + 1) acc[q] += ww;
-        }
-    }
-    block_partials<kMaxDots>(acc, j + 2, part, gridDim.x);
-}
-
 // partials of (V_i, w), i <= j, and (w, w) for an assembled w
 __global__ void __launch_bounds__(kBS)
 dots_kernel(const double *__restrict__ w, const double *__restrict__ V, int64_t ng, int j, double *__restrict__ part)
@@ -1355,7 +1321,6 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
     const int mres = o.restart > 0 ? std::min(o.restart, kGmresMaxRestart) : kGmresMaxRestart;
     const int64_t ng = m.ng;
     const int nbf = cg_blocks(ng);
-    const int nbd = (int)((node_grid(m.lat) + mg::kDotRows - 1) / mg::kDotRows);
     double hv[mg::kMaxDots];
     std::vector<double> y(mres);
     h = CgState{};
@@ -1396,14 +1361,11 @@ sem_status solve_gmres_hsmg(const Mesh &m, const sem_solve_opts &o, const CgVecs
             double *Vj = gb.V + (size_t)j * ng, *Vn = gb.V + (size_t)(j + 1) * ng, *Zj = gb.Z + (size_t)j * ng;
             SEM_HIP_TRY(hsmg_apply(m, o.h1, o.h2, Vj, Zj, gb.hb, 3, kWeightAvg, s, fine));
             SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, Zj, v.w, nullptr, s));
-            if (m.NP == 8)
-                hipLaunchKernelGGL(mg::assemble_dots_kernel<8>, dim3(nbd), dim3(kBS), 0, s, v.w, m.lat, Vn, gb.V, ng,
-                                   j, gb.part);
-            else
-                hipLaunchKernelGGL(mg::assemble_dots_kernel<0>, dim3(nbd), dim3(kBS), 0, s, v.w, m.lat, Vn, gb.V, ng,
-                                   j, gb.part);
+            // Vn = mask(Q^T w), then (V_i, Vn) and (Vn, Vn) in a grid-stride pass
+            launch_assemble_fine(m.lat, v.w, kWeightNone, nullptr, Vn, s, nullptr, nullptr);
+            hipLaunchKernelGGL(mg::dots_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.part);
             SEM_HIP_TRY(hipGetLastError());
-            SEM_HIP_TRY(reduce_to_dev(gb.part, nbd, j + 2, gb.stage, gb.hdev, nullptr, s));
+            SEM_HIP_TRY(reduce_to_dev(gb.part, nbf, j + 2, gb.stage, gb.hdev, nullptr, s));
             hipLaunchKernelGGL(mg::gmres_column_kernel, dim3(1), dim3(64), 0, s, gb.gd, gb.hdev, j);
             // second pass: the first update and its inner products share one read of V
             hipLaunchKernelGGL(mg::orth_dots_kernel, dim3(nbf), dim3(kBS), 0, s, Vn, gb.V, ng, j, gb.hdev, gb.part,
