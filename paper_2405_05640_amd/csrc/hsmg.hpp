@@ -91,14 +91,14 @@ hipError_t hsmg_apply(const Mesh &m, double h1, double h2, const double *r, doub
 
 // The mid and coarse levels' part alone: b.zp = P_01 [Sw_1(R_10 r) +
 // P_12 C^-1 R_21 R_10 r] (what the cycle adds to its fine level).
-// The coarser-level part queued on the mesh's side stream after the work
-// queued so far on s (fork), and s made to wait for it (join): the learned
+hipError_t hsmg_coarse_part(const Mesh &m, double h1, double h2, const double *r, const HsmgBufs &b, int weight,
+                            hipStream_t s);
+// The same part queued on the mesh's side stream after the work queued so
+// far on s (fork), and s made to wait for it (join): the learned
 // multigrid's network and coarser levels are independent terms of z.
 hipError_t hsmg_coarse_part_fork(const Mesh &m, double h1, double h2, const double *r, const HsmgBufs &b, int weight,
                                  hipStream_t s);
 hipError_t hsmg_coarse_part_join(const Mesh &m, hipStream_t s);
-hipError_t hsmg_coarse_part(const Mesh &m, double h1, double h2, const double *r, const HsmgBufs &b, int weight,
-                            hipStream_t s);
 
 // Flexible GMRES work buffers: V [(m+1) ng], Z [m ng], block partials,
 // reduction stage, device vectors of inner products and of y.
