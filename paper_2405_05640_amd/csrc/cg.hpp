@@ -1,7 +1,7 @@
 // cg.hpp -- internal interface of the assembled-vector Krylov kernels.
 #pragma once
-
 #include <algorithm>
+#include <cmath>
 
 #include "sem_internal.hpp"
 
@@ -38,6 +38,28 @@ constexpr int32_t kDoneStalled = 4;
 // the last smoother output was rejected (p restarts from dinv r),
 // fallback_at = iteration of the switch to Jacobi (-1: none), nn_skip =
 // done || !learned
+
+// Iterations to queue before the next host poll of a CG run: check_every,
+// or fewer once the contraction of the recursive residual observed between
+// polls says convergence is nearer.  The kernels of a converged run return
+// at once, but a multigrid or network preconditioner queued after
+// convergence still runs, so over-queueing there costs whole applications.
+struct PollPlan {
+    double rr0 = -1.0;
+    int it0 = 0;
+    int next(const CgState &h, int check_every)
+    {
+        int n = check_every;
+        if (rr0 > 0.0 && h.it > it0 && h.rr > h.tol2 && h.rr < rr0 && h.tol2 > 0.0) {
+            const double per_it = std::log(h.rr / rr0) / (double)(h.it - it0);   // < 0
+            const double need = std::log(h.tol2 / h.rr) / per_it;                // > 0
+            if (need < (double)check_every) n = std::max(1, (int)std::ceil(need));
+        }
+        rr0 = h.rr;
+        it0 = h.it;
+        return n;
+    }
+};
 
 // Vectors of one CG run: x, r, p, dinv are assembled (n_global); w is local
 // (n_local, the unassembled operator output); part_e has n_elem entries,

@@ -1507,11 +1507,13 @@ sem_status pc_run(const Mesh &m, const sem_solve_opts &o, const CgVecs<double> &
                   sem_solve_report *rep, CgState &h)
 {
     int restarts = 0;
+    PollPlan plan;
     for (;;) {
         for (;;) {
             SEM_TRY(read_st(h, st, s));
             if (h.done) break;
-            for (int q = 0; q < check_every; ++q) {
+            const int nq = plan.next(h, check_every);
+            for (int q = 0; q < nq; ++q) {
                 SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.p, v.w, v.part_e, s, &st->done));
                 SEM_TRY(pc_after_ax(m, o, v, z, st, hb, levels, hist, s));
             }

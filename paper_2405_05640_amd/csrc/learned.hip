@@ -465,11 +465,13 @@ sem_status solve_fcg(const Mesh &m, const Smoother &sm, const sem_solve_opts &o,
     hipLaunchKernelGGL(lk::zero_kernel, dim3(nb), dim3(kBS), 0, s, v.p, m.ng);
     SEM_TRY(fcg_direction(m, o, sm, v, z, st, 1, mg, s));
     int restarts = 0;
+    PollPlan plan;
     for (;;) {
         for (;;) {
             SEM_TRY(read_state(h, st, s));
             if (h.done) break;
-            for (int it = 0; it < check_every; ++it) {
+            const int nq = plan.next(h, check_every);
+            for (int it = 0; it < nq; ++it) {
                 SEM_HIP_TRY(launch_ax_f64_gather(m, o.h1, o.h2, v.p, v.w, v.part_e, s, &st->done));
                 SEM_HIP_TRY(cg_alpha(m, v.part_e, v.stage, st, s));
                 hipLaunchKernelGGL(lk::fcg_update_kernel, dim3(nbn), dim3(kBS), 0, s, st, v.w, v.x, v.r, v.p, v.dinv,
