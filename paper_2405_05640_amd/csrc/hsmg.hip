@@ -501,6 +501,60 @@ prolong_owned_kernel(const double *__restrict__ zm, Lattice Lm, const double *__
     zp[gather_index32(L, ex, ey, ez, i, j, k)] = s;
 }
 
+// N = 7 with the order-3 middle level: the same interpolation with one
+// wavefront per element and the same sums in the same order.  The 64 lanes
+// load the 4^3 middle values, each lane forms two of the 128 x-interpolated
+// values, then lane (j, k) finishes the x-pencil zp(0..7, j, k) in registers
+// and writes the nodes it owns (eight consecutive global nodes per lane).
+__global__ void __launch_bounds__(64)
+prolong_pencil_kernel(const double *__restrict__ zm, Lattice Lm, const double *__restrict__ J, Lattice L,
+                      double *__restrict__ zp)
+{
+    constexpr int NP = 8, NPM = 4;
+    __shared__ double s0[NPM * NPM * NPM], s1[NP * NPM * NPM], sJ[NP * NPM];
+    const int t = threadIdx.x & 63;
+    const int64_t e = xcd_block();
+    int ex, ey, ez;
+    elem_coords(L, e, ex, ey, ez);
+    s0[t] = zm[gather_index32(Lm, ex, ey, ez, t % NPM, (t / NPM) % NPM, t / (NPM * NPM))];
+    if (t < NP * NPM) sJ[t] = J[t];
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = t + 64 * h, ii = q % NP, b = (q / NP) % NPM, c = q / (NP * NPM);
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < NPM; ++a) s += sJ[ii * NPM + a] * s0[(c * NPM + b) * NPM + a];
+        s1[q] = s;
+    }
+    __syncthreads();
+    const int j = t % NP, k = t / NP;
+    const int N = L.N;
+    const bool own_jk = (j < N || (ey == L.nely - 1 && !L.per[1])) && (k < N || (ez == L.nelz - 1 && !L.per[2]));
+    if (!own_jk) return;
+    const bool last_x = ex == L.nelx - 1 && !L.per[0];
+    double Jj[NPM], Jk[NPM];
+#pragma unroll
+    for (int b = 0; b < NPM; ++b) {
+        Jj[b] = sJ[j * NPM + b];
+        Jk[b] = sJ[k * NPM + b];
+    }
+    const int64_t g0 = gather_index32(L, ex, ey, ez, 0, j, k);   // the pencil's 8 nodes are consecutive
+#pragma unroll 2
+    for (int i = 0; i < NP; ++i) {
+        if (i == N && !last_x) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < NPM; ++c) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int b = 0; b < NPM; ++b) s2 += Jj[b] * s1[(c * NPM + b) * NP + i];
+            s += Jk[c] * s2;
+        }
+        zp[g0 + i] = s;
+    }
+}
+
 // out[g] = mask(sum of the copies of rows at g, times 1 / count
 // (kWeightAvg) or 1 / sqrt(count) (kWeightSym)) + (zc != null: the order-1
 // interpolant of zc at g); NPC = N + 1 of the level fixed at compile time
@@ -1104,7 +1158,10 @@ hipError_t prolong_fine(const Mesh &m, const HsmgBufs &b, hipStream_t s)
         SEM_PF(5, 4)
         SEM_PF(6, 4)
         SEM_PF(7, 4)
-        SEM_PF(8, 4)
+    case 8:
+        hipLaunchKernelGGL(mg::prolong_pencil_kernel, dim3((unsigned)m.E), dim3(64), 0, s, b.zm, h.lat_m, h.d_Jfm, m.lat,
+                           b.zp);
+        break;
         SEM_PF(9, 4)
         SEM_PF(10, 4)
     default:
